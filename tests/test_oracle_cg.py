@@ -1,0 +1,95 @@
+"""Pins of the oracle's CG family against dense linear algebra.
+
+* CG's k-th iterate minimises f over x0 + span{g0, H g0, ..., H^{k-1} g0},
+  H = A^T A (the Krylov property of CG); the reference minimiser comes from a
+  dense QR basis of that Krylov space and a dense least-squares solve.
+* Run to convergence, CG reaches the dense least-squares solution.
+* S-CG with gamma0 = 0 (no perturbation) produces CG's iterates: the
+  perturbation-resilient step reproduces CG in exact arithmetic.
+"""
+import numpy as np
+import pytest
+
+from oracle import algorithms as alg
+
+
+def _small_problem(oracle_lib, n=6, na=16, nb=9, seed=0):
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(seed)
+    A = g.dense()
+    y = A @ rng.uniform(0, 1, g.J) + 0.05 * rng.standard_normal(g.L)
+    return g, A, y
+
+
+def test_cg_krylov_minimisers(oracle_lib):
+    g, A, y = _small_problem(oracle_lib)
+    prob = alg.Problem(g, y)
+    x0 = np.zeros(g.J)
+    H = A.T @ A
+    g0 = A.T @ (A @ x0 - y)
+    # iterates of CG with eps = 0 (runs max_iter steps)
+    iters = []
+    x = x0.copy()
+    for k in range(1, 7):
+        res = alg.cg(prob, x0, eps=0.0, max_iter=k)
+        iters.append(res.x)
+    for k, xk in enumerate(iters, start=1):
+        K = np.empty((g.J, k))
+        v = g0.copy()
+        for col in range(k):
+            K[:, col] = v
+            v = H @ v
+        Q, _ = np.linalg.qr(K)
+        c, *_ = np.linalg.lstsq(A @ Q, y - A @ x0, rcond=None)
+        xref = x0 + Q @ c
+        assert np.linalg.norm(xk - xref) <= 1e-8 * np.linalg.norm(xref), k
+
+
+def test_cg_reaches_least_squares(oracle_lib):
+    g, A, y = _small_problem(oracle_lib, seed=2)
+    prob = alg.Problem(g, y)
+    eps0, xls = alg.ls_floor_dense(g, y)
+    res = alg.cg(prob, np.zeros(g.J), eps=eps0 * (1 + 1e-13), max_iter=500)
+    assert np.linalg.norm(res.x - xls) <= 1e-6 * np.linalg.norm(xls)
+    assert res.f_out <= eps0 * (1 + 1e-13)
+
+
+def test_pcg_reaches_least_squares_consistent(oracle_lib):
+    """With consistent data (y in the range of A) the filtered-residual
+    preconditioner still leads PCG to the least-squares solution, f -> 0."""
+    g = oracle_lib.Geometry(6, 16, 9)
+    rng = np.random.default_rng(3)
+    A = g.dense()
+    xt = rng.uniform(0, 1, g.J)
+    y = A @ xt
+    prob = alg.Problem(g, y)
+    res = alg.pcg(prob, np.zeros(g.J), eps=1e-20 * float(y @ y), max_iter=500)
+    assert res.status == "ok"
+    assert np.linalg.norm(res.x - xt) <= 1e-6 * np.linalg.norm(xt)
+
+
+def test_scg_without_perturbation_is_cg(oracle_lib):
+    g, A, y = _small_problem(oracle_lib, n=8, na=20, nb=13, seed=4)
+    prob = alg.Problem(g, y)
+    x0 = np.zeros(g.J)
+    pp = alg.PerturbParams(gamma0=0.0)
+    for k in range(1, 9):
+        ref = alg.cg(prob, x0, eps=0.0, max_iter=k).x
+        res = alg.scg(prob, x0, eps=0.0, pp=pp, max_iter=k - 1, record=True)
+        # after k-1 PR steps the last x_{k} is records[-1]['x_next'] (x1 when k = 1)
+        xk = res.records[-1]["x_next"] if res.records else None
+        if xk is None:
+            continue
+        assert np.linalg.norm(xk - ref) <= 1e-9 * np.linalg.norm(ref), k
+
+
+def test_pcg_k_and_cg_k_steps(oracle_lib):
+    """CG-K from x0 with K steps equals K iterations of CG."""
+    g, A, y = _small_problem(oracle_lib, seed=5)
+    prob = alg.Problem(g, y)
+    x0 = np.zeros(g.J)
+    for K in (1, 2, 3):
+        xk, f0 = alg.cg_k(prob, x0, K)
+        ref = alg.cg(prob, x0, eps=0.0, max_iter=K).x
+        assert np.allclose(xk, ref, rtol=0, atol=1e-12 * np.linalg.norm(ref))
+        assert f0 == pytest.approx(prob.f(x0))

@@ -1,0 +1,141 @@
+"""The Appendix's statements about S-CG, checked on the oracle.
+
+  Prop. 2  <g_{n+1}, p_n> = 0 with g_{n+1} the gradient at the unperturbed x_{n+1}
+  Prop. 3  h_{k-1} = A^T A p_{k-1} before each PR step
+  Prop. 4  <A p_k, A p_{k-1}> = 0 even with perturbations
+  Prop. 5  2f(x_{k+1/2}) - 2f(x_{k+1}) = <g_{k+1/2}, p_k>^2 / ||A p_k||^2, and
+           >= ||g_k||^2/(16 c^2) when ||u_k|| = eta0 ||g_k||, eta0 <= 1/(4c^2)
+  Lemma 6  2f(x_k) - 2f(x_{k+1}) >= ||g_k||^2/(32 c^2) when eta0 <= eta_l
+  Thm 1    for eps > eps0 S-CG terminates with f(output) <= eps
+and the abstract's claim that the output's TV is at most that of
+unsuperiorized CG at the same eps (stated, not proved, in the paper).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import algorithms as alg
+from synth import make_workload
+
+
+def _problem(oracle_lib, n=16, na=24, nb=25, seed=0, noise=0.02):
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(seed)
+    xt = np.zeros((n, n))
+    xt[3:11, 4:12] = 1.0
+    xt[6:9, 2:14] += 0.5
+    y = g.project(xt)
+    y = y + noise * np.max(y) * rng.standard_normal(y.size)
+    return g, y
+
+
+def _gamma0(prob):
+    x1 = alg.scg(prob, np.zeros(prob.g.J), eps=0.0, pp=alg.PerturbParams(0.0), max_iter=0)
+    return x1
+
+
+def test_orthogonality_and_conjugacy(oracle_lib):
+    g, y = _problem(oracle_lib)
+    prob = alg.Problem(g, y)
+    pp = alg.PerturbParams(gamma0=2.0)
+    res = alg.scg(prob, np.zeros(g.J), eps=0.0, pp=pp, max_iter=12, record=True)
+    perturbed = 0
+    for rec in res.records:
+        # Prop. 2 at the unperturbed x_{k+1}
+        g_next = prob.AT(prob.residual(rec["x_next"]))
+        p = rec["p"]
+        assert abs(g_next @ p) <= 1e-9 * np.linalg.norm(g_next) * np.linalg.norm(p) + 1e-300
+        # Prop. 4
+        q, qp = rec["q"], rec["q_prev"]
+        assert abs(q @ qp) <= 1e-9 * np.linalg.norm(q) * np.linalg.norm(qp)
+        # Prop. 5 identity
+        lhs = 2 * prob.f(rec["x_half"]) - 2 * prob.f(rec["x_next"])
+        rhs = (rec["g_half"] @ p) ** 2 / (q @ q)
+        assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), 1e-30)
+        if np.linalg.norm(rec["x_half"] - rec["x_k"]) > 0:
+            perturbed += 1
+    assert perturbed >= 3          # the checks ran with real perturbations
+
+
+def test_h_is_normal_product(oracle_lib):
+    """Prop. 3: the h carried into each PR step is A^T A p of the previous
+    direction, which the record holds as A^T(q_prev)."""
+    g, y = _problem(oracle_lib, seed=1)
+    prob = alg.Problem(g, y)
+    res = alg.scg(prob, np.zeros(g.J), eps=0.0, pp=alg.PerturbParams(1.0), max_iter=5,
+                  record=True)
+    for rec in res.records:
+        h = prob.AT(prob.A(rec["p_prev"]))
+        beta = res.trace[rec["k"] - 1]["beta"]
+        # beta = g'^T h / p^T h: recompute from the definition with this h
+        ref = (rec["g_half"] @ h) / (rec["p_prev"] @ h)
+        assert abs(beta - ref) <= 1e-10 * max(1.0, abs(ref))
+
+
+def test_decrease_bounds_with_forced_perturbations(oracle_lib):
+    """Prop. 5 and Lemma 6 with ||u_k|| = eta0 ||g_k|| and eta0 = eta_l."""
+    g, y = _problem(oracle_lib, seed=2)
+    prob = alg.Problem(g, y)
+    c2 = alg.power_norm2(prob, iters=300)
+    eta1 = 1.0 / (4 * c2)
+    # eta2: positive root of (2 + c^2 eta) eta = 1/(32 c^2)
+    eta2 = (-2 + math.sqrt(4 + 4 * c2 / (32 * c2))) / (2 * c2)
+    eta_l = min(eta1, eta2)
+    rng = np.random.default_rng(9)
+    log = []
+
+    def force(x, k, ctx):
+        gk = prob.AT(prob.residual(x))
+        u = rng.standard_normal(x.size)
+        u *= eta_l * np.linalg.norm(gk) / np.linalg.norm(u)
+        log.append((k, x.copy(), gk))
+        return x + u
+
+    res = alg.scg(prob, np.zeros(g.J), eps=0.0, pp=alg.PerturbParams(0.0), max_iter=15,
+                  perturb_fn=force, record=True)
+    for (k, xk, gk), rec in zip(log, res.records):
+        gn2 = gk @ gk
+        d_half = 2 * prob.f(rec["x_half"]) - 2 * prob.f(rec["x_next"])
+        d_full = 2 * prob.f(xk) - 2 * prob.f(rec["x_next"])
+        assert d_half >= gn2 / (16 * c2) * (1 - 1e-9)
+        assert d_full >= gn2 / (32 * c2) * (1 - 1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_termination_theorem(oracle_lib, seed):
+    """Thm 1 on the 64 x 64 workload shape with eps = 1.1 eps0, eps0 from a
+    dense least-squares solve."""
+    w = make_workload(1, seed, supersample=2)
+    g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
+    prob = alg.Problem(g, w.y)
+    eps0, _ = alg.ls_floor_dense(g, w.y)
+    eps = 1.1 * eps0
+    x1 = alg.cg(prob, np.zeros(g.J), eps=0.0, max_iter=1).x
+    pp = alg.PerturbParams(gamma0=0.05 * np.linalg.norm(x1))
+    res = alg.scg(prob, np.zeros(g.J), eps=eps, pp=pp, max_iter=2000)
+    assert res.status == "ok"
+    assert prob.f(res.x) <= eps
+    assert res.f_out == pytest.approx(prob.f(res.x), rel=1e-12)
+
+
+@pytest.mark.slow
+def test_tv_not_above_unsuperiorized_cg(oracle_lib):
+    """The abstract's claim: at the same eps, S-CG's output has TV at or
+    below CG's. Checked over seeds of the 64 x 64 workload shape."""
+    wins = 0
+    seeds = range(6)
+    for seed in seeds:
+        w = make_workload(1, 100 + seed, supersample=2)
+        g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
+        prob = alg.Problem(g, w.y)
+        eps0, _ = alg.ls_floor_dense(g, w.y)
+        eps = 1.1 * eps0
+        cg = alg.cg(prob, np.zeros(g.J), eps=eps, max_iter=5000)
+        x1 = alg.cg(prob, np.zeros(g.J), eps=0.0, max_iter=1).x
+        pp = alg.PerturbParams(gamma0=0.05 * np.linalg.norm(x1))
+        s = alg.scg(prob, np.zeros(g.J), eps=eps, pp=pp, max_iter=5000)
+        assert s.status == "ok" and cg.status == "ok"
+        if g.tv(s.x) <= g.tv(cg.x):
+            wins += 1
+    assert wins == len(seeds)
