@@ -1,0 +1,185 @@
+/*
+ * libscg: total-variation superiorized conjugate gradient for parallel-beam
+ * CT on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the least-squares problem of the paper's Introduction,
+ *     minimise f(x) = 1/2 ||y - A x||^2,
+ * with the superiorized CG family of its third section: the iteration stops
+ * as soon as f(x_{k-1/2}) <= eps, and every step is preceded by a TV-reducing
+ * perturbation x_{k+1/2} = x_k + gamma_k v_k (eq. superiorization, with
+ * gamma taken from gamma_l = gamma0 a^l, eq. gamma_sequence).
+ *
+ * Geometry (the paper fixes parallel rays, angles uniform over [0, 180 deg)
+ * and the image/detector sizes; the remaining conventions are this
+ * library's): the image has N x N unit pixels, pixel (i, j) (row i from the
+ * top, column j from the left) has centre x_j = j - (N-1)/2,
+ * y_i = (N-1)/2 - i and flat index i*N + j. Angle a has theta_a = a*pi/n_a,
+ * bin b has centre t_b = b - (n_b-1)/2, ray (a, b) is the line
+ * x cos theta_a + y sin theta_a = t_b, and sinograms are angle-major with flat
+ * index a*n_b + b. A's entry for (ray, pixel) is the length of the ray inside
+ * the pixel's closed unit square; a ray lying on a pixel edge gives each side
+ * half of it.
+ *
+ * Conventions for every entry point:
+ *   - Return value: SCG_OK (0) or a negative status; nothing throws across
+ *     the ABI. scg_strerror() names a status.
+ *   - Vectors are raw device pointers owned by the caller. The library never
+ *     frees caller memory and never keeps a caller pointer after returning.
+ *   - Element type follows the precision argument: SCG_F32 -> float,
+ *     SCG_F64 -> double. In SCG_F32 the operators, TV and vector updates run
+ *     in FP32 while the CG scalars (alpha, beta), the residual norm and the
+ *     eps test are accumulated and evaluated in FP64.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
+ *     on it; calls that return host scalars synchronise it.
+ *   - A plan owns small device scratch buffers: calls that share a plan must
+ *     not overlap in time (use one plan per concurrent stream).
+ */
+#ifndef SCG_H
+#define SCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SCG_OK            0
+#define SCG_EINVAL       -1   /* invalid argument (size, pointer, parameter)     */
+#define SCG_ENOMEM       -2   /* device allocation failed / workspace too small  */
+#define SCG_EDEVICE      -3   /* HIP runtime error                               */
+#define SCG_ENOCONV      -4   /* max_iter steps done and f > eps still holds     */
+#define SCG_ENAN         -5   /* a non-finite CG scalar appeared                 */
+#define SCG_EBREAKDOWN   -6   /* ||A p||^2 = 0 for a new direction p             */
+#define SCG_EAGAIN       -7   /* no free slot / memory in a batch                */
+#define SCG_EINPROGRESS  -8   /* batch ticket still running                      */
+#define SCG_ENOTFOUND    -9   /* unknown batch ticket                            */
+
+/* ---- enums ------------------------------------------------------------- */
+typedef enum { SCG_F32 = 0, SCG_F64 = 1 } scg_prec;
+
+typedef enum {
+    SCG_CG = 0,      /* Alg. CG (unsuperiorized, recursive gradient)           */
+    SCG_S_CG = 1,    /* Alg. S-CG with CG-PR-STEP                              */
+    SCG_S_CG_CD = 2, /* Alg. S-CG-CD with CG-CD-STEP (conjugate-descent beta)  */
+    SCG_S_PCG = 3    /* Alg. S-PCG with PCG-PR-STEP (filtered preconditioner)  */
+} scg_variant;
+
+/* flags of scg_params.flags */
+#define SCG_FLAG_NO_PERTURB 1u   /* skip perturbed(): x_{k+1/2} = x_k           */
+
+/* ---- plain structs ----------------------------------------------------- */
+typedef struct {
+    int32_t n;          /* image side N (N x N pixels), >= 2                    */
+    int32_t n_angles;   /* angles uniform over [0, 180 deg), >= 1              */
+    int32_t n_bins;     /* unit-width detector bins, >= 1                       */
+} scg_geom;
+
+typedef struct {
+    int32_t variant;     /* scg_variant                                           */
+    int32_t prec;        /* scg_prec                                              */
+    double  eps;         /* stop when f(x_{k-1/2}) <= eps; must be > 0            */
+    double  gamma0;      /* gamma_l = gamma0 * a^l; >= 0 (0: no perturbation)     */
+    double  a;           /* 0 < a < 1 (the paper's experiments use 0.975)         */
+    int32_t max_iter;    /* cap on the number of steps after the initial one     */
+    int32_t max_trials;  /* cap on trials of perturbed() per step, 1..1024        */
+    double  tv_kappa;    /* 0: exact isotropic TV; > 0: sqrt(a^2+b^2+kappa^2)     */
+    double  precond_mu;  /* mu of the filter c(w) (S-PCG); <= 0 selects 2 pi / P  */
+    uint32_t flags;      /* SCG_FLAG_*                                            */
+} scg_params;
+
+typedef struct {
+    int32_t status;       /* SCG_OK, SCG_ENOCONV, SCG_ENAN or SCG_EBREAKDOWN      */
+    int32_t k;            /* the paper's counter k when the loop ended; the       */
+                          /* output is x_{k-1/2}                                  */
+    int32_t steps;        /* steps executed after the initial one                 */
+    int32_t trials_total; /* TV trials made by perturbed()                        */
+    int32_t ell;          /* final value of the gamma counter l                   */
+    int32_t reserved;
+    double  f_out;        /* f at the output (FP64 accumulation)                  */
+    double  tv_out;       /* TV of x_k at the last perturbation, or 0             */
+} scg_report;
+
+/* One entry per step k = 1, 2, ... (the step that forms x_{k+1/2}, x_{k+1}). */
+typedef struct {
+    int32_t k;
+    int32_t accepted;     /* index of the accepted trial in this step, -1: none   */
+    int32_t trials;       /* trials made in this step                             */
+    int32_t ell;          /* l after the step's perturbation                      */
+    double  f_half;       /* f(x_{k+1/2})                                         */
+    double  tv_x;         /* TV(x_k)                                              */
+    double  gamma;        /* step used (0: unperturbed)                           */
+    double  beta;
+    double  alpha;
+} scg_trace_entry;
+
+typedef struct scg_plan scg_plan;
+
+/* ---- plans ------------------------------------------------------------- */
+
+/* Creates a plan for geometry *g on HIP device `device`: FP64 angle tables
+ * (cos/sin evaluated in double and snapped to 0/+-1 within 1e-12) are built on
+ * the host and uploaded, and the plan's scratch is allocated. *out is set to
+ * NULL on failure. Errors: SCG_EINVAL (sizes), SCG_ENOMEM, SCG_EDEVICE. */
+int scg_plan_create(const scg_geom *g, int device, scg_plan **out);
+
+/* Frees a plan and its device memory (NULL is accepted). The caller must
+ * have synchronised every stream that used the plan. */
+void scg_plan_destroy(scg_plan *plan);
+
+/* Device bytes the caller must provide to scg_solve for these parameters. */
+int scg_workspace_bytes(const scg_plan *plan, const scg_params *params, size_t *bytes);
+
+/* ---- operators --------------------------------------------------------- */
+
+/* y = A x (the discrete line integrals of the Introduction). x: N*N
+ * elements, y: n_angles*n_bins elements, both device pointers of the type
+ * given by `prec`. The plan's scratch holds a padded copy of x. */
+int scg_project(scg_plan *plan, int prec, const void *x, void *y, void *stream);
+
+/* x = A^T y, the exact transpose of scg_project (a pixel-driven gather). */
+int scg_backproject(scg_plan *plan, int prec, const void *y, void *x, void *stream);
+
+/* TV(x) (isotropic forward differences over the (N-1)^2 interior terms,
+ * sqrt(a^2 + b^2 + kappa^2) per term) into *tv_host, and optionally a
+ * subgradient of TV at x into s (device, N*N elements; NULL to skip). Terms
+ * are computed in the precision `prec` and summed in FP64. Synchronises. */
+int scg_tv(scg_plan *plan, int prec, const void *x, double kappa, void *s, double *tv_host,
+           void *stream);
+
+/* The preconditioning filter F^T C F of the paper's Filters for
+ * Preconditioning section applied to every projection of r: zero padding to
+ * P = 2^ceil(log2(2 n_bins)) samples, DFT, multiplication by
+ * c(w) = (|w| + mu)(0.54 + 0.46 cos w) at w_m = 2 pi m / P, inverse DFT,
+ * first n_bins samples kept. mu <= 0 selects 2 pi / P. */
+int scg_filter(scg_plan *plan, int prec, double mu, const void *r, void *out, void *stream);
+
+/* ---- solver ------------------------------------------------------------ */
+
+/* Runs params->variant from x0 on data y (device, n_angles*n_bins) and
+ * writes the output x_{k-1/2} to x_out (device, N*N). x0 may be NULL
+ * (the zero image). ws/ws_bytes: device workspace of at least
+ * scg_workspace_bytes(); the library allocates nothing during the solve.
+ * rep (host) receives the report. trace (host, may be NULL) receives up to
+ * trace_cap entries, one per step. forced (host, may be NULL) replays
+ * perturbation decisions: for step k, forced[2(k-1)] is the number of trials
+ * and forced[2(k-1)+1] the accepted trial index (-1: none) to use instead of
+ * the TV tests, for the first forced_len steps. Returns rep->status on a
+ * completed solve, or an argument/device error. Synchronises `stream`. */
+int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const void *x0,
+              void *x_out, void *ws, size_t ws_bytes, scg_report *rep,
+              scg_trace_entry *trace, int32_t trace_cap, const int32_t *forced,
+              int32_t forced_len, void *stream);
+
+/* Fills *params with the library's defaults: S-CG, FP32, a = 0.975,
+ * max_iter = 1000, max_trials = 100, kappa = 0, mu = 2 pi / P; eps and
+ * gamma0 are set to 0 and must be provided. */
+void scg_default_params(scg_params *params);
+
+const char *scg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCG_H */

@@ -1,0 +1,645 @@
+// C-ABI of libscg: plans, operators and the superiorized CG solver driver.
+//
+// The solver keeps all state on the device. Each loop iteration is a fixed
+// sequence of kernels that read the device-resident scalars (alpha, beta,
+// f, the TV-trial decision) and return at once when the device `done` flag is
+// set; the host enqueues iterations in chunks and reads the flag between
+// chunks, so the iteration count is decided on the device.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "scg_internal.h"
+
+using scg::BpAngle;
+using scg::DevState;
+using scg::Geo;
+using scg::ProjAngle;
+
+struct scg_plan {
+    int device = 0;
+    Geo G{};
+    std::vector<double> cosv, sinv;
+    ProjAngle *pang = nullptr;
+    BpAngle *bang = nullptr;
+    void *xs[2] = {nullptr, nullptr};     // staged image scratch per precision
+    void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    double *tvbuf = nullptr;
+    void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
+    double kern_mu = -1.0;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kKCap = 1048576.0;   // 2^20: K for axis-aligned rays
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SCG_OK : SCG_EDEVICE; }
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return SCG_EDEVICE;     \
+    } while (0)
+
+double snap(double v)
+{
+    if (std::fabs(v) < 1e-12) return 0.0;
+    if (std::fabs(1.0 - std::fabs(v)) < 1e-12) return v > 0 ? 1.0 : -1.0;
+    return v;
+}
+
+// Per-angle frames for the ray-driven projector and the pixel-driven
+// backprojector, from the FP64 trig table.
+void build_angles(const Geo &G, const std::vector<double> &cv, const std::vector<double> &sv,
+                  std::vector<ProjAngle> &pa, std::vector<BpAngle> &ba)
+{
+    const double h = G.h, hb = G.hb;
+    pa.resize(G.na);
+    ba.resize(G.na);
+    for (int a = 0; a < G.na; ++a) {
+        const double c = cv[a], s = sv[a];
+        const double ac = std::fabs(c), as = std::fabs(s);
+        const double m = std::max(ac, as), n = std::min(ac, as);
+        ProjAngle P{};
+        if (ac >= as) {     // step over rows: x = (t - y s) / c
+            P.major = 0;
+            P.u0_base = (-hb - h * s) / c + h;
+            P.u0_step = 1.0 / c;
+            P.slope = s / c;
+        } else {            // step over columns: y = (t - x c) / s
+            P.major = 1;
+            P.u0_base = h - (h * c - hb) / s;
+            P.u0_step = -1.0 / s;
+            P.slope = c / s;
+        }
+        P.K = n > 0.0 ? std::min(m / n, kKCap) : kKCap;
+        P.C = 0.5 * P.K + 0.5;
+        P.inv_m = 1.0 / m;
+        P.Kf = (float)P.K;
+        P.Cf = (float)P.C;
+        P.inv_mf = (float)P.inv_m;
+        pa[a] = P;
+
+        BpAngle B{};
+        B.c = c;
+        B.s = s;
+        B.K = n > 0.0 ? std::min(1.0 / n, kKCap) : kKCap;
+        B.C = 0.5 * m * B.K + 0.5;
+        B.inv_m = 1.0 / m;
+        B.Kf = (float)B.K;
+        B.Cf = (float)B.C;
+        B.CKf = (float)(B.C - B.K);
+        B.inv_mf = (float)B.inv_m;
+        ba[a] = B;
+    }
+}
+
+int filter_pad(int nb)
+{
+    int P = 1;
+    while (P < 2 * nb) P <<= 1;
+    return P;
+}
+
+// k[d] = (1/P) sum_{m=-P/2}^{P/2-1} c(w_m) cos(w_m d), c(w) = (|w| + mu)(0.54 + 0.46 cos w).
+int ensure_filter(scg_plan *p, double mu)
+{
+    const int nb = p->G.nb, P = filter_pad(nb);
+    if (mu <= 0.0) mu = 2.0 * kPi / P;
+    if (p->kern[0] != nullptr && p->kern_mu == mu) return SCG_OK;
+    std::vector<double> k(nb);
+    std::vector<double> cw(P);
+    for (int m = -P / 2; m < P / 2; ++m) {
+        const double w = 2.0 * kPi * m / P;
+        cw[m + P / 2] = (std::fabs(w) + mu) * (0.54 + 0.46 * std::cos(w));
+    }
+    for (int d = 0; d < nb; ++d) {
+        double acc = 0.0;
+        for (int m = -P / 2; m < P / 2; ++m) acc += cw[m + P / 2] * std::cos(2.0 * kPi * m * d / P);
+        k[d] = acc / P;
+    }
+    std::vector<float> kf(k.begin(), k.end());
+    if (p->kern[0] == nullptr) {
+        HIP_TRY(hipMalloc(&p->kern[0], nb * sizeof(float)));
+        HIP_TRY(hipMalloc(&p->kern[1], nb * sizeof(double)));
+    }
+    HIP_TRY(hipMemcpy(p->kern[0], kf.data(), nb * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->kern[1], k.data(), nb * sizeof(double), hipMemcpyHostToDevice));
+    p->kern_mu = mu;
+    return SCG_OK;
+}
+
+struct Device {
+    int prev = -1;
+    explicit Device(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~Device()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace layout of scg_solve.
+struct Layout {
+    size_t x, xh, p, g, h, s, z, r, q, rt, xs, partials, counter, state, forced, trace, tv,
+        total;
+};
+
+Layout layout(const Geo &G, size_t esz, int max_iter)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t J = G.img_elems(), S = G.sino_elems();
+    L.x = take(J * esz);
+    L.xh = take(J * esz);
+    L.p = take(J * esz);
+    L.g = take(J * esz);
+    L.h = take(J * esz);
+    L.s = take(J * esz);
+    L.z = take(J * esz);
+    L.r = take(S * esz);
+    L.q = take(S * esz);
+    L.rt = take(S * esz);
+    L.xs = take(G.staged_elems() * esz);
+    L.partials = take(scg::kMaxPartials * sizeof(double));
+    L.counter = take(64);
+    L.state = take(sizeof(DevState));
+    L.forced = take((size_t)2 * (max_iter + 1) * sizeof(int32_t));
+    L.trace = take((size_t)(max_iter + 1) * sizeof(scg_trace_entry));
+    L.tv = take(sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int check_params(const scg_params *pr)
+{
+    if (pr == nullptr) return SCG_EINVAL;
+    if (pr->variant < SCG_CG || pr->variant > SCG_S_PCG) return SCG_EINVAL;
+    if (pr->prec != SCG_F32 && pr->prec != SCG_F64) return SCG_EINVAL;
+    if (!(pr->eps > 0.0) || !std::isfinite(pr->eps)) return SCG_EINVAL;
+    if (!(pr->gamma0 >= 0.0) || !std::isfinite(pr->gamma0)) return SCG_EINVAL;
+    if (!(pr->a > 0.0 && pr->a < 1.0)) return SCG_EINVAL;
+    if (pr->max_iter < 0 || pr->max_iter > 1000000) return SCG_EINVAL;
+    if (pr->max_trials < 1 || pr->max_trials > 1024) return SCG_EINVAL;
+    if (!(pr->tv_kappa >= 0.0) || !std::isfinite(pr->tv_kappa)) return SCG_EINVAL;
+    return SCG_OK;
+}
+
+template <typename T> int prec_index();
+template <> int prec_index<float>() { return 0; }
+template <> int prec_index<double>() { return 1; }
+
+template <typename T>
+int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void *x0_, void *xout_,
+               char *ws, scg_report *rep, scg_trace_entry *trace_host, int32_t trace_cap,
+               const int32_t *forced_host, int32_t forced_len, hipStream_t st0)
+{
+    const Geo &G = plan->G;
+    const size_t J = G.img_elems(), S = G.sino_elems();
+    const Layout Lw = layout(G, sizeof(T), pr->max_iter);
+    T *x = reinterpret_cast<T *>(ws + Lw.x);
+    T *xh = reinterpret_cast<T *>(ws + Lw.xh);
+    T *p = reinterpret_cast<T *>(ws + Lw.p);
+    T *g = reinterpret_cast<T *>(ws + Lw.g);
+    T *h = reinterpret_cast<T *>(ws + Lw.h);
+    T *s = reinterpret_cast<T *>(ws + Lw.s);
+    T *z = reinterpret_cast<T *>(ws + Lw.z);
+    T *r = reinterpret_cast<T *>(ws + Lw.r);
+    T *q = reinterpret_cast<T *>(ws + Lw.q);
+    T *rt = reinterpret_cast<T *>(ws + Lw.rt);
+    T *xs = reinterpret_cast<T *>(ws + Lw.xs);
+    double *partials = reinterpret_cast<double *>(ws + Lw.partials);
+    unsigned *counter = reinterpret_cast<unsigned *>(ws + Lw.counter);
+    DevState *st = reinterpret_cast<DevState *>(ws + Lw.state);
+    int32_t *forced = reinterpret_cast<int32_t *>(ws + Lw.forced);
+    scg_trace_entry *trace = reinterpret_cast<scg_trace_entry *>(ws + Lw.trace);
+    double *tvd = reinterpret_cast<double *>(ws + Lw.tv);
+    const T *y = static_cast<const T *>(y_);
+    const T *x0 = static_cast<const T *>(x0_);
+    T *xout = static_cast<T *>(xout_);
+    const int variant = pr->variant;
+    const bool is_cg = variant == SCG_CG;
+
+    if (variant == SCG_S_PCG) {
+        int rc = ensure_filter(plan, pr->precond_mu);
+        if (rc) return rc;
+    }
+    const T *kern = static_cast<const T *>(plan->kern[prec_index<T>()]);
+
+    // Pads of the staged image and of the sinograms must be zero.
+    scg::launch_fill<T>(r, S, T(0), st0);
+    scg::launch_fill<T>(q, S, T(0), st0);
+    scg::launch_fill<T>(rt, S, T(0), st0);
+    scg::launch_fill<T>(xs, G.staged_elems(), T(0), st0);
+    HIP_TRY(hipMemsetAsync(counter, 0, 64, st0));
+
+    DevState hs{};
+    hs.eps = pr->eps;
+    hs.gamma0 = pr->gamma0;
+    hs.a = pr->a;
+    hs.kappa = pr->tv_kappa;
+    hs.max_iter = pr->max_iter;
+    hs.max_trials = pr->max_trials;
+    hs.variant = variant;
+    hs.flags = (int)pr->flags;
+    hs.k = 0;
+    hs.steps = is_cg ? 0 : -1;   // the initial step of the S- variants is not counted
+    hs.accepted = -1;
+    hs.trace_cap = std::min<int32_t>(trace_cap > 0 ? trace_cap : 0, pr->max_iter + 1);
+    if (trace_host == nullptr) hs.trace_cap = pr->max_iter + 1;
+    const int nf = forced_host ? std::min<int32_t>(std::max<int32_t>(forced_len, 0), pr->max_iter + 1) : 0;
+    hs.forced_len = nf;
+    HIP_TRY(hipMemcpyAsync(st, &hs, sizeof(DevState), hipMemcpyHostToDevice, st0));
+    if (nf > 0)
+        HIP_TRY(hipMemcpyAsync(forced, forced_host, (size_t)2 * nf * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st0));
+    const int32_t *forced_d = nf > 0 ? forced : nullptr;
+    const int is_f32 = sizeof(T) == 4;
+
+    // x_{1/2} = x0 (S- variants) or x_0 (CG).
+    T *x_start = is_cg ? x : xh;
+    if (x0 != nullptr) scg::launch_copy<T>(x_start, x0, J, nullptr, st0);
+    else scg::launch_fill<T>(x_start, J, T(0), st0);
+
+    const int rs = G.rs, off = scg::kSinoPadL;
+    auto project_res = [&](const T *img, int mode) {
+        scg::launch_stage<T>(img, xs, G, st, st0);
+        scg::launch_project<T>(xs, G, plan->pang, y, G.nb, r, rs, off, partials, counter, st, mode,
+                               trace, st0);
+    };
+    auto project_q = [&](int mode) {
+        scg::launch_stage<T>(p, xs, G, st, st0);
+        scg::launch_project<T>(xs, G, plan->pang, nullptr, 0, q, rs, off, partials, counter, st,
+                               mode, trace, st0);
+    };
+
+    // ---- initial step -------------------------------------------------
+    if (is_cg) {
+        // Alg. CG: g0 = A^T(A x0 - y), p0 = -g0, delta0 = ||g0||^2.
+        project_res(x, scg::kRedResidual);
+        scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
+                                   counter, st, scg::kRedDotGG, st0);
+        scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 3, 1, trace, st0);
+    } else {
+        // S-CG / S-CG-CD / S-PCG steps 1-7: x_{1/2} = x0, g0, (z0), p0, h0,
+        // alpha = -g0^T p0 / p0^T h0, x1 = x0 + alpha p0, k = 1.
+        project_res(xh, scg::kRedResidual);
+        if (variant == SCG_S_PCG) {
+            scg::launch_filter<T>(r, rt, kern, G, 1, st, st0);
+            scg::launch_backproject<T>(r, rt, G, plan->bang, g, z, nullptr, partials, counter, st,
+                                       scg::kRedNone, st0);
+            scg::launch_p_update<T>(g, z, p, G, partials, counter, st, 2, 1, trace, st0);
+        } else {
+            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
+                                       counter, st, scg::kRedNone, st0);
+            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 0, 1, trace, st0);
+        }
+        project_q(scg::kRedNormQ);
+        if (variant != SCG_S_CG_CD)
+            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
+                                       counter, st, scg::kRedNone, st0);
+        scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0, partials, counter, st0);
+    }
+
+    const int passes = (pr->max_trials + scg::kTrialsPerPass - 1) / scg::kTrialsPerPass;
+    auto enqueue_iteration = [&]() {
+        scg::launch_iter_begin(st, forced_d, trace, is_f32, st0);
+        if (is_cg) {
+            project_q(scg::kRedNormQCG);
+            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
+                                       counter, st, scg::kRedNone, st0);
+            scg::launch_x_update<T>(x, p, x, h, g, G, st, 1, partials, counter, st0);
+            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 3, 0, trace, st0);
+            project_res(x, scg::kRedResidual);
+            return;
+        }
+        // perturbed(x_k)
+        scg::launch_tv<T>(x, s, G, pr->tv_kappa, partials, counter, st, 1, nullptr, st0);
+        for (int ps = 0; ps < passes; ++ps)
+            scg::launch_trials<T>(x, s, G, partials, counter, st, trace, st0);
+        scg::launch_perturb<T>(x, s, xh, G, st, st0);
+        // the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP)
+        project_res(xh, scg::kRedResidualStep);
+        if (variant == SCG_S_PCG) {
+            scg::launch_filter<T>(r, rt, kern, G, 1, st, st0);
+            scg::launch_backproject<T>(r, rt, G, plan->bang, g, z, h, partials, counter, st,
+                                       scg::kRedDotGH, st0);
+            scg::launch_p_update<T>(g, z, p, G, partials, counter, st, 2, 0, trace, st0);
+        } else if (variant == SCG_S_CG_CD) {
+            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
+                                       counter, st, scg::kRedDotGG, st0);
+            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 1, 0, trace, st0);
+        } else {
+            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, h, partials,
+                                       counter, st, scg::kRedDotGH, st0);
+            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 0, 0, trace, st0);
+        }
+        project_q(scg::kRedNormQ);
+        if (variant != SCG_S_CG_CD)
+            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
+                                       counter, st, scg::kRedNone, st0);
+        scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0, partials, counter, st0);
+    };
+
+    // ---- loop: chunks of iterations, device decides when to stop ---------
+    int done = 0;
+    long issued = 0;
+    int chunk = 2;
+    HIP_TRY(hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipStreamSynchronize(st0));
+    while (!done && issued <= (long)pr->max_iter) {
+        for (int c = 0; c < chunk; ++c) enqueue_iteration();
+        issued += chunk;
+        chunk = std::min(chunk * 2, 16);
+        HIP_TRY(hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
+        HIP_TRY(hipStreamSynchronize(st0));
+    }
+    if (!done) {   // only reachable if the cap check never fired; close it now
+        scg::launch_iter_begin(st, forced_d, trace, is_f32, st0);
+    }
+
+    // ---- output ---------------------------------------------------------
+    const T *out = is_cg ? x : xh;
+    scg::launch_copy<T>(xout, out, J, nullptr, st0);
+    scg::launch_tv<T>(out, nullptr, G, pr->tv_kappa, partials, counter, nullptr, 0, tvd, st0);
+    DevState fs{};
+    double tv_out = 0.0;
+    HIP_TRY(hipMemcpyAsync(&fs, st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipMemcpyAsync(&tv_out, tvd, sizeof(double), hipMemcpyDeviceToHost, st0));
+    if (trace_host != nullptr && trace_cap > 0) {
+        const int n = std::min<int>(trace_cap, pr->max_iter + 1);
+        HIP_TRY(hipMemcpyAsync(trace_host, trace, (size_t)n * sizeof(scg_trace_entry),
+                               hipMemcpyDeviceToHost, st0));
+    }
+    HIP_TRY(hipStreamSynchronize(st0));
+    if (rep != nullptr) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->status = fs.done ? fs.status : SCG_ENOCONV;
+        rep->k = is_cg ? fs.k : std::max(fs.k, 1);
+        rep->steps = std::max(fs.steps, 0);
+        rep->trials_total = fs.trials_total;
+        rep->ell = fs.ell;
+        rep->f_out = fs.f_half;
+        rep->tv_out = tv_out;
+    }
+    return fs.done ? fs.status : SCG_ENOCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+void scg_default_params(scg_params *p)
+{
+    if (p == nullptr) return;
+    std::memset(p, 0, sizeof(*p));
+    p->variant = SCG_S_CG;
+    p->prec = SCG_F32;
+    p->eps = 0.0;
+    p->gamma0 = 0.0;
+    p->a = 0.975;
+    p->max_iter = 1000;
+    p->max_trials = 100;
+    p->tv_kappa = 0.0;
+    p->precond_mu = 0.0;
+    p->flags = 0;
+}
+
+const char *scg_strerror(int status)
+{
+    switch (status) {
+    case SCG_OK: return "ok";
+    case SCG_EINVAL: return "invalid argument";
+    case SCG_ENOMEM: return "out of device memory or workspace too small";
+    case SCG_EDEVICE: return "HIP runtime error";
+    case SCG_ENOCONV: return "iteration cap reached with f > eps";
+    case SCG_ENAN: return "non-finite value in a CG scalar";
+    case SCG_EBREAKDOWN: return "breakdown: ||A p||^2 = 0";
+    case SCG_EAGAIN: return "no free slot or memory";
+    case SCG_EINPROGRESS: return "in progress";
+    case SCG_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
+{
+    if (out == nullptr) return SCG_EINVAL;
+    *out = nullptr;
+    if (g == nullptr || g->n < 2 || g->n_angles < 1 || g->n_bins < 1) return SCG_EINVAL;
+    if (g->n > 16384 || g->n_angles > 65536 || g->n_bins > 65536) return SCG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SCG_EDEVICE;
+    Device dg(device);
+    scg_plan *p = new (std::nothrow) scg_plan();
+    if (p == nullptr) return SCG_ENOMEM;
+    p->device = device;
+    Geo &G = p->G;
+    G.n = g->n;
+    G.na = g->n_angles;
+    G.nb = g->n_bins;
+    G.xp = G.n + scg::kPadL + scg::kPadR;
+    G.rs = G.nb + scg::kSinoPadL + scg::kSinoPadR;
+    G.h = 0.5 * (G.n - 1);
+    G.hb = 0.5 * (G.nb - 1);
+    // The projector and backprojector grids must fit the reduction partials,
+    // and a padded projection plus the filter taps must fit in LDS.
+    const size_t bp_blocks = (size_t)((G.n + 15) / 16) * ((G.n + 15) / 16);
+    if ((size_t)((G.nb + 255) / 256) * G.na > (size_t)scg::kMaxPartials ||
+        bp_blocks > (size_t)scg::kMaxPartials || (size_t)3 * G.nb * sizeof(double) > 65536) {
+        delete p;
+        return SCG_EINVAL;
+    }
+    p->cosv.resize(G.na);
+    p->sinv.resize(G.na);
+    for (int a = 0; a < G.na; ++a) {
+        const double th = (double)a * kPi / (double)G.na;
+        p->cosv[a] = snap(std::cos(th));
+        p->sinv[a] = snap(std::sin(th));
+    }
+    std::vector<ProjAngle> pa;
+    std::vector<BpAngle> ba;
+    build_angles(G, p->cosv, p->sinv, pa, ba);
+    bool ok = hipMalloc(&p->pang, pa.size() * sizeof(ProjAngle)) == hipSuccess &&
+              hipMalloc(&p->bang, ba.size() * sizeof(BpAngle)) == hipSuccess &&
+              hipMalloc(&p->xs[0], G.staged_elems() * sizeof(float)) == hipSuccess &&
+              hipMalloc(&p->xs[1], G.staged_elems() * sizeof(double)) == hipSuccess &&
+              hipMalloc(&p->rpad[0], G.sino_elems() * sizeof(float)) == hipSuccess &&
+              hipMalloc(&p->rpad[1], G.sino_elems() * sizeof(double)) == hipSuccess &&
+              hipMalloc(&p->partials, scg::kMaxPartials * sizeof(double)) == hipSuccess &&
+              hipMalloc(&p->counter, 64) == hipSuccess &&
+              hipMalloc(&p->tvbuf, sizeof(double)) == hipSuccess;
+    if (!ok) {
+        scg_plan_destroy(p);
+        return SCG_ENOMEM;
+    }
+    ok = hipMemcpy(p->pang, pa.data(), pa.size() * sizeof(ProjAngle), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(p->bang, ba.data(), ba.size() * sizeof(BpAngle), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemset(p->xs[0], 0, G.staged_elems() * sizeof(float)) == hipSuccess &&
+         hipMemset(p->xs[1], 0, G.staged_elems() * sizeof(double)) == hipSuccess &&
+         hipMemset(p->rpad[0], 0, G.sino_elems() * sizeof(float)) == hipSuccess &&
+         hipMemset(p->rpad[1], 0, G.sino_elems() * sizeof(double)) == hipSuccess &&
+         hipMemset(p->counter, 0, 64) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        scg_plan_destroy(p);
+        return SCG_EDEVICE;
+    }
+    *out = p;
+    return SCG_OK;
+}
+
+void scg_plan_destroy(scg_plan *p)
+{
+    if (p == nullptr) return;
+    Device dg(p->device);
+    (void)hipFree(p->pang);
+    (void)hipFree(p->bang);
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(p->xs[i]);
+        (void)hipFree(p->rpad[i]);
+        (void)hipFree(p->kern[i]);
+    }
+    (void)hipFree(p->partials);
+    (void)hipFree(p->counter);
+    (void)hipFree(p->tvbuf);
+    delete p;
+}
+
+int scg_workspace_bytes(const scg_plan *plan, const scg_params *params, size_t *bytes)
+{
+    if (plan == nullptr || bytes == nullptr) return SCG_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    const size_t esz = params->prec == SCG_F64 ? sizeof(double) : sizeof(float);
+    *bytes = layout(plan->G, esz, params->max_iter).total;
+    return SCG_OK;
+}
+
+int scg_project(scg_plan *plan, int prec, const void *x, void *y, void *stream)
+{
+    if (plan == nullptr || x == nullptr || y == nullptr) return SCG_EINVAL;
+    if (prec != SCG_F32 && prec != SCG_F64) return SCG_EINVAL;
+    Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geo &G = plan->G;
+    if (prec == SCG_F32) {
+        float *xs = static_cast<float *>(plan->xs[0]);
+        scg::launch_stage<float>(static_cast<const float *>(x), xs, G, nullptr, s);
+        scg::launch_project<float>(xs, G, plan->pang, nullptr, 0, static_cast<float *>(y), G.nb, 0,
+                                   nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+    } else {
+        double *xs = static_cast<double *>(plan->xs[1]);
+        scg::launch_stage<double>(static_cast<const double *>(x), xs, G, nullptr, s);
+        scg::launch_project<double>(xs, G, plan->pang, nullptr, 0, static_cast<double *>(y), G.nb,
+                                    0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int scg_backproject(scg_plan *plan, int prec, const void *y, void *x, void *stream)
+{
+    if (plan == nullptr || x == nullptr || y == nullptr) return SCG_EINVAL;
+    if (prec != SCG_F32 && prec != SCG_F64) return SCG_EINVAL;
+    Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geo &G = plan->G;
+    if (prec == SCG_F32) {
+        float *rp = static_cast<float *>(plan->rpad[0]);
+        scg::launch_pad_sino<float>(static_cast<const float *>(y), rp, G, s);
+        scg::launch_backproject<float>(rp, nullptr, G, plan->bang, static_cast<float *>(x), nullptr,
+                                       nullptr, nullptr, nullptr, nullptr, scg::kRedNone, s);
+    } else {
+        double *rp = static_cast<double *>(plan->rpad[1]);
+        scg::launch_pad_sino<double>(static_cast<const double *>(y), rp, G, s);
+        scg::launch_backproject<double>(rp, nullptr, G, plan->bang, static_cast<double *>(x),
+                                        nullptr, nullptr, nullptr, nullptr, nullptr, scg::kRedNone,
+                                        s);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int scg_tv(scg_plan *plan, int prec, const void *x, double kappa, void *s_out, double *tv_host,
+           void *stream)
+{
+    if (plan == nullptr || x == nullptr || tv_host == nullptr) return SCG_EINVAL;
+    if (prec != SCG_F32 && prec != SCG_F64) return SCG_EINVAL;
+    if (!(kappa >= 0.0)) return SCG_EINVAL;
+    Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geo &G = plan->G;
+    if (prec == SCG_F32)
+        scg::launch_tv<float>(static_cast<const float *>(x), static_cast<float *>(s_out), G, kappa,
+                              plan->partials, plan->counter, nullptr, 0, plan->tvbuf, s);
+    else
+        scg::launch_tv<double>(static_cast<const double *>(x), static_cast<double *>(s_out), G,
+                               kappa, plan->partials, plan->counter, nullptr, 0, plan->tvbuf, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(tv_host, plan->tvbuf, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SCG_OK;
+}
+
+int scg_filter(scg_plan *plan, int prec, double mu, const void *r, void *out, void *stream)
+{
+    if (plan == nullptr || r == nullptr || out == nullptr) return SCG_EINVAL;
+    if (prec != SCG_F32 && prec != SCG_F64) return SCG_EINVAL;
+    Device dg(plan->device);
+    int rc = ensure_filter(plan, mu);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geo &G = plan->G;
+    if (prec == SCG_F32) {
+        float *rp = static_cast<float *>(plan->rpad[0]);
+        scg::launch_pad_sino<float>(static_cast<const float *>(r), rp, G, s);
+        scg::launch_filter<float>(rp, static_cast<float *>(out),
+                                  static_cast<const float *>(plan->kern[0]), G, 0, nullptr, s);
+    } else {
+        double *rp = static_cast<double *>(plan->rpad[1]);
+        scg::launch_pad_sino<double>(static_cast<const double *>(r), rp, G, s);
+        scg::launch_filter<double>(rp, static_cast<double *>(out),
+                                   static_cast<const double *>(plan->kern[1]), G, 0, nullptr, s);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const void *x0,
+              void *x_out, void *ws, size_t ws_bytes, scg_report *rep, scg_trace_entry *trace,
+              int32_t trace_cap, const int32_t *forced, int32_t forced_len, void *stream)
+{
+    if (plan == nullptr || y == nullptr || x_out == nullptr || ws == nullptr) return SCG_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    size_t need = 0;
+    scg_workspace_bytes(plan, params, &need);
+    if (ws_bytes < need) return SCG_ENOMEM;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SCG_EINVAL;
+    Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (params->prec == SCG_F32)
+        rc = solve_impl<float>(plan, params, y, x0, x_out, static_cast<char *>(ws), rep, trace,
+                               trace_cap, forced, forced_len, s);
+    else
+        rc = solve_impl<double>(plan, params, y, x0, x_out, static_cast<char *>(ws), rep, trace,
+                                trace_cap, forced, forced_len, s);
+    if (hipGetLastError() != hipSuccess) return SCG_EDEVICE;
+    return rc;
+}
+
+}  // extern "C"

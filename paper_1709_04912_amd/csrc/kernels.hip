@@ -1,0 +1,817 @@
+// gfx950 kernels of libscg: matrix-free projector / backprojector, TV and its
+// subgradient, the perturbation trials, CG vector updates and the
+// preconditioning filter. Every reduction is deterministic: FP64 per-thread
+// accumulation, a fixed wavefront butterfly, fixed per-block partials and a
+// fixed-order final sum done by the last block to finish (no floating-point
+// atomics).
+#include "scg_internal.h"
+
+namespace scg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxVecBlocks = 512;
+
+__device__ __forceinline__ float sat(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+__device__ __forceinline__ double sat(double v) { return fmin(fmax(v, 0.0), 1.0); }
+
+template <typename T> __device__ __forceinline__ T pK(const ProjAngle &a);
+template <> __device__ __forceinline__ float pK<float>(const ProjAngle &a) { return a.Kf; }
+template <> __device__ __forceinline__ double pK<double>(const ProjAngle &a) { return a.K; }
+template <typename T> __device__ __forceinline__ T pC(const ProjAngle &a);
+template <> __device__ __forceinline__ float pC<float>(const ProjAngle &a) { return a.Cf; }
+template <> __device__ __forceinline__ double pC<double>(const ProjAngle &a) { return a.C; }
+template <typename T> __device__ __forceinline__ T pM(const ProjAngle &a);
+template <> __device__ __forceinline__ float pM<float>(const ProjAngle &a) { return a.inv_mf; }
+template <> __device__ __forceinline__ double pM<double>(const ProjAngle &a) { return a.inv_m; }
+
+template <typename T> struct BpW { T K, C, CK, M; };
+template <typename T> __device__ __forceinline__ BpW<T> bpw(const BpAngle &a);
+template <> __device__ __forceinline__ BpW<float> bpw<float>(const BpAngle &a)
+{
+    return {a.Kf, a.Cf, a.CKf, a.inv_mf};
+}
+template <> __device__ __forceinline__ BpW<double> bpw<double>(const BpAngle &a)
+{
+    return {a.K, a.C, a.C - a.K, a.inv_m};
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double load_relaxed(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block partial sums of NV values; the last block to finish sums all partials
+// in a fixed order. Returns true in the last block; `tot` is valid in its
+// thread 0. Every thread of the block must call this.
+template <int NV>
+__device__ bool reduce_finish(const double (&v)[NV], double *partials, unsigned *counter,
+                              double (&tot)[NV])
+{
+    __shared__ double sh[NV][kBlock / 64];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const unsigned nblk = gridDim.x * gridDim.y;
+    const unsigned bid = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) sh[k][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[k][w];
+            partials[(size_t)bid * NV + k] = s;
+        }
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        s_last = (prev == nblk - 1);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += load_relaxed(&partials[(size_t)b * NV + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(acc[k]);
+        if (lane == 0) sh[k][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[k][w];
+            tot[k] = s;
+        }
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool stopped(const DevState *st) { return st != nullptr && st->done; }
+
+__device__ __forceinline__ scg_trace_entry *trace_at(DevState *st, scg_trace_entry *trace, int k)
+{
+    if (trace == nullptr || k < 1 || k > st->trace_cap) return nullptr;
+    return &trace[k - 1];
+}
+
+__device__ __forceinline__ void set_done(DevState *st, int status)
+{
+    st->done = 1;
+    st->status = status;
+}
+
+inline int vec_blocks(size_t n)
+{
+    size_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > (size_t)kMaxVecBlocks) b = kMaxVecBlocks;
+    return (int)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n, T v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+__global__ void k_copy(T *dst, const T *src, size_t n, const DevState *st)
+{
+    if (stopped(st)) return;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+template <typename T> void launch_fill(T *p, size_t n, T v, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(kBlock), 0, s, p, n, v);
+}
+
+template <typename T>
+void launch_copy(T *dst, const T *src, size_t n, const DevState *st, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_copy<T>, dim3(vec_blocks(n)), dim3(kBlock), 0, s, dst, src, n, st);
+}
+
+// ---------------------------------------------------------------------------
+// Image staging: padded row-major and padded transposed copies (32x32 tiles
+// through LDS so both writes are coalesced).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__restrict__ xs,
+                                                Geo G, const DevState *st)
+{
+    if (stopped(st)) return;
+    __shared__ T tile[32][33];
+    const int n = G.n, xp = G.xp;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    T *rows = xs + (size_t)xp + kPadL;                 // after the first guard row
+    T *cols = xs + (size_t)(n + 2) * xp + kPadL;       // after the middle guard row
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        T v = T(0);
+        if (i < n && j < n) {
+            v = x[(size_t)i * n + j];
+            rows[(size_t)i * xp + j] = v;
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (i < n && j < n) cols[(size_t)j * xp + i] = tile[tx][r];
+    }
+}
+
+template <typename T>
+void launch_stage(const T *x, T *xs, const Geo &G, const DevState *st, hipStream_t s)
+{
+    dim3 grid((G.n + 31) / 32, (G.n + 31) / 32);
+    hipLaunchKernelGGL(k_stage<T>, grid, dim3(256), 0, s, x, xs, G, st);
+}
+
+// ---------------------------------------------------------------------------
+// Forward projector A (ray-driven). One thread per ray (a, b); the ray walks
+// the steps of its major axis and, at each step, gathers the two pixels that
+// bracket its crossing point from the padded staged image.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(const T *__restrict__ xs, Geo G,
+                                                  const ProjAngle *__restrict__ ang,
+                                                  const T *__restrict__ y, int y_stride,
+                                                  T *__restrict__ out, int out_stride,
+                                                  int out_off, double *partials,
+                                                  unsigned *counter, DevState *st, int mode,
+                                                  scg_trace_entry *trace)
+{
+    if (stopped(st)) return;
+    const int a = blockIdx.y;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (b < G.nb) {
+        const ProjAngle A = ang[a];
+        const int n = G.n;
+        const T *img = xs + (size_t)(A.major ? (n + 2) : 1) * G.xp + kPadL;
+        const double u0 = fma((double)b, A.u0_step, A.u0_base);
+        // Steps whose crossing lies in [-1, n) carry weight; the range is
+        // widened by one step on each side and the padding absorbs the extra.
+        int s_lo = 0, s_hi = n - 1;
+        if (A.slope == 0.0) {
+            if (!(u0 >= -1.0 && u0 < (double)n)) s_hi = -1;
+        } else {
+            double l1 = (-1.0 - u0) / A.slope, l2 = ((double)n - u0) / A.slope;
+            double lo = fmin(l1, l2), hi = fmax(l1, l2);
+            if (lo > (double)(n - 1) || hi < 0.0) {
+                s_hi = -1;
+            } else {
+                s_lo = (int)floor(fmax(lo, 0.0));
+                s_hi = (int)ceil(fmin(hi, (double)(n - 1)));
+            }
+        }
+        const T K = pK<T>(A), C = pC<T>(A);
+        T acc = T(0), accr = T(0);
+        for (int i = s_lo; i <= s_hi; ++i) {
+            const double u = fma((double)i, A.slope, u0);
+            const double fu = floor(u);
+            const int jl = (int)fu;
+            const T fl = (T)(u - fu);
+            const T wl = sat(fma(fl, -K, C));
+            const T *row = img + (size_t)i * G.xp;
+            const T xl = row[jl], xr = row[jl + 1];
+            acc = fma(wl, xl - xr, acc);
+            accr += xr;
+        }
+        T val = (acc + accr) * pM<T>(A);
+        if (y != nullptr) val -= y[(size_t)a * y_stride + b];
+        out[(size_t)a * out_stride + out_off + b] = val;
+        sq = (double)val * (double)val;
+    }
+    if (mode == kRedNone) return;
+    double v[1] = {sq}, tot[1];
+    if (!reduce_finish<1>(v, partials, counter, tot) || threadIdx.x != 0) return;
+    const double s = tot[0];
+    if (mode == kRedResidual || mode == kRedResidualStep) {
+        const double f = 0.5 * s;
+        st->f_half = f;
+        if (mode == kRedResidualStep)
+            if (scg_trace_entry *t = trace_at(st, trace, st->k)) t->f_half = f;
+        if (!isfinite(f)) {
+            set_done(st, SCG_ENAN);
+        } else if (f <= st->eps) {
+            // Inside a step, the next loop test f(x_{k+1/2}) <= eps ends the
+            // solve at k+1 with output x_{k+1/2}; the rest of the step is not
+            // needed for the output and is skipped.
+            if (mode == kRedResidualStep) {
+                st->steps += 1;
+                st->k += 1;
+            }
+            set_done(st, SCG_OK);
+        }
+    } else if (mode == kRedNormQ || mode == kRedInitNormQ || mode == kRedNormQCG) {
+        st->qq = s;
+        if (!isfinite(s)) {
+            set_done(st, SCG_ENAN);
+        } else if (s == 0.0) {
+            set_done(st, SCG_EBREAKDOWN);
+        } else {
+            st->alpha = (mode == kRedNormQCG) ? st->delta / s : -st->gp / s;
+            if (scg_trace_entry *t = trace_at(st, trace, st->k)) t->alpha = st->alpha;
+        }
+    }
+}
+
+template <typename T>
+void launch_project(const T *xs, const Geo &G, const ProjAngle *ang, const T *y, int y_stride,
+                    T *out, int out_stride, int out_off, double *partials, unsigned *counter,
+                    DevState *st, int mode, scg_trace_entry *trace, hipStream_t s)
+{
+    dim3 grid((G.nb + kBlock - 1) / kBlock, G.na);
+    hipLaunchKernelGGL(k_project<T>, grid, dim3(kBlock), 0, s, xs, G, ang, y, y_stride, out,
+                       out_stride, out_off, partials, counter, st, mode, trace);
+}
+
+// Copies an unpadded sinogram into the padded layout (pads stay zero).
+template <typename T>
+__global__ void k_pad_sino(const T *__restrict__ y, T *__restrict__ rpad, Geo G)
+{
+    const size_t L = (size_t)G.na * G.nb;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < L;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const size_t a = q / G.nb, b = q % G.nb;
+        rpad[a * G.rs + kSinoPadL + b] = y[q];
+    }
+}
+
+template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pad_sino<T>, dim3(vec_blocks((size_t)G.na * G.nb)), dim3(kBlock), 0, s,
+                       y, rpad, G);
+}
+
+// ---------------------------------------------------------------------------
+// Backprojector A^T (pixel-driven). One thread per pixel of a 16x16 tile;
+// per angle the pixel's footprint covers at most two bins. With r2 != NULL
+// the same weights also backproject a second sinogram (dual backprojection
+// for S-PCG: g' = A^T r and z' = A^T F^T C F r in one pass).
+// ---------------------------------------------------------------------------
+
+template <typename T, bool DUAL>
+__global__ __launch_bounds__(256) void k_backproject(const T *__restrict__ r,
+                                                      const T *__restrict__ r2, Geo G,
+                                                      const BpAngle *__restrict__ ang,
+                                                      T *__restrict__ out, T *__restrict__ out2,
+                                                      const T *__restrict__ dotv,
+                                                      double *partials, unsigned *counter,
+                                                      DevState *st, int mode)
+{
+    if (stopped(st)) return;
+    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const bool in = (i < G.n) && (j < G.n);
+    const double xc = (double)j - G.h, yc = G.h - (double)i;
+    T acc = T(0), acc2 = T(0);
+    const T *rr = r + kSinoPadL;
+    const T *rr2 = DUAL ? r2 + kSinoPadL : nullptr;
+    const double ub = (double)G.nb;
+    for (int a = 0; a < G.na; ++a) {
+        const BpAngle A = ang[a];
+        const BpW<T> W = bpw<T>(A);
+        double u = fma(xc, A.c, fma(yc, A.s, G.hb));
+        u = fmin(fmax(u, -1.0), ub);
+        const double fu = floor(u);
+        const int b0 = (int)fu;
+        const T f = (T)(u - fu);
+        const T w0 = sat(fma(f, -W.K, W.C));
+        const T w1 = sat(fma(f, W.K, W.CK));
+        const size_t off = (size_t)a * G.rs + b0;
+        acc = fma(W.M, fma(w0, rr[off], w1 * rr[off + 1]), acc);
+        if (DUAL) acc2 = fma(W.M, fma(w0, rr2[off], w1 * rr2[off + 1]), acc2);
+    }
+    double d = 0.0;
+    if (in) {
+        const size_t p = (size_t)i * G.n + j;
+        out[p] = acc;
+        if (DUAL) out2[p] = acc2;
+        if (mode == kRedDotGH) d = (double)(DUAL ? acc2 : acc) * (double)dotv[p];
+        else if (mode == kRedDotGG) d = (double)acc * (double)acc;
+    }
+    if (mode == kRedNone) return;
+    double v[1] = {d}, tot[1];
+    if (!reduce_finish<1>(v, partials, counter, tot) || threadIdx.x != 0) return;
+    if (mode == kRedDotGH) st->gh = tot[0];
+    else st->gg = tot[0];
+}
+
+template <typename T>
+void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,
+                        T *out2, const T *dotv, double *partials, unsigned *counter,
+                        DevState *st, int mode, hipStream_t s)
+{
+    dim3 grid((G.n + 15) / 16, (G.n + 15) / 16);
+    if (r2 != nullptr)
+        hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(256), 0, s, r, r2, G, ang, out,
+                           out2, dotv, partials, counter, st, mode);
+    else
+        hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(256), 0, s, r, r2, G, ang, out,
+                           out2, dotv, partials, counter, st, mode);
+}
+
+// ---------------------------------------------------------------------------
+// Total variation: t_ij = sqrt(a^2 + b^2 + kappa^2) over the (N-1)^2 interior
+// forward differences a = x[i+1][j] - x[i][j], b = x[i][j+1] - x[i][j], and
+// the subgradient s = sum over terms of d t / d x (a term with t = 0 adds 0).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T tv_term(T a, T b, T k2)
+{
+    return sqrt(fma(a, a, fma(b, b, k2)));
+}
+
+// mode 0: TV only into *tv_dst; mode 1: TV + subgradient + ||s||^2 into the
+// solver state (the start of perturbed()).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tv(const T *__restrict__ x, T *__restrict__ s_out,
+                                             Geo G, double kappa, double *partials,
+                                             unsigned *counter, DevState *st, int mode,
+                                             double *tv_dst)
+{
+    if (stopped(st) && mode == 1) return;
+    const int n = G.n;
+    const T k2 = (T)(kappa * kappa);
+    double tv = 0.0, ss = 0.0;
+    const size_t J = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < J;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        const T xc = x[p];
+        T sg = T(0);
+        if (i + 1 < n && j + 1 < n) {          // own term (i, j)
+            const T a = x[p + n] - xc, b = x[p + 1] - xc;
+            const T t = tv_term(a, b, k2);
+            tv += (double)t;
+            if (t != T(0)) sg -= (a + b) / t;
+        }
+        if (i >= 1 && j + 1 < n) {             // term (i-1, j): x is its lower neighbour
+            const T base = x[p - n];
+            const T a = xc - base, b = x[p - n + 1] - base;
+            const T t = tv_term(a, b, k2);
+            if (t != T(0)) sg += a / t;
+        }
+        if (j >= 1 && i + 1 < n) {             // term (i, j-1): x is its right neighbour
+            const T base = x[p - 1];
+            const T a = x[p - 1 + n] - base, b = xc - base;
+            const T t = tv_term(a, b, k2);
+            if (t != T(0)) sg += b / t;
+        }
+        if (s_out != nullptr) s_out[p] = sg;
+        ss += (double)sg * (double)sg;
+    }
+    double v[2] = {tv, ss}, tot[2];
+    if (!reduce_finish<2>(v, partials, counter, tot) || threadIdx.x != 0) return;
+    if (mode == 0) {
+        *tv_dst = tot[0];
+        return;
+    }
+    st->tv_x = tot[0];
+    st->s_norm2 = tot[1];
+    if (tot[1] > 0.0 && isfinite(tot[1])) {
+        st->inv_snorm = 1.0 / sqrt(tot[1]);
+    } else {
+        // No nonascending direction: x_{k+1/2} = x_k and l is unchanged.
+        st->inv_snorm = 0.0;
+        st->search_done = 1;
+        st->accepted = -1;
+        st->gamma = 0.0;
+    }
+}
+
+template <typename T>
+void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
+               unsigned *counter, DevState *st, int mode, double *tv_dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tv<T>, dim3(vec_blocks((size_t)G.n * G.n)), dim3(kBlock), 0, s, x, s_out,
+                       G, kappa, partials, counter, st, mode, tv_dst);
+}
+
+// ---------------------------------------------------------------------------
+// perturbed(): one pass evaluates TV(x + gamma_m v) for kTrialsPerPass
+// successive values gamma_m = gamma0 a^(l+m), v = -s/||s||, together with
+// TV(x) summed in the same order; the last block takes the first m with
+// TV(x + gamma_m v) <= TV(x), exactly as trying them one after another.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trials(const T *__restrict__ x, const T *__restrict__ s,
+                                                 Geo G, double *partials, unsigned *counter,
+                                                 DevState *st, scg_trace_entry *trace)
+{
+    if (st->done || st->search_done) return;
+    constexpr int M = kTrialsPerPass;
+    __shared__ T gam[M];
+    if (threadIdx.x < M)
+        gam[threadIdx.x] = (T)(st->gamma0 * pow(st->a, (double)(st->ell + (int)threadIdx.x)));
+    __syncthreads();
+    const T inv = (T)st->inv_snorm;
+    const T k2 = (T)(st->kappa * st->kappa);
+    const int n = G.n, m1 = n - 1;
+    double acc[M + 1];
+#pragma unroll
+    for (int m = 0; m <= M; ++m) acc[m] = 0.0;
+    const size_t terms = (size_t)m1 * m1;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < terms;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / m1), j = (int)(q % m1);
+        const size_t c = (size_t)i * n + j;
+        const T xc = x[c], xd = x[c + n], xr = x[c + 1];
+        const T vc = -s[c] * inv, vd = -s[c + n] * inv, vr = -s[c + 1] * inv;
+        acc[M] += (double)tv_term(xd - xc, xr - xc, k2);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const T g = gam[m];
+            const T zc = fma(g, vc, xc), zd = fma(g, vd, xd), zr = fma(g, vr, xr);
+            acc[m] += (double)tv_term(zd - zc, zr - zc, k2);
+        }
+    }
+    double tot[M + 1];
+    if (!reduce_finish<M + 1>(acc, partials, counter, tot) || threadIdx.x != 0) return;
+    const double tvx = tot[M];
+    st->tv_x = tvx;
+    const int left = st->max_trials - st->trials_step;
+    const int nv = left < M ? left : M;
+    int hit = -1;
+    for (int m = 0; m < nv; ++m)
+        if (tot[m] <= tvx) {
+            hit = m;
+            break;
+        }
+    const int used = hit >= 0 ? hit + 1 : nv;
+    const int first = st->trials_step;
+    st->ell += used;
+    st->trials_step += used;
+    st->trials_total += used;
+    if (hit >= 0) {
+        st->accepted = first + hit;
+        st->gamma = (double)gam[hit];
+        st->search_done = 1;
+    } else if (st->trials_step >= st->max_trials) {
+        st->accepted = -1;
+        st->gamma = 0.0;
+        st->search_done = 1;
+    }
+    if (st->search_done) {
+        if (scg_trace_entry *t = trace_at(st, trace, st->k)) {
+            t->accepted = st->accepted;
+            t->trials = st->trials_step;
+            t->ell = st->ell;
+            t->gamma = st->gamma;
+            t->tv_x = tvx;
+        }
+    }
+}
+
+template <typename T>
+void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsigned *counter,
+                   DevState *st, scg_trace_entry *trace, hipStream_t s0)
+{
+    size_t terms = (size_t)(G.n - 1) * (G.n - 1);
+    hipLaunchKernelGGL(k_trials<T>, dim3(vec_blocks(terms)), dim3(kBlock), 0, s0, x, s, G,
+                       partials, counter, st, trace);
+}
+
+// x_{k+1/2} = x_k + gamma v, computed exactly as in the trials.
+template <typename T>
+__global__ void k_perturb(const T *__restrict__ x, const T *__restrict__ s, T *__restrict__ xh,
+                          size_t J, DevState *st)
+{
+    if (st->done) return;
+    const bool move = st->accepted >= 0 && st->gamma != 0.0;
+    const T g = (T)st->gamma, inv = (T)st->inv_snorm;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < J;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const T xc = x[p];
+        xh[p] = move ? fma(g, -s[p] * inv, xc) : xc;
+    }
+}
+
+template <typename T>
+void launch_perturb(const T *x, const T *s, T *xh, const Geo &G, DevState *st, hipStream_t s0)
+{
+    size_t J = (size_t)G.n * G.n;
+    hipLaunchKernelGGL(k_perturb<T>, dim3(vec_blocks(J)), dim3(kBlock), 0, s0, x, s, xh, J, st);
+}
+
+// ---------------------------------------------------------------------------
+// Direction update p' = -src + beta p with the partial g'^T p'.
+//   rule 0 (CG-PR-STEP):  beta = g'^T h / p^T h   (p^T h evaluated as ||A p||^2)
+//   rule 1 (CG-CD-STEP):  beta = -||g'||^2 / g^T p
+//   rule 2 (PCG-PR-STEP): beta = z'^T h / p^T h, src = z'
+//   rule 3 (CG-STEP):     beta = delta' / delta, delta' = ||g'||^2
+// init != 0: beta = 0 (the initial p0 = -g0 or -z0).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_p_update(const T *__restrict__ g, const T *__restrict__ z,
+                                                   T *__restrict__ p, size_t J, double *partials,
+                                                   unsigned *counter, DevState *st, int rule,
+                                                   int init, scg_trace_entry *trace)
+{
+    if (st->done) return;
+    double beta = 0.0;
+    if (!init) {
+        if (rule == 0 || rule == 2) beta = st->gh / st->qq_prev;
+        else if (rule == 1) beta = -st->gg / st->gp_prev;
+        else beta = st->gg / st->delta;
+    }
+    const T bt = (T)beta;
+    const T *src = (rule == 2) ? z : g;
+    double acc = 0.0;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < J;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const T pn = init ? -src[q] : fma(bt, p[q], -src[q]);
+        p[q] = pn;
+        acc += (double)g[q] * (double)pn;
+    }
+    double v[1] = {acc}, tot[1];
+    if (!reduce_finish<1>(v, partials, counter, tot) || threadIdx.x != 0) return;
+    st->beta = beta;
+    st->gp = tot[0];
+    if (rule == 3) st->delta = st->gg;
+    if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
+    if (!init)
+        if (scg_trace_entry *t = trace_at(st, trace, st->k)) t->beta = beta;
+}
+
+template <typename T>
+void launch_p_update(const T *g, const T *z, T *p, const Geo &G, double *partials,
+                     unsigned *counter, DevState *st, int rule, int init,
+                     scg_trace_entry *trace, hipStream_t s)
+{
+    size_t J = (size_t)G.n * G.n;
+    hipLaunchKernelGGL(k_p_update<T>, dim3(vec_blocks(J)), dim3(kBlock), 0, s, g, z, p, J,
+                       partials, counter, st, rule, init, trace);
+}
+
+// x' = x_{k+1/2} + alpha p'. The first block's thread 0 closes the step
+// (k, steps, and the carried ||A p||^2, g^T p). In plain CG mode also
+// g' = g + alpha h with ||g'||^2 (CG-STEP's recursive gradient).
+template <typename T>
+__global__ __launch_bounds__(256) void k_x_update(const T *__restrict__ xh, const T *__restrict__ p,
+                                                   T *__restrict__ x, const T *__restrict__ h,
+                                                   T *__restrict__ g, size_t J, DevState *st,
+                                                   int cg_mode, double *partials,
+                                                   unsigned *counter)
+{
+    if (st->done) return;
+    const T al = (T)st->alpha;
+    double acc = 0.0;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < J;
+         q += (size_t)gridDim.x * blockDim.x) {
+        x[q] = fma(al, p[q], xh[q]);
+        if (cg_mode) {
+            const T gn = fma(al, h[q], g[q]);
+            g[q] = gn;
+            acc += (double)gn * (double)gn;
+        }
+    }
+    if (!cg_mode) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->qq_prev = st->qq;
+            st->gp_prev = st->gp;
+            st->k += 1;
+            st->steps += 1;
+        }
+        return;
+    }
+    double v[1] = {acc}, tot[1];
+    if (!reduce_finish<1>(v, partials, counter, tot) || threadIdx.x != 0) return;
+    st->gg = tot[0];
+    st->qq_prev = st->qq;
+    st->k += 1;
+    st->steps += 1;
+}
+
+template <typename T>
+void launch_x_update(const T *xh, const T *p, T *x, const T *h, T *g, const Geo &G, DevState *st,
+                     int cg_mode, double *partials, unsigned *counter, hipStream_t s)
+{
+    size_t J = (size_t)G.n * G.n;
+    hipLaunchKernelGGL(k_x_update<T>, dim3(vec_blocks(J)), dim3(kBlock), 0, s, xh, p, x, h, g, J,
+                       st, cg_mode, partials, counter);
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioning filter F^T C F per projection, as the linear convolution
+// with k[d] = (1/P) sum_m c(w_m) cos(w_m d) (|d| < n_bins) that the
+// zero-padded DFT product equals. One block per angle; the projection and
+// the kernel are staged in LDS and each thread produces four neighbouring
+// outputs from a sliding window of kernel taps.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__restrict__ out,
+                                                 const T *__restrict__ kern, Geo G,
+                                                 int out_padded, const DevState *st)
+{
+    if (stopped(st)) return;
+    extern __shared__ unsigned char smem[];
+    T *row = reinterpret_cast<T *>(smem);
+    T *kk = row + G.nb;                  // kk[d + nb - 1] = k[|d|], d in (-nb, nb)
+    const int a = blockIdx.x, nb = G.nb;
+    const T *ra = r + (size_t)a * G.rs + kSinoPadL;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) row[b] = ra[b];
+    for (int d = threadIdx.x; d < 2 * nb - 1; d += blockDim.x) {
+        const int dd = d - (nb - 1);
+        kk[d] = kern[dd < 0 ? -dd : dd];
+    }
+    __syncthreads();
+    for (int b0 = threadIdx.x * 4; b0 < nb; b0 += blockDim.x * 4) {
+        // out[b0+t] = sum_bp k[b0 + t - bp] row[bp]
+        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        for (int bp = 0; bp < nb; ++bp) {
+            const T rv = row[bp];
+            const int base = b0 - bp + nb - 1;
+            acc0 = fma(kk[base], rv, acc0);
+            if (b0 + 1 < nb) acc1 = fma(kk[base + 1], rv, acc1);
+            if (b0 + 2 < nb) acc2 = fma(kk[base + 2], rv, acc2);
+            if (b0 + 3 < nb) acc3 = fma(kk[base + 3], rv, acc3);
+        }
+        T *oa = out + (size_t)a * (out_padded ? G.rs : nb) + (out_padded ? kSinoPadL : 0);
+        oa[b0] = acc0;
+        if (b0 + 1 < nb) oa[b0 + 1] = acc1;
+        if (b0 + 2 < nb) oa[b0 + 2] = acc2;
+        if (b0 + 3 < nb) oa[b0 + 3] = acc3;
+    }
+}
+
+template <typename T>
+void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
+                   const DevState *st, hipStream_t s)
+{
+    size_t shm = (size_t)(3 * G.nb) * sizeof(T);
+    hipLaunchKernelGGL(k_filter<T>, dim3(G.na), dim3(256), shm, s, r, out, kernel, G, out_padded,
+                       st);
+}
+
+// ---------------------------------------------------------------------------
+// Start of a loop iteration: the iteration cap, per-step resets and replayed
+// perturbation decisions.
+// ---------------------------------------------------------------------------
+
+__global__ void k_iter_begin(DevState *st, const int32_t *forced, scg_trace_entry *trace,
+                             int is_f32)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (st->done) return;
+    if (st->steps >= st->max_iter) {
+        set_done(st, SCG_ENOCONV);
+        return;
+    }
+    st->trials_step = 0;
+    st->accepted = -1;
+    st->gamma = 0.0;
+    st->search_done = (st->flags & SCG_FLAG_NO_PERTURB) ? 1 : 0;
+    const int k = st->k;
+    if (scg_trace_entry *t = trace_at(st, trace, k)) {
+        t->k = k;
+        t->accepted = -1;
+        t->trials = 0;
+        t->ell = st->ell;
+        t->gamma = 0.0;
+        t->beta = 0.0;
+        t->alpha = 0.0;
+        t->tv_x = 0.0;
+        t->f_half = 0.0;
+    }
+    if (forced != nullptr && k - 1 < st->forced_len && !st->search_done) {
+        const int nt = forced[2 * (k - 1)], am = forced[2 * (k - 1) + 1];
+        const int l0 = st->ell;
+        double g = 0.0;
+        if (am >= 0) {
+            g = st->gamma0 * pow(st->a, (double)(l0 + am));
+            g = is_f32 ? (double)(float)g : g;
+        }
+        st->ell = l0 + nt;
+        st->trials_step = nt;
+        st->trials_total += nt;
+        st->accepted = am;
+        st->gamma = g;
+        st->search_done = 1;
+        if (scg_trace_entry *t = trace_at(st, trace, k)) {
+            t->accepted = am;
+            t->trials = nt;
+            t->ell = st->ell;
+            t->gamma = g;
+        }
+    }
+}
+
+void launch_iter_begin(DevState *st, const int32_t *forced, scg_trace_entry *trace,
+                       int is_f32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(64), 0, s, st, forced, trace, is_f32);
+}
+
+// ---- explicit instantiations ----------------------------------------------
+#define SCG_INST(T)                                                                            \
+    template void launch_fill<T>(T *, size_t, T, hipStream_t);                                 \
+    template void launch_copy<T>(T *, const T *, size_t, const DevState *, hipStream_t);       \
+    template void launch_stage<T>(const T *, T *, const Geo &, const DevState *, hipStream_t); \
+    template void launch_project<T>(const T *, const Geo &, const ProjAngle *, const T *, int,  \
+                                    T *, int, int, double *, unsigned *, DevState *, int,       \
+                                    scg_trace_entry *, hipStream_t);                            \
+    template void launch_pad_sino<T>(const T *, T *, const Geo &, hipStream_t);                \
+    template void launch_backproject<T>(const T *, const T *, const Geo &, const BpAngle *,    \
+                                        T *, T *, const T *, double *, unsigned *, DevState *, \
+                                        int, hipStream_t);                                      \
+    template void launch_tv<T>(const T *, T *, const Geo &, double, double *, unsigned *,      \
+                               DevState *, int, double *, hipStream_t);                         \
+    template void launch_trials<T>(const T *, const T *, const Geo &, double *, unsigned *,    \
+                                   DevState *, scg_trace_entry *, hipStream_t);                 \
+    template void launch_perturb<T>(const T *, const T *, T *, const Geo &, DevState *,        \
+                                    hipStream_t);                                               \
+    template void launch_p_update<T>(const T *, const T *, T *, const Geo &, double *,         \
+                                     unsigned *, DevState *, int, int, scg_trace_entry *,      \
+                                     hipStream_t);                                              \
+    template void launch_x_update<T>(const T *, const T *, T *, const T *, T *, const Geo &,   \
+                                     DevState *, int, double *, unsigned *, hipStream_t);      \
+    template void launch_filter<T>(const T *, T *, const T *, const Geo &, int,                \
+                                   const DevState *, hipStream_t);
+
+SCG_INST(float)
+SCG_INST(double)
+
+}  // namespace scg

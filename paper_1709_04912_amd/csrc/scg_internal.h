@@ -1,0 +1,127 @@
+// Internal declarations of libscg (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/scg.h"
+
+namespace scg {
+
+// Staged image layout (ray-driven projector input): two N x N copies of the
+// image, row-major and transposed, each row padded with zeros (kPadL columns
+// on the left, kPadR on the right) and with one zero guard row before, between
+// and after the copies. Padding lets a ray read the two pixels around its
+// crossing point without bounds checks.
+constexpr int kPadL = 2;
+constexpr int kPadR = 4;
+// Padded sinogram layout (backprojector input): rows of n_bins + 4 entries,
+// bin b at offset b + 1; the pads stay zero.
+constexpr int kSinoPadL = 1;
+constexpr int kSinoPadR = 3;
+
+constexpr int kTrialsPerPass = 16;   // TV trials evaluated per pass of perturbed()
+constexpr int kMaxPartials = 16384;  // block partials per reduction (max blocks x values)
+
+struct Geo {
+    int n, na, nb;
+    int xp;       // staged image row length  = n + kPadL + kPadR
+    int rs;       // padded sinogram row stride = nb + kSinoPadL + kSinoPadR
+    double h;     // (n - 1) / 2
+    double hb;    // (nb - 1) / 2
+    size_t staged_elems() const { return (size_t)(2 * n + 3) * xp; }
+    size_t sino_elems() const { return (size_t)na * rs; }
+    size_t img_elems() const { return (size_t)n * n; }
+};
+
+// Ray-driven frame of one angle. A ray crosses the image one step (row or
+// column of the major axis) at a time; at step i the crossing coordinate
+// along the minor axis, in pixel-index units, is
+//     u(i, b) = u0_base + b * u0_step + i * slope,
+// the chord splits between the pixels floor(u) and floor(u) + 1, and the left
+// one receives (1/m) * clamp(C - frac(u) * K, 0, 1) with m = max(|c|,|s|),
+// K = m/n (n = min(|c|,|s|); K capped at 2^20 for axis-aligned rays), C = K/2+1/2.
+struct ProjAngle {
+    double u0_base, u0_step, slope;
+    double K, C, inv_m;
+    float Kf, Cf, inv_mf;
+    int major;    // 0: steps over rows (|c| >= |s|), 1: steps over columns
+};
+
+// Pixel-driven frame of one angle: pixel centre projects to the bin coordinate
+// u = x c + y s + (nb-1)/2; bins floor(u) and floor(u)+1 receive
+// (1/m) clamp(C - d K, 0, 1) at distances d = frac(u) and 1 - frac(u), with
+// K = 1/n (capped at 2^20) and C = m K / 2 + 1/2.
+struct BpAngle {
+    double c, s;
+    double K, C, inv_m;
+    float Kf, Cf, CKf, inv_mf;   // CKf = C - K
+};
+
+// Device-resident solver state: scalars in FP64, control in int.
+struct DevState {
+    // parameters
+    double eps, gamma0, a, kappa;
+    int max_iter, max_trials, variant, flags;
+    // loop control
+    int k, steps, done, status;
+    // perturbation
+    int ell, trials_step, accepted, search_done;
+    int trials_total, forced_len, trace_cap, pad0;
+    double tv_x, s_norm2, inv_snorm, gamma;
+    // CG scalars
+    double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
+    double tv_out;
+};
+
+enum RedMode : int {
+    kRedNone = 0,
+    kRedResidual = 1,   // f_half = 1/2 sum r^2, stop test (initial point / plain CG)
+    kRedResidualStep = 7,  // as kRedResidual inside a step; a stop closes the step
+    kRedNormQ = 2,      // qq = sum q^2, alpha = -gp / qq
+    kRedInitNormQ = 3,  // init: qq, alpha, qq_prev
+    kRedDotGH = 4,      // gh = sum g h
+    kRedDotGG = 5,      // gg = sum g g
+    kRedNormQCG = 6,    // plain CG: qq, alpha = delta / qq
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+template <typename T> void launch_fill(T *p, size_t n, T v, hipStream_t s);
+template <typename T> void launch_copy(T *dst, const T *src, size_t n, const DevState *st,
+                                       hipStream_t s);
+template <typename T> void launch_stage(const T *x, T *xs, const Geo &G, const DevState *st,
+                                        hipStream_t s);
+template <typename T>
+void launch_project(const T *xs, const Geo &G, const ProjAngle *ang, const T *y, int y_stride,
+                    T *out, int out_stride, int out_off, double *partials, unsigned *counter,
+                    DevState *st, int mode, scg_trace_entry *trace, hipStream_t s);
+template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
+template <typename T>
+void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,
+                        T *out2, const T *dotv, double *partials, unsigned *counter,
+                        DevState *st, int mode, hipStream_t s);
+template <typename T>
+void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
+               unsigned *counter, DevState *st, int mode, double *tv_dst, hipStream_t s);
+template <typename T>
+void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsigned *counter,
+                   DevState *st, scg_trace_entry *trace, hipStream_t stream);
+template <typename T>
+void launch_perturb(const T *x, const T *s, T *xh, const Geo &G, DevState *st,
+                    hipStream_t stream);
+template <typename T>
+void launch_p_update(const T *g, const T *z, T *p, const Geo &G, double *partials,
+                     unsigned *counter, DevState *st, int rule, int init,
+                     scg_trace_entry *trace, hipStream_t s);
+template <typename T>
+void launch_x_update(const T *xh, const T *p, T *x, const T *h, T *g, const Geo &G, DevState *st,
+                     int cg_mode, double *partials, unsigned *counter, hipStream_t s);
+template <typename T>
+void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
+                   const DevState *st, hipStream_t s);
+void launch_iter_begin(DevState *st, const int32_t *forced, scg_trace_entry *trace,
+                       int is_f32, hipStream_t s);
+
+}  // namespace scg
