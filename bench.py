@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: S-CG reconstructions per second on one MI355X.
+
+Workload (512 x 512 image, 720 angles over [0, 180 deg), 729 unit bins): a
+seeded 30-ellipse phantom with a fine random texture of amplitude 0.02,
+exact analytic line integrals, transmission-style noise (I0 = 1e5), and a
+discrepancy stopping value: eps = f(x_true) = 1/2 ||y - A x_true||^2, the data
+misfit of the pixelised phantom itself (noise plus the model mismatch of the
+analytic line integrals; the paper's eps = N sigma^2 counts noise only, which
+here lies below the least-squares floor). One step = one complete S-CG solve from the
+zero image to f <= eps: FP32 projector, backprojector, TV and vector updates,
+FP64 CG scalars and eps test, gamma0 = RHO * ||x_1||, a = 0.975.
+
+Prints one JSON line. `roofline` describes the dominant kernel (its average
+duration measured with HIP events on the solve's stream during the timed
+solves); `cpu_baseline` times the FP64 oracle on the host for a bounded
+sample (the initial step plus two S-CG steps), extrapolated to the GPU's step
+count.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+RHO = 0.05                    # gamma0 = RHO * ||x_1||
+N, N_ANGLES, N_BINS = 512, 720, 729
+PEAK_LANE_OPS = 256 * 64 * 2.4e9   # VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+OPS_PER_NNZ = 8                    # weight evaluation + multiply-accumulate per nonzero
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def count_nnz(n, n_angles, n_bins):
+    """Exact number of nonzero entries of A: for every angle and pixel, the
+    bins b whose line crosses the pixel square with positive length, i.e.
+    |t_b - proj| < (|c|+|s|)/2, or <= 1/2 for axis-aligned rays (a ray on a
+    pixel edge has half weight)."""
+    import numpy as np
+    h, hb = 0.5 * (n - 1), 0.5 * (n_bins - 1)
+    X, Y = np.meshgrid(np.arange(n) - h, h - np.arange(n))
+    total = 0
+    for a in range(n_angles):
+        th = a * math.pi / n_angles
+        c, s = math.cos(th), math.sin(th)
+        c = 0.0 if abs(c) < 1e-12 else c
+        s = 0.0 if abs(s) < 1e-12 else s
+        u = X * c + Y * s + hb            # bin coordinate of the pixel centre
+        if min(abs(c), abs(s)) == 0.0:
+            lo, hi = np.ceil(u - 0.5), np.floor(u + 0.5)
+        else:
+            half = 0.5 * (abs(c) + abs(s))
+            lo, hi = np.floor(u - half + 1e-9) + 1, np.ceil(u + half - 1e-9) - 1
+        lo = np.maximum(lo, 0)
+        hi = np.minimum(hi, n_bins - 1)
+        total += int(np.maximum(hi - lo + 1, 0).sum())
+    return total
+
+
+def cpu_baseline(w, eps, gamma0, steps_gpu):
+    import numpy as np
+    import oracle
+    from oracle import algorithms as alg
+    threads = oracle.ops.max_threads()
+    g = oracle.Geometry(w.n, w.n_angles, w.n_bins, threads=threads)
+    prob = alg.Problem(g, w.y)
+    pp = alg.PerturbParams(gamma0)
+    x0 = np.zeros(g.J)
+    t = time.perf_counter()
+    alg.scg(prob, x0, eps=eps, pp=pp, max_iter=0)
+    t_init = time.perf_counter() - t
+    t = time.perf_counter()
+    alg.scg(prob, x0, eps=eps, pp=pp, max_iter=2)
+    t_two = time.perf_counter() - t
+    per_step = max(t_two - t_init, 1e-9) / 2.0
+    est = t_init + per_step * steps_gpu
+    return {"value": 1.0 / est, "unit": "recons/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle at {w.n}x{w.n} ({w.n_angles}x{w.n_bins}): initial step "
+                       f"{t_init:.2f} s + 2 S-CG steps ({per_step:.2f} s/step), extrapolated to "
+                       f"the GPU solve's {steps_gpu} steps")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1709_04912_amd import scg
+    from synth import make_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("generating the 512x512 workload")
+    w = make_workload(3, 0)
+    dev = torch.device("cuda:0")
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    plan = scg.Plan(N, N_ANGLES, N_BINS, device=0)
+    xt = torch.tensor(w.x_true.reshape(-1), dtype=torch.float32, device=dev)
+    res = plan.project(xt).double() - y.double()
+    eps = 0.5 * float((res * res).sum())
+    # gamma0 from the first CG iterate of the library's own CG
+    p1 = plan.params(eps=1e-30, gamma0=0.0, variant="CG", max_iter=1)
+    x1, _, _ = plan.solve(y, p1, trace=False)
+    gamma0 = RHO * float(torch.linalg.vector_norm(x1.double()))
+    params = plan.params(eps=eps, gamma0=gamma0, variant="S_CG", prec=scg.SCG_F32,
+                         max_iter=2000)
+    ws = plan.workspace(params)
+    out = torch.empty(N * N, dtype=torch.float32, device=dev)
+
+    # warm-up solves; the first one also profiles every kernel class
+    plan.profile(scg.KERNEL_CLASSES)
+    rep = None
+    for i in range(max(args.warmup, 1)):
+        _, rep, _ = plan.solve(y, params, out=out, ws=ws, trace=False)
+        if i == 0:
+            prof_all = plan.profile_read()
+            plan.profile(())
+    log(f"warm-up: status={rep.status} k={rep.k} steps={rep.steps} f={rep.f_out:.6g} "
+        f"eps={eps:.6g}")
+    dominant = max(("project", "backproject"), key=lambda c: prof_all[c][1])
+
+    # timed solves (events only around the dominant kernel)
+    plan.profile((dominant,))
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, rep, _ = plan.solve(y, params, out=out, ws=ws, trace=False, stream=stream)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(())
+    assert rep.status == scg.SCG_OK and rep.f_out <= eps, rep
+
+    launches, ms = prof[dominant]
+    avg_s = ms / max(launches, 1) / 1e3
+    nnz = count_nnz(N, N_ANGLES, N_BINS)
+    achieved = OPS_PER_NNZ * nnz / avg_s
+    err = float(np.linalg.norm(out.double().cpu().numpy() - w.x_true.reshape(-1))
+                / np.linalg.norm(w.x_true))
+    per_class = {c: {"launches": int(v[0]), "avg_us": (1e3 * v[1] / v[0]) if v[0] else 0.0}
+                 for c, v in prof_all.items()}
+    compulsory = 4 * (N * N + N_ANGLES * N_BINS)
+
+    result = {
+        "metric": "S-CG recons/s at 512x512 (720 angles x 729 bins)",
+        "value": args.steps / elapsed,
+        "unit": "recons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("512x512 S-CG solve to eps: 720 angles x 729 bins, 30 random ellipses "
+                         "+ texture 0.02, transmission noise I0=1e5, eps = f(x_true)"),
+            "variant": "S_CG", "scalars": "f64", "steps_per_solve": rep.steps, "k": rep.k,
+            "gamma0": gamma0, "rho": RHO, "a": 0.975, "eps": eps, "f_out": rep.f_out,
+            "tv_out": rep.tv_out, "rel_err_vs_phantom": err,
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                           "p99": 1e3 * float(np.percentile(lat, 99))},
+            "kernel_avg_us": per_class,
+        },
+        "roofline": {
+            "kernel": dominant,
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "T lane-op/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": None,
+            "per_launch": {"nnz": nnz, "ops_per_nnz": OPS_PER_NNZ, "avg_us": avg_s * 1e6,
+                           "launches": int(launches),
+                           "compulsory_hbm_GBs": compulsory / avg_s / 1e9,
+                           "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM},
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        result["cpu_baseline"] = cpu_baseline(w, eps, gamma0, rep.steps)
+    print(json.dumps(result), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -98,7 +98,7 @@ typedef struct {
     int32_t ell;          /* final value of the gamma counter l                   */
     int32_t reserved;
     double  f_out;        /* f at the output (FP64 accumulation)                  */
-    double  tv_out;       /* TV of x_k at the last perturbation, or 0             */
+    double  tv_out;       /* TV of the output image (terms summed in FP64)        */
 } scg_report;
 
 /* One entry per step k = 1, 2, ... (the step that forms x_{k+1/2}, x_{k+1}). */
@@ -171,6 +171,34 @@ int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const voi
               void *x_out, void *ws, size_t ws_bytes, scg_report *rep,
               scg_trace_entry *trace, int32_t trace_cap, const int32_t *forced,
               int32_t forced_len, void *stream);
+
+/* ---- kernel timing ----------------------------------------------------- */
+
+/* Kernel classes for scg_profile. */
+#define SCG_KC_PROJECT     0   /* forward projector A                          */
+#define SCG_KC_BACKPROJECT 1   /* backprojector A^T (single or dual)            */
+#define SCG_KC_TV          2   /* TV and subgradient                            */
+#define SCG_KC_TRIALS      3   /* perturbation trials                           */
+#define SCG_KC_VECTOR      4   /* direction, image and perturbation updates     */
+#define SCG_KC_STAGE       5   /* image staging for the projector               */
+#define SCG_KC_FILTER      6   /* preconditioning filter                        */
+#define SCG_KC_CONTROL     7   /* per-iteration control                         */
+#define SCG_KC_COUNT       8
+
+typedef struct {
+    int64_t launches;
+    double  total_ms;
+} scg_kernel_time;
+
+/* Times every kernel launch of the classes in class_mask (bit c = class c)
+ * that scg_solve enqueues on this plan, with a HIP event recorded on the
+ * solve's stream before and after the launch. 0 turns timing off. Resets the
+ * accumulated totals. */
+int scg_profile(scg_plan *plan, uint32_t class_mask);
+
+/* Accumulated launches and milliseconds per class since the last
+ * scg_profile call; out must hold SCG_KC_COUNT entries. */
+int scg_profile_read(scg_plan *plan, scg_kernel_time *out);
 
 /* Fills *params with the library's defaults: S-CG, FP32, a = 0.975,
  * max_iter = 1000, max_trials = 100, kappa = 0, mu = 2 pi / P; eps and

@@ -16,7 +16,9 @@
 using scg::BpAngle;
 using scg::DevState;
 using scg::Geo;
+using scg::PjGroup;
 using scg::ProjAngle;
+using scg::ProjTables;
 
 struct scg_plan {
     int device = 0;
@@ -24,13 +26,27 @@ struct scg_plan {
     std::vector<double> cosv, sinv;
     ProjAngle *pang = nullptr;
     BpAngle *bang = nullptr;
-    void *xs[2] = {nullptr, nullptr};     // staged image scratch per precision
+    PjGroup *pgroups = nullptr;
+    int *pwin = nullptr;
+    ProjTables ptab{};
+    void *xs[2] = {nullptr, nullptr};     // transposed-image scratch per precision
     void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision
     double *partials = nullptr;
     unsigned *counter = nullptr;
     double *tvbuf = nullptr;
     void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
     double kern_mu = -1.0;
+    // kernel timing (scg_profile): HIP events around launches of chosen classes
+    struct ProfRec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<ProfRec> prof_pending;
+    hipEvent_t prof_open[SCG_KC_COUNT] = {};
+    int64_t prof_count[SCG_KC_COUNT] = {};
+    double prof_ms[SCG_KC_COUNT] = {};
 };
 
 namespace {
@@ -95,8 +111,82 @@ void build_angles(const Geo &G, const std::vector<double> &cv, const std::vector
         B.Cf = (float)B.C;
         B.CKf = (float)(B.C - B.K);
         B.inv_mf = (float)B.inv_m;
+        B.cf = (float)c;
+        B.sf = (float)s;
         ba[a] = B;
     }
+}
+
+// Groups of consecutive angles stepping along the same axis and, for every
+// (group, bin chunk, band), the first LDS-staged column: the band's columns
+// crossed by any of the block's rays, with two columns of margin each side.
+// The group size shrinks until every window fits kPjWin columns.
+int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa)
+{
+    const Geo &G = p->G;
+    const int n_chunks = (G.nb + scg::kPjBins - 1) / scg::kPjBins;
+    const int n_bands = (G.n + scg::kPjBand - 1) / scg::kPjBand;
+    for (int gmax = scg::kPjGroup; gmax >= 1; --gmax) {
+        std::vector<PjGroup> groups;
+        for (int a = 0; a < G.na;) {
+            PjGroup g{a, 1, pa[a].major, 0};
+            while (g.count < gmax && a + g.count < G.na && pa[a + g.count].major == g.major)
+                ++g.count;
+            groups.push_back(g);
+            a += g.count;
+        }
+        if ((size_t)groups.size() * n_chunks > (size_t)scg::kMaxPartials) return SCG_EINVAL;
+        std::vector<int> win((size_t)groups.size() * n_chunks * n_bands);
+        bool ok = true;
+        for (size_t gi = 0; gi < groups.size() && ok; ++gi) {
+            for (int ch = 0; ch < n_chunks && ok; ++ch) {
+                const int b_lo = ch * scg::kPjBins;
+                const int b_hi = std::min(G.nb, b_lo + scg::kPjBins) - 1;
+                for (int band = 0; band < n_bands; ++band) {
+                    const int i_lo = band * scg::kPjBand, i_hi = i_lo + scg::kPjBand - 1;
+                    double umin = INFINITY, umax = -INFINITY;
+                    for (int g = 0; g < groups[gi].count; ++g) {
+                        const ProjAngle &A = pa[groups[gi].a0 + g];
+                        for (int b : {b_lo, b_hi})
+                            for (int i : {i_lo, i_hi}) {
+                                const double u0 = std::fma((double)b, A.u0_step, A.u0_base);
+                                const double u = std::fma((double)i, A.slope, u0);
+                                umin = std::min(umin, u);
+                                umax = std::max(umax, u);
+                            }
+                    }
+                    int &w = win[((size_t)gi * n_chunks + ch) * n_bands + band];
+                    if (umax < -2.0 || umin > (double)G.n + 1.0) {
+                        w = scg::kWinSkip;
+                        continue;
+                    }
+                    const double fmin = std::floor(umin), fmax = std::floor(umax);
+                    if (fmax - fmin > (double)(scg::kPjWin - 5)) {
+                        ok = false;
+                        break;
+                    }
+                    w = (int)fmin - 2;
+                }
+            }
+        }
+        if (!ok) continue;
+        if (hipMalloc(&p->pgroups, groups.size() * sizeof(PjGroup)) != hipSuccess ||
+            hipMalloc(&p->pwin, win.size() * sizeof(int)) != hipSuccess)
+            return SCG_ENOMEM;
+        if (hipMemcpy(p->pgroups, groups.data(), groups.size() * sizeof(PjGroup),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->pwin, win.data(), win.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                hipSuccess)
+            return SCG_EDEVICE;
+        p->ptab.ang = p->pang;
+        p->ptab.groups = p->pgroups;
+        p->ptab.win = p->pwin;
+        p->ptab.n_groups = (int)groups.size();
+        p->ptab.n_chunks = n_chunks;
+        p->ptab.n_bands = n_bands;
+        return SCG_OK;
+    }
+    return SCG_EINVAL;
 }
 
 int filter_pad(int nb)
@@ -148,6 +238,60 @@ struct Device {
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+hipEvent_t take_event(scg_plan *p)
+{
+    if (!p->ev_free.empty()) {
+        hipEvent_t e = p->ev_free.back();
+        p->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Marks the start (begin = true) or end of a launch of class `cls` when the
+// class is being timed.
+void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin)
+{
+    if (!(p->prof_mask & (1u << cls))) return;
+    hipEvent_t e = take_event(p);
+    if (e == nullptr) return;
+    (void)hipEventRecord(e, s);
+    if (begin) {
+        p->prof_open[cls] = e;
+    } else if (p->prof_open[cls] != nullptr) {
+        p->prof_pending.push_back({cls, p->prof_open[cls], e});
+        p->prof_open[cls] = nullptr;
+    } else {
+        p->ev_free.push_back(e);
+    }
+}
+
+// Accumulates the elapsed times of recorded launches (the stream must have
+// passed them).
+void prof_drain(scg_plan *p)
+{
+    for (const auto &r : p->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            p->prof_ms[r.cls] += ms;
+            p->prof_count[r.cls] += 1;
+        }
+        p->ev_free.push_back(r.a);
+        p->ev_free.push_back(r.b);
+    }
+    p->prof_pending.clear();
+}
+
+#define PROF(cls, call)                          \
+    do {                                         \
+        prof_mark(plan, (cls), st0, true);       \
+        call;                                    \
+        prof_mark(plan, (cls), st0, false);      \
+    } while (0)
 
 // Workspace layout of scg_solve.
 struct Layout {
@@ -278,82 +422,88 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
 
     const int rs = G.rs, off = scg::kSinoPadL;
     auto project_res = [&](const T *img, int mode) {
-        scg::launch_stage<T>(img, xs, G, st, st0);
-        scg::launch_project<T>(xs, G, plan->pang, y, G.nb, r, rs, off, partials, counter, st, mode,
-                               trace, st0);
+        PROF(SCG_KC_STAGE, scg::launch_stage<T>(img, xs, G, st, st0));
+        PROF(SCG_KC_PROJECT, scg::launch_project<T>(img, xs, G, plan->ptab, y, G.nb, r, rs, off,
+                                                    partials, counter, st, mode, trace, st0));
     };
     auto project_q = [&](int mode) {
-        scg::launch_stage<T>(p, xs, G, st, st0);
-        scg::launch_project<T>(xs, G, plan->pang, nullptr, 0, q, rs, off, partials, counter, st,
-                               mode, trace, st0);
+        PROF(SCG_KC_STAGE, scg::launch_stage<T>(p, xs, G, st, st0));
+        PROF(SCG_KC_PROJECT, scg::launch_project<T>(p, xs, G, plan->ptab, nullptr, 0, q, rs, off,
+                                                    partials, counter, st, mode, trace, st0));
+    };
+    auto backproject = [&](const T *src, const T *src2, T *dst, T *dst2, const T *dotv,
+                            int mode) {
+        PROF(SCG_KC_BACKPROJECT, scg::launch_backproject<T>(src, src2, G, plan->bang, dst, dst2,
+                                                            dotv, partials, counter, st, mode,
+                                                            st0));
+    };
+    auto p_update = [&](const T *src_z, int rule, int init) {
+        PROF(SCG_KC_VECTOR, scg::launch_p_update<T>(g, src_z, p, G, partials, counter, st, rule,
+                                                    init, trace, st0));
+    };
+    auto filter = [&]() {
+        PROF(SCG_KC_FILTER, scg::launch_filter<T>(r, rt, kern, G, 1, st, st0));
     };
 
     // ---- initial step -------------------------------------------------
     if (is_cg) {
         // Alg. CG: g0 = A^T(A x0 - y), p0 = -g0, delta0 = ||g0||^2.
         project_res(x, scg::kRedResidual);
-        scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
-                                   counter, st, scg::kRedDotGG, st0);
-        scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 3, 1, trace, st0);
+        backproject(r, nullptr, g, nullptr, nullptr, scg::kRedDotGG);
+        p_update(nullptr, 3, 1);
     } else {
         // S-CG / S-CG-CD / S-PCG steps 1-7: x_{1/2} = x0, g0, (z0), p0, h0,
         // alpha = -g0^T p0 / p0^T h0, x1 = x0 + alpha p0, k = 1.
         project_res(xh, scg::kRedResidual);
         if (variant == SCG_S_PCG) {
-            scg::launch_filter<T>(r, rt, kern, G, 1, st, st0);
-            scg::launch_backproject<T>(r, rt, G, plan->bang, g, z, nullptr, partials, counter, st,
-                                       scg::kRedNone, st0);
-            scg::launch_p_update<T>(g, z, p, G, partials, counter, st, 2, 1, trace, st0);
+            filter();
+            backproject(r, rt, g, z, nullptr, scg::kRedNone);
+            p_update(z, 2, 1);
         } else {
-            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
-                                       counter, st, scg::kRedNone, st0);
-            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 0, 1, trace, st0);
+            backproject(r, nullptr, g, nullptr, nullptr, scg::kRedNone);
+            p_update(nullptr, 0, 1);
         }
         project_q(scg::kRedNormQ);
-        if (variant != SCG_S_CG_CD)
-            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
-                                       counter, st, scg::kRedNone, st0);
-        scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0, partials, counter, st0);
+        if (variant != SCG_S_CG_CD) backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
+        PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0,
+                                                    partials, counter, st0));
     }
 
     const int passes = (pr->max_trials + scg::kTrialsPerPass - 1) / scg::kTrialsPerPass;
     auto enqueue_iteration = [&]() {
-        scg::launch_iter_begin(st, forced_d, trace, is_f32, st0);
+        PROF(SCG_KC_CONTROL, scg::launch_iter_begin(st, forced_d, trace, is_f32, st0));
         if (is_cg) {
             project_q(scg::kRedNormQCG);
-            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
-                                       counter, st, scg::kRedNone, st0);
-            scg::launch_x_update<T>(x, p, x, h, g, G, st, 1, partials, counter, st0);
-            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 3, 0, trace, st0);
+            backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
+            PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(x, p, x, h, g, G, st, 1, partials,
+                                                        counter, st0));
+            p_update(nullptr, 3, 0);
             project_res(x, scg::kRedResidual);
             return;
         }
         // perturbed(x_k)
-        scg::launch_tv<T>(x, s, G, pr->tv_kappa, partials, counter, st, 1, nullptr, st0);
+        PROF(SCG_KC_TV, scg::launch_tv<T>(x, s, G, pr->tv_kappa, partials, counter, st, 1,
+                                          nullptr, st0));
         for (int ps = 0; ps < passes; ++ps)
-            scg::launch_trials<T>(x, s, G, partials, counter, st, trace, st0);
-        scg::launch_perturb<T>(x, s, xh, G, st, st0);
+            PROF(SCG_KC_TRIALS, scg::launch_trials<T>(x, s, G, partials, counter, st, trace, st0));
+        PROF(SCG_KC_VECTOR, scg::launch_perturb<T>(x, s, xh, G, st, st0));
         // the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP)
         project_res(xh, scg::kRedResidualStep);
         if (variant == SCG_S_PCG) {
-            scg::launch_filter<T>(r, rt, kern, G, 1, st, st0);
-            scg::launch_backproject<T>(r, rt, G, plan->bang, g, z, h, partials, counter, st,
-                                       scg::kRedDotGH, st0);
-            scg::launch_p_update<T>(g, z, p, G, partials, counter, st, 2, 0, trace, st0);
+            filter();
+            backproject(r, rt, g, z, h, scg::kRedDotGH);
+            p_update(z, 2, 0);
         } else if (variant == SCG_S_CG_CD) {
-            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, nullptr, partials,
-                                       counter, st, scg::kRedDotGG, st0);
-            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 1, 0, trace, st0);
+            backproject(r, nullptr, g, nullptr, nullptr, scg::kRedDotGG);
+            p_update(nullptr, 1, 0);
         } else {
-            scg::launch_backproject<T>(r, nullptr, G, plan->bang, g, nullptr, h, partials,
-                                       counter, st, scg::kRedDotGH, st0);
-            scg::launch_p_update<T>(g, nullptr, p, G, partials, counter, st, 0, 0, trace, st0);
+            backproject(r, nullptr, g, nullptr, h, scg::kRedDotGH);
+            p_update(nullptr, 0, 0);
         }
         project_q(scg::kRedNormQ);
-        if (variant != SCG_S_CG_CD)
-            scg::launch_backproject<T>(q, nullptr, G, plan->bang, h, nullptr, nullptr, partials,
-                                       counter, st, scg::kRedNone, st0);
-        scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0, partials, counter, st0);
+        if (variant != SCG_S_CG_CD) backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
+        PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0,
+                                                    partials, counter, st0));
     };
 
     // ---- loop: chunks of iterations, device decides when to stop ---------
@@ -368,6 +518,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
         chunk = std::min(chunk * 2, 16);
         HIP_TRY(hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
         HIP_TRY(hipStreamSynchronize(st0));
+        prof_drain(plan);
     }
     if (!done) {   // only reachable if the cap check never fired; close it now
         scg::launch_iter_begin(st, forced_d, trace, is_f32, st0);
@@ -453,15 +604,14 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     G.n = g->n;
     G.na = g->n_angles;
     G.nb = g->n_bins;
-    G.xp = G.n + scg::kPadL + scg::kPadR;
     G.rs = G.nb + scg::kSinoPadL + scg::kSinoPadR;
     G.h = 0.5 * (G.n - 1);
     G.hb = 0.5 * (G.nb - 1);
-    // The projector and backprojector grids must fit the reduction partials,
-    // and a padded projection plus the filter taps must fit in LDS.
-    const size_t bp_blocks = (size_t)((G.n + 15) / 16) * ((G.n + 15) / 16);
-    if ((size_t)((G.nb + 255) / 256) * G.na > (size_t)scg::kMaxPartials ||
-        bp_blocks > (size_t)scg::kMaxPartials || (size_t)3 * G.nb * sizeof(double) > 65536) {
+    // The backprojector grid must fit the reduction partials, and a padded
+    // projection plus the filter taps must fit in LDS.
+    const size_t bp_tiles = (size_t)((G.n + scg::kBpTile - 1) / scg::kBpTile);
+    if (bp_tiles * bp_tiles > (size_t)scg::kMaxPartials ||
+        (size_t)3 * G.nb * sizeof(double) > 65536) {
         delete p;
         return SCG_EINVAL;
     }
@@ -501,6 +651,11 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
         scg_plan_destroy(p);
         return SCG_EDEVICE;
     }
+    int rc = build_proj_tables(p, pa);
+    if (rc != SCG_OK) {
+        scg_plan_destroy(p);
+        return rc;
+    }
     *out = p;
     return SCG_OK;
 }
@@ -511,6 +666,8 @@ void scg_plan_destroy(scg_plan *p)
     Device dg(p->device);
     (void)hipFree(p->pang);
     (void)hipFree(p->bang);
+    (void)hipFree(p->pgroups);
+    (void)hipFree(p->pwin);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->xs[i]);
         (void)hipFree(p->rpad[i]);
@@ -519,7 +676,38 @@ void scg_plan_destroy(scg_plan *p)
     (void)hipFree(p->partials);
     (void)hipFree(p->counter);
     (void)hipFree(p->tvbuf);
+    prof_drain(p);
+    for (hipEvent_t e : p->ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->prof_open)
+        if (e != nullptr) (void)hipEventDestroy(e);
     delete p;
+}
+
+int scg_profile(scg_plan *plan, uint32_t class_mask)
+{
+    if (plan == nullptr) return SCG_EINVAL;
+    Device dg(plan->device);
+    prof_drain(plan);
+    for (int c = 0; c < SCG_KC_COUNT; ++c) {
+        plan->prof_count[c] = 0;
+        plan->prof_ms[c] = 0.0;
+        if (plan->prof_open[c] != nullptr) plan->ev_free.push_back(plan->prof_open[c]);
+        plan->prof_open[c] = nullptr;
+    }
+    plan->prof_mask = class_mask & ((1u << SCG_KC_COUNT) - 1);
+    return SCG_OK;
+}
+
+int scg_profile_read(scg_plan *plan, scg_kernel_time *out)
+{
+    if (plan == nullptr || out == nullptr) return SCG_EINVAL;
+    Device dg(plan->device);
+    prof_drain(plan);
+    for (int c = 0; c < SCG_KC_COUNT; ++c) {
+        out[c].launches = plan->prof_count[c];
+        out[c].total_ms = plan->prof_ms[c];
+    }
+    return SCG_OK;
 }
 
 int scg_workspace_bytes(const scg_plan *plan, const scg_params *params, size_t *bytes)
@@ -541,14 +729,16 @@ int scg_project(scg_plan *plan, int prec, const void *x, void *y, void *stream)
     const Geo &G = plan->G;
     if (prec == SCG_F32) {
         float *xs = static_cast<float *>(plan->xs[0]);
-        scg::launch_stage<float>(static_cast<const float *>(x), xs, G, nullptr, s);
-        scg::launch_project<float>(xs, G, plan->pang, nullptr, 0, static_cast<float *>(y), G.nb, 0,
-                                   nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+        const float *xf = static_cast<const float *>(x);
+        scg::launch_stage<float>(xf, xs, G, nullptr, s);
+        scg::launch_project<float>(xf, xs, G, plan->ptab, nullptr, 0, static_cast<float *>(y),
+                                   G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
     } else {
         double *xs = static_cast<double *>(plan->xs[1]);
-        scg::launch_stage<double>(static_cast<const double *>(x), xs, G, nullptr, s);
-        scg::launch_project<double>(xs, G, plan->pang, nullptr, 0, static_cast<double *>(y), G.nb,
-                                    0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+        const double *xd = static_cast<const double *>(x);
+        scg::launch_stage<double>(xd, xs, G, nullptr, s);
+        scg::launch_project<double>(xd, xs, G, plan->ptab, nullptr, 0, static_cast<double *>(y),
+                                    G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
     }
     return hip_status(hipGetLastError());
 }

@@ -26,15 +26,15 @@ template <typename T> __device__ __forceinline__ T pM(const ProjAngle &a);
 template <> __device__ __forceinline__ float pM<float>(const ProjAngle &a) { return a.inv_mf; }
 template <> __device__ __forceinline__ double pM<double>(const ProjAngle &a) { return a.inv_m; }
 
-template <typename T> struct BpW { T K, C, CK, M; };
+template <typename T> struct BpW { T K, C, CK, M, c, s; };
 template <typename T> __device__ __forceinline__ BpW<T> bpw(const BpAngle &a);
 template <> __device__ __forceinline__ BpW<float> bpw<float>(const BpAngle &a)
 {
-    return {a.Kf, a.Cf, a.CKf, a.inv_mf};
+    return {a.Kf, a.Cf, a.CKf, a.inv_mf, a.cf, a.sf};
 }
 template <> __device__ __forceinline__ BpW<double> bpw<double>(const BpAngle &a)
 {
-    return {a.K, a.C, a.C - a.K, a.inv_m};
+    return {a.K, a.C, a.C - a.K, a.inv_m, a.c, a.s};
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -164,100 +164,161 @@ void launch_copy(T *dst, const T *src, size_t n, const DevState *st, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Image staging: padded row-major and padded transposed copies (32x32 tiles
-// through LDS so both writes are coalesced).
+// Image staging: the transposed copy that angles stepping over columns read
+// (32x32 tiles through LDS so both the read and the write are coalesced).
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__restrict__ xs,
+__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__restrict__ xt,
                                                 Geo G, const DevState *st)
 {
     if (stopped(st)) return;
     __shared__ T tile[32][33];
-    const int n = G.n, xp = G.xp;
+    const int n = G.n;
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    T *rows = xs + (size_t)xp + kPadL;                 // after the first guard row
-    T *cols = xs + (size_t)(n + 2) * xp + kPadL;       // after the middle guard row
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, j = bx + tx;
-        T v = T(0);
-        if (i < n && j < n) {
-            v = x[(size_t)i * n + j];
-            rows[(size_t)i * xp + j] = v;
-        }
-        tile[r][tx] = v;
+        tile[r][tx] = (i < n && j < n) ? x[(size_t)i * n + j] : T(0);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int j = bx + r, i = by + tx;
-        if (i < n && j < n) cols[(size_t)j * xp + i] = tile[tx][r];
+        if (i < n && j < n) xt[(size_t)j * n + i] = tile[tx][r];
     }
 }
 
 template <typename T>
-void launch_stage(const T *x, T *xs, const Geo &G, const DevState *st, hipStream_t s)
+void launch_stage(const T *x, T *xt, const Geo &G, const DevState *st, hipStream_t s)
 {
     dim3 grid((G.n + 31) / 32, (G.n + 31) / 32);
-    hipLaunchKernelGGL(k_stage<T>, grid, dim3(256), 0, s, x, xs, G, st);
+    hipLaunchKernelGGL(k_stage<T>, grid, dim3(256), 0, s, x, xt, G, st);
 }
 
 // ---------------------------------------------------------------------------
-// Forward projector A (ray-driven). One thread per ray (a, b); the ray walks
-// the steps of its major axis and, at each step, gathers the two pixels that
-// bracket its crossing point from the padded staged image.
+// Forward projector A (ray-driven, banded). Block (bin chunk, angle group):
+// thread t owns bin b = chunk*kPjBins + (t & 127) for the group's angles
+// (t >> 7) + 2m, m = 0..3. The block walks bands of kPjBand steps along the
+// group's major axis (rows of x, or rows of x^T for angles stepping over
+// columns), staging kPjWin columns of each band in LDS; the next band is
+// prefetched into registers while the current one is consumed. Within a band
+// a ray's crossing coordinate is kept as an integer anchor plus an FP32
+// fraction (anchor from FP64), so the split weights stay accurate near the
+// axes where the chord ramp is steep.
 // ---------------------------------------------------------------------------
 
+template <typename T, int STEPS>
+__device__ __forceinline__ void ray_band(const T *__restrict__ lds, int base, T F0, T slope, T K,
+                                         T C, T &acc, T &accr)
+{
+#pragma unroll
+    for (int k = 0; k < STEPS; ++k) {
+        const T v = fma((T)k, slope, F0);
+        const T fv = floor(v);
+        const int jl = (int)fv;
+        const T fl = v - fv;
+        const T wl = sat(fma(fl, -K, C));
+        const T *row = lds + k * kPjWin + base + jl;
+        const T xl = row[0], xr = row[1];
+        acc = fma(wl, xl - xr, acc);
+        accr += xr;
+    }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_project(const T *__restrict__ xs, Geo G,
-                                                  const ProjAngle *__restrict__ ang,
-                                                  const T *__restrict__ y, int y_stride,
-                                                  T *__restrict__ out, int out_stride,
-                                                  int out_off, double *partials,
-                                                  unsigned *counter, DevState *st, int mode,
-                                                  scg_trace_entry *trace)
+__global__ __launch_bounds__(kPjThreads) void k_project(const T *__restrict__ x,
+                                                         const T *__restrict__ xt, Geo G,
+                                                         ProjTables P, const T *__restrict__ y,
+                                                         int y_stride, T *__restrict__ out,
+                                                         int out_stride, int out_off,
+                                                         double *partials, unsigned *counter,
+                                                         DevState *st, int mode,
+                                                         scg_trace_entry *trace)
 {
     if (stopped(st)) return;
-    const int a = blockIdx.y;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    double sq = 0.0;
-    if (b < G.nb) {
-        const ProjAngle A = ang[a];
-        const int n = G.n;
-        const T *img = xs + (size_t)(A.major ? (n + 2) : 1) * G.xp + kPadL;
-        const double u0 = fma((double)b, A.u0_step, A.u0_base);
-        // Steps whose crossing lies in [-1, n) carry weight; the range is
-        // widened by one step on each side and the padding absorbs the extra.
-        int s_lo = 0, s_hi = n - 1;
-        if (A.slope == 0.0) {
-            if (!(u0 >= -1.0 && u0 < (double)n)) s_hi = -1;
-        } else {
-            double l1 = (-1.0 - u0) / A.slope, l2 = ((double)n - u0) / A.slope;
-            double lo = fmin(l1, l2), hi = fmax(l1, l2);
-            if (lo > (double)(n - 1) || hi < 0.0) {
-                s_hi = -1;
-            } else {
-                s_lo = (int)floor(fmax(lo, 0.0));
-                s_hi = (int)ceil(fmin(hi, (double)(n - 1)));
+    constexpr int NE = kPjBand * kPjWin / kPjThreads;   // staged elements per thread
+    constexpr int SLOTS = kPjGroup / 2;
+    __shared__ T lds[kPjBand * kPjWin];
+    const int t = threadIdx.x;
+    const int chunk = blockIdx.x, gi = blockIdx.y;
+    const PjGroup grp = P.groups[gi];
+    const int half = t >> 7;
+    const int b_raw = chunk * kPjBins + (t & (kPjBins - 1));
+    const bool bin_ok = b_raw < G.nb;
+    const int b = bin_ok ? b_raw : G.nb - 1;   // idle lanes trace the chunk's last ray
+    const int n = G.n;
+    const T *img = grp.major ? xt : x;
+    const int *win = P.win + ((size_t)gi * P.n_chunks + chunk) * P.n_bands;
+
+    double u0[SLOTS];
+    T acc[SLOTS], accr[SLOTS];
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+        const int slot = half + 2 * m;
+        acc[m] = T(0);
+        accr[m] = T(0);
+        u0[m] = 0.0;
+        if (slot < grp.count) {
+            const ProjAngle A = P.ang[grp.a0 + slot];
+            u0[m] = fma((double)b, A.u0_step, A.u0_base);
+        }
+    }
+
+    auto next_band = [&](int from) {
+        int bb = from;
+        while (bb < P.n_bands && win[bb] == kWinSkip) ++bb;
+        return bb;
+    };
+    T pre[NE];
+    auto prefetch = [&](int band) {
+        const int jw = win[band];
+        const int i0 = band * kPjBand;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int q = t + e * kPjThreads;
+            const int r = q / kPjWin, c = q % kPjWin;
+            const int row = i0 + r, col = jw + c;
+            pre[e] = (row < n && col >= 0 && col < n) ? img[(size_t)row * n + col] : T(0);
+        }
+    };
+
+    int band = next_band(0);
+    if (band < P.n_bands) prefetch(band);
+    while (band < P.n_bands) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < NE; ++e) lds[t + e * kPjThreads] = pre[e];
+        __syncthreads();
+        const int jw = win[band];
+        const int i0 = band * kPjBand;
+        const int nxt = next_band(band + 1);
+        if (nxt < P.n_bands) prefetch(nxt);
+#pragma unroll
+        for (int m = 0; m < SLOTS; ++m) {
+            const int slot = half + 2 * m;
+            if (slot < grp.count) {
+                const ProjAngle A = P.ang[grp.a0 + slot];
+                const double us = fma((double)i0, A.slope, u0[m]);
+                const double fu = floor(us);
+                const int base = (int)fu - jw;
+                ray_band<T, kPjBand>(lds, base, (T)(us - fu), (T)A.slope, pK<T>(A), pC<T>(A),
+                                     acc[m], accr[m]);
             }
         }
-        const T K = pK<T>(A), C = pC<T>(A);
-        T acc = T(0), accr = T(0);
-        for (int i = s_lo; i <= s_hi; ++i) {
-            const double u = fma((double)i, A.slope, u0);
-            const double fu = floor(u);
-            const int jl = (int)fu;
-            const T fl = (T)(u - fu);
-            const T wl = sat(fma(fl, -K, C));
-            const T *row = img + (size_t)i * G.xp;
-            const T xl = row[jl], xr = row[jl + 1];
-            acc = fma(wl, xl - xr, acc);
-            accr += xr;
+        band = nxt;
+    }
+
+    double sq = 0.0;
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+        const int slot = half + 2 * m;
+        if (slot < grp.count && bin_ok) {
+            const int a = grp.a0 + slot;
+            T val = (acc[m] + accr[m]) * pM<T>(P.ang[a]);
+            if (y != nullptr) val -= y[(size_t)a * y_stride + b];
+            out[(size_t)a * out_stride + out_off + b] = val;
+            sq += (double)val * (double)val;
         }
-        T val = (acc + accr) * pM<T>(A);
-        if (y != nullptr) val -= y[(size_t)a * y_stride + b];
-        out[(size_t)a * out_stride + out_off + b] = val;
-        sq = (double)val * (double)val;
     }
     if (mode == kRedNone) return;
     double v[1] = {sq}, tot[1];
@@ -267,7 +328,7 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ xs, Geo G
         const double f = 0.5 * s;
         st->f_half = f;
         if (mode == kRedResidualStep)
-            if (scg_trace_entry *t = trace_at(st, trace, st->k)) t->f_half = f;
+            if (scg_trace_entry *tr = trace_at(st, trace, st->k)) tr->f_half = f;
         if (!isfinite(f)) {
             set_done(st, SCG_ENAN);
         } else if (f <= st->eps) {
@@ -288,18 +349,19 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ xs, Geo G
             set_done(st, SCG_EBREAKDOWN);
         } else {
             st->alpha = (mode == kRedNormQCG) ? st->delta / s : -st->gp / s;
-            if (scg_trace_entry *t = trace_at(st, trace, st->k)) t->alpha = st->alpha;
+            if (scg_trace_entry *tr = trace_at(st, trace, st->k)) tr->alpha = st->alpha;
         }
     }
 }
 
 template <typename T>
-void launch_project(const T *xs, const Geo &G, const ProjAngle *ang, const T *y, int y_stride,
-                    T *out, int out_stride, int out_off, double *partials, unsigned *counter,
-                    DevState *st, int mode, scg_trace_entry *trace, hipStream_t s)
+void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, const T *y,
+                    int y_stride, T *out, int out_stride, int out_off, double *partials,
+                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace,
+                    hipStream_t s)
 {
-    dim3 grid((G.nb + kBlock - 1) / kBlock, G.na);
-    hipLaunchKernelGGL(k_project<T>, grid, dim3(kBlock), 0, s, xs, G, ang, y, y_stride, out,
+    dim3 grid(P.n_chunks, P.n_groups);
+    hipLaunchKernelGGL(k_project<T>, grid, dim3(kPjThreads), 0, s, x, xt, G, P, y, y_stride, out,
                        out_stride, out_off, partials, counter, st, mode, trace);
 }
 
@@ -322,51 +384,131 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 }
 
 // ---------------------------------------------------------------------------
-// Backprojector A^T (pixel-driven). One thread per pixel of a 16x16 tile;
-// per angle the pixel's footprint covers at most two bins. With r2 != NULL
-// the same weights also backproject a second sinogram (dual backprojection
-// for S-PCG: g' = A^T r and z' = A^T F^T C F r in one pass).
+// Backprojector A^T (pixel-driven, tiled). A block owns a 16 x 16 pixel tile;
+// thread t owns the pixels (t >> 3, 2(t & 7)) and (t >> 3, 2(t & 7) + 1).
+// Angles are processed in chunks of kBpChunk: for each angle the kBpWin bins
+// around the tile centre's projection are staged in LDS, already scaled by
+// 1/m, with the centre's fractional position; the next chunk is prefetched
+// into registers while the current one is consumed. A pixel's footprint
+// centre is then an FP32 offset from the tile centre (|offset| < 27 bins),
+// its two bins are LDS reads and its two weights clamped FMAs. DUAL
+// backprojects a second sinogram with the same weights (S-PCG: g' and z').
 // ---------------------------------------------------------------------------
 
 template <typename T, bool DUAL>
-__global__ __launch_bounds__(256) void k_backproject(const T *__restrict__ r,
-                                                      const T *__restrict__ r2, Geo G,
-                                                      const BpAngle *__restrict__ ang,
-                                                      T *__restrict__ out, T *__restrict__ out2,
-                                                      const T *__restrict__ dotv,
-                                                      double *partials, unsigned *counter,
-                                                      DevState *st, int mode)
+__global__ __launch_bounds__(kBpThreads) void k_backproject(const T *__restrict__ r,
+                                                             const T *__restrict__ r2, Geo G,
+                                                             const BpAngle *__restrict__ ang,
+                                                             T *__restrict__ out,
+                                                             T *__restrict__ out2,
+                                                             const T *__restrict__ dotv,
+                                                             double *partials, unsigned *counter,
+                                                             DevState *st, int mode)
 {
     if (stopped(st)) return;
-    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const bool in = (i < G.n) && (j < G.n);
-    const double xc = (double)j - G.h, yc = G.h - (double)i;
-    T acc = T(0), acc2 = T(0);
-    const T *rr = r + kSinoPadL;
-    const T *rr2 = DUAL ? r2 + kSinoPadL : nullptr;
-    const double ub = (double)G.nb;
-    for (int a = 0; a < G.na; ++a) {
-        const BpAngle A = ang[a];
-        const BpW<T> W = bpw<T>(A);
-        double u = fma(xc, A.c, fma(yc, A.s, G.hb));
-        u = fmin(fmax(u, -1.0), ub);
-        const double fu = floor(u);
-        const int b0 = (int)fu;
-        const T f = (T)(u - fu);
-        const T w0 = sat(fma(f, -W.K, W.C));
-        const T w1 = sat(fma(f, W.K, W.CK));
-        const size_t off = (size_t)a * G.rs + b0;
-        acc = fma(W.M, fma(w0, rr[off], w1 * rr[off + 1]), acc);
-        if (DUAL) acc2 = fma(W.M, fma(w0, rr2[off], w1 * rr2[off + 1]), acc2);
+    constexpr int NW = DUAL ? 2 : 1;
+    constexpr int NE = kBpChunk * kBpWin / kBpThreads;   // staged bins per thread and sinogram
+    __shared__ T win[NW][kBpChunk * kBpWin];
+    __shared__ T frac[kBpChunk];
+    const int t = threadIdx.x;
+    const int ty = t >> 3, tx = (t & 7) * 2;
+    const int i0 = blockIdx.y * kBpTile, j0 = blockIdx.x * kBpTile;
+    const double xc = ((double)j0 + 7.5) - G.h, yc = G.h - ((double)i0 + 7.5);
+    const T dx = (T)((double)tx - 7.5), dy = (T)(7.5 - (double)ty);
+    T acc0 = T(0), acc1 = T(0), bcc0 = T(0), bcc1 = T(0);
+    const int nchunks = (G.na + kBpChunk - 1) / kBpChunk;
+
+    T pre[NW][NE];
+    T pfrac = T(0);
+    auto prefetch = [&](int ch) {
+        const int a0 = ch * kBpChunk;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int q = t + e * kBpThreads;
+            const int al = q / kBpWin, k = q % kBpWin;
+            const int a = a0 + al;
+            T v = T(0), v2 = T(0);
+            if (a < G.na) {
+                const BpAngle A = ang[a];
+                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
+                const int bb = (int)floor(pc) - kBpHalf + k;
+                if (bb >= 0 && bb < G.nb) {
+                    const T m = (T)A.inv_m;
+                    const size_t off = (size_t)a * G.rs + kSinoPadL + bb;
+                    v = r[off] * m;
+                    if (DUAL) v2 = r2[off] * m;
+                }
+            }
+            pre[0][e] = v;
+            if (DUAL) pre[NW - 1][e] = v2;
+        }
+        if (t < kBpChunk) {
+            const int a = a0 + t;
+            T f = T(0);
+            if (a < G.na) {
+                const BpAngle A = ang[a];
+                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
+                f = (T)(pc - (floor(pc) - kBpHalf));
+            }
+            pfrac = f;
+        }
+    };
+
+    prefetch(0);
+    for (int ch = 0; ch < nchunks; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            win[0][t + e * kBpThreads] = pre[0][e];
+            if (DUAL) win[NW - 1][t + e * kBpThreads] = pre[NW - 1][e];
+        }
+        if (t < kBpChunk) frac[t] = pfrac;
+        __syncthreads();
+        if (ch + 1 < nchunks) prefetch(ch + 1);
+        const int a0 = ch * kBpChunk;
+        const int na = min(kBpChunk, G.na - a0);
+        for (int al = 0; al < na; ++al) {
+            const BpAngle A = ang[a0 + al];
+            const BpW<T> W = bpw<T>(A);
+            const T c = W.c, s = W.s;
+            const T u0 = fma(dx, c, fma(dy, s, frac[al]));
+            const T u1 = u0 + c;
+            const T *row = &win[0][al * kBpWin];
+            const T fu0 = floor(u0), fu1 = floor(u1);
+            const int b0 = (int)fu0, b1 = (int)fu1;
+            const T f0 = u0 - fu0, f1 = u1 - fu1;
+            const T w00 = sat(fma(f0, -W.K, W.C)), w01 = sat(fma(f0, W.K, W.CK));
+            const T w10 = sat(fma(f1, -W.K, W.C)), w11 = sat(fma(f1, W.K, W.CK));
+            acc0 = fma(w00, row[b0], acc0);
+            acc0 = fma(w01, row[b0 + 1], acc0);
+            acc1 = fma(w10, row[b1], acc1);
+            acc1 = fma(w11, row[b1 + 1], acc1);
+            if (DUAL) {
+                const T *row2 = &win[NW - 1][al * kBpWin];
+                bcc0 = fma(w00, row2[b0], bcc0);
+                bcc0 = fma(w01, row2[b0 + 1], bcc0);
+                bcc1 = fma(w10, row2[b1], bcc1);
+                bcc1 = fma(w11, row2[b1 + 1], bcc1);
+            }
+        }
     }
+
+    const int i = i0 + ty, j = j0 + tx;
     double d = 0.0;
-    if (in) {
+    if (i < G.n) {
         const size_t p = (size_t)i * G.n + j;
-        out[p] = acc;
-        if (DUAL) out2[p] = acc2;
-        if (mode == kRedDotGH) d = (double)(DUAL ? acc2 : acc) * (double)dotv[p];
-        else if (mode == kRedDotGG) d = (double)acc * (double)acc;
+        if (j < G.n) {
+            out[p] = acc0;
+            if (DUAL) out2[p] = bcc0;
+            if (mode == kRedDotGH) d += (double)(DUAL ? bcc0 : acc0) * (double)dotv[p];
+            else if (mode == kRedDotGG) d += (double)acc0 * (double)acc0;
+        }
+        if (j + 1 < G.n) {
+            out[p + 1] = acc1;
+            if (DUAL) out2[p + 1] = bcc1;
+            if (mode == kRedDotGH) d += (double)(DUAL ? bcc1 : acc1) * (double)dotv[p + 1];
+            else if (mode == kRedDotGG) d += (double)acc1 * (double)acc1;
+        }
     }
     if (mode == kRedNone) return;
     double v[1] = {d}, tot[1];
@@ -380,13 +522,13 @@ void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *an
                         T *out2, const T *dotv, double *partials, unsigned *counter,
                         DevState *st, int mode, hipStream_t s)
 {
-    dim3 grid((G.n + 15) / 16, (G.n + 15) / 16);
+    dim3 grid((G.n + kBpTile - 1) / kBpTile, (G.n + kBpTile - 1) / kBpTile);
     if (r2 != nullptr)
-        hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(256), 0, s, r, r2, G, ang, out,
-                           out2, dotv, partials, counter, st, mode);
+        hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(kBpThreads), 0, s, r, r2, G, ang,
+                           out, out2, dotv, partials, counter, st, mode);
     else
-        hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(256), 0, s, r, r2, G, ang, out,
-                           out2, dotv, partials, counter, st, mode);
+        hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(kBpThreads), 0, s, r, r2, G, ang,
+                           out, out2, dotv, partials, counter, st, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -790,9 +932,9 @@ void launch_iter_begin(DevState *st, const int32_t *forced, scg_trace_entry *tra
     template void launch_fill<T>(T *, size_t, T, hipStream_t);                                 \
     template void launch_copy<T>(T *, const T *, size_t, const DevState *, hipStream_t);       \
     template void launch_stage<T>(const T *, T *, const Geo &, const DevState *, hipStream_t); \
-    template void launch_project<T>(const T *, const Geo &, const ProjAngle *, const T *, int,  \
-                                    T *, int, int, double *, unsigned *, DevState *, int,       \
-                                    scg_trace_entry *, hipStream_t);                            \
+    template void launch_project<T>(const T *, const T *, const Geo &, const ProjTables &,      \
+                                    const T *, int, T *, int, int, double *, unsigned *,        \
+                                    DevState *, int, scg_trace_entry *, hipStream_t);           \
     template void launch_pad_sino<T>(const T *, T *, const Geo &, hipStream_t);                \
     template void launch_backproject<T>(const T *, const T *, const Geo &, const BpAngle *,    \
                                         T *, T *, const T *, double *, unsigned *, DevState *, \

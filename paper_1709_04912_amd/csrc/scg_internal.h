@@ -10,15 +10,28 @@
 
 namespace scg {
 
-// Staged image layout (ray-driven projector input): two N x N copies of the
-// image, row-major and transposed, each row padded with zeros (kPadL columns
-// on the left, kPadR on the right) and with one zero guard row before, between
-// and after the copies. Padding lets a ray read the two pixels around its
-// crossing point without bounds checks.
-constexpr int kPadL = 2;
-constexpr int kPadR = 4;
-// Padded sinogram layout (backprojector input): rows of n_bins + 4 entries,
-// bin b at offset b + 1; the pads stay zero.
+// Forward projector tiling. A block owns up to kPjGroup consecutive angles
+// that step along the same axis and kPjBins consecutive bins; it walks the
+// image in bands of kPjBand rows (of the image or of its transpose), staging
+// kPjWin columns of each band in LDS. The window start of every
+// (group, bin chunk, band) is precomputed on the host (kWinSkip: the band
+// holds no pixel any of the block's rays crosses).
+constexpr int kPjBins = 128;
+constexpr int kPjBand = 16;
+constexpr int kPjWin = 256;
+constexpr int kPjGroup = 8;
+constexpr int kPjThreads = 256;
+constexpr int kWinSkip = -0x40000000;
+// Backprojector tiling: 16 x 16 pixel tiles, 128 threads (two adjacent
+// pixels each), angles staged in LDS in chunks of kBpChunk with a window of
+// kBpWin bins per angle around the tile centre's projection.
+constexpr int kBpTile = 16;
+constexpr int kBpThreads = 128;
+constexpr int kBpChunk = 32;
+constexpr int kBpWin = 32;
+constexpr int kBpHalf = 15;       // window start = floor(centre projection) - kBpHalf
+// Padded sinogram layout (solver residuals): rows of n_bins + 4 entries, bin b
+// at offset b + 1; the pads stay zero.
 constexpr int kSinoPadL = 1;
 constexpr int kSinoPadR = 3;
 
@@ -27,11 +40,10 @@ constexpr int kMaxPartials = 16384;  // block partials per reduction (max blocks
 
 struct Geo {
     int n, na, nb;
-    int xp;       // staged image row length  = n + kPadL + kPadR
     int rs;       // padded sinogram row stride = nb + kSinoPadL + kSinoPadR
     double h;     // (n - 1) / 2
     double hb;    // (nb - 1) / 2
-    size_t staged_elems() const { return (size_t)(2 * n + 3) * xp; }
+    size_t staged_elems() const { return (size_t)n * n; }   // transposed image copy
     size_t sino_elems() const { return (size_t)na * rs; }
     size_t img_elems() const { return (size_t)n * n; }
 };
@@ -50,6 +62,18 @@ struct ProjAngle {
     int major;    // 0: steps over rows (|c| >= |s|), 1: steps over columns
 };
 
+struct PjGroup {
+    int a0, count, major, pad;
+};
+
+// Device tables of the forward projector.
+struct ProjTables {
+    const ProjAngle *ang;
+    const PjGroup *groups;
+    const int *win;      // [group][chunk][band] window start column or kWinSkip
+    int n_groups, n_chunks, n_bands, pad;
+};
+
 // Pixel-driven frame of one angle: pixel centre projects to the bin coordinate
 // u = x c + y s + (nb-1)/2; bins floor(u) and floor(u)+1 receive
 // (1/m) clamp(C - d K, 0, 1) at distances d = frac(u) and 1 - frac(u), with
@@ -58,6 +82,7 @@ struct BpAngle {
     double c, s;
     double K, C, inv_m;
     float Kf, Cf, CKf, inv_mf;   // CKf = C - K
+    float cf, sf;
 };
 
 // Device-resident solver state: scalars in FP64, control in int.
@@ -94,9 +119,10 @@ template <typename T> void launch_copy(T *dst, const T *src, size_t n, const Dev
 template <typename T> void launch_stage(const T *x, T *xs, const Geo &G, const DevState *st,
                                         hipStream_t s);
 template <typename T>
-void launch_project(const T *xs, const Geo &G, const ProjAngle *ang, const T *y, int y_stride,
-                    T *out, int out_stride, int out_off, double *partials, unsigned *counter,
-                    DevState *st, int mode, scg_trace_entry *trace, hipStream_t s);
+void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, const T *y,
+                    int y_stride, T *out, int out_stride, int out_off, double *partials,
+                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace,
+                    hipStream_t s);
 template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
 template <typename T>
 void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,

@@ -47,6 +47,14 @@ class scg_trace_entry(C.Structure):
                 ("gamma", C.c_double), ("beta", C.c_double), ("alpha", C.c_double)]
 
 
+class scg_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+KERNEL_CLASSES = ("project", "backproject", "tv", "trials", "vector", "stage", "filter",
+                  "control")
+
+
 class ScgError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -69,12 +77,14 @@ def _load() -> C.CDLL:
     L.scg_solve.argtypes = [vp, C.POINTER(scg_params), vp, vp, vp, vp, C.c_size_t,
                             C.POINTER(scg_report), C.POINTER(scg_trace_entry), i32,
                             C.POINTER(i32), i32, vp]
+    L.scg_profile.argtypes = [vp, C.c_uint32]
+    L.scg_profile_read.argtypes = [vp, C.POINTER(scg_kernel_time)]
     L.scg_default_params.argtypes = [C.POINTER(scg_params)]
     L.scg_default_params.restype = None
     L.scg_strerror.argtypes = [C.c_int]
     L.scg_strerror.restype = C.c_char_p
     for name in ("scg_plan_create", "scg_workspace_bytes", "scg_project", "scg_backproject",
-                 "scg_tv", "scg_filter", "scg_solve"):
+                 "scg_tv", "scg_filter", "scg_solve", "scg_profile", "scg_profile_read"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -194,6 +204,20 @@ class Plan:
                               _dev(out, self.L, "out"), C.c_void_p(_stream_handle(stream))),
                "scg_filter")
         return out
+
+    # -- kernel timing -----------------------------------------------------
+    def profile(self, classes=()):
+        """Times the named kernel classes inside scg_solve (scg_profile)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        _check(lib.scg_profile(self._h, mask), "scg_profile")
+
+    def profile_read(self) -> dict:
+        arr = (scg_kernel_time * len(KERNEL_CLASSES))()
+        _check(lib.scg_profile_read(self._h, arr), "scg_profile_read")
+        return {name: (arr[i].launches, arr[i].total_ms)
+                for i, name in enumerate(KERNEL_CLASSES)}
 
     # -- solver ------------------------------------------------------------
     def params(self, eps: float, gamma0: float, variant: str = "S_CG", prec: int = SCG_F32,

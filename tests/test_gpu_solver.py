@@ -108,15 +108,26 @@ def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
 
 
 def test_cg_parity(scg, torch_mod, oracle_lib):
+    """Plain CG (recursive gradient, CG-STEP) amplifies rounding: on this
+    workload perturbing y by 1e-15 (relative) moves the oracle's own 26-step
+    output by 2e-4, while 10 steps stay within 1e-12 - which is why the
+    perturbation-resilient step recomputes the gradient. So CG is compared
+    tightly at 10 steps and, at the stop, by k, the eps test and 1e-3."""
     torch = torch_mod
     w, g, prob, eps, gamma0 = _case(oracle_lib, 0)
-    ref = alg.cg(prob, np.zeros(g.J), eps=eps, max_iter=1000)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        ref10 = alg.cg(prob, np.zeros(g.J), eps=1e-6 * eps, max_iter=10)
+        p = plan.params(eps=1e-6 * eps, gamma0=0.0, variant="CG", prec=scg.SCG_F64, max_iter=10)
+        x, rep, _ = plan.solve(y, p, trace=False)
+        assert rep.status == scg.SCG_ENOCONV and rep.k == 10
+        assert _rel(x.cpu().numpy(), ref10.x) <= 1e-9
+        ref = alg.cg(prob, np.zeros(g.J), eps=eps, max_iter=1000)
         p = plan.params(eps=eps, gamma0=0.0, variant="CG", prec=scg.SCG_F64)
         x, rep, _ = plan.solve(y, p, trace=False)
     assert rep.status == scg.SCG_OK and rep.k == ref.k
-    assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
+    assert rep.f_out <= eps and prob.f(x.cpu().numpy()) <= eps
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-3
 
 
 def test_superiorized_tv_below_cg(scg, torch_mod, oracle_lib):
@@ -157,11 +168,18 @@ def test_edge_cases(scg, torch_mod, oracle_lib):
         ybad[5] = float("nan")
         x, rep, _ = plan.solve(ybad, plan.params(eps=eps, gamma0=gamma0))
         assert rep.status == scg.SCG_ENAN
-        # no perturbation flag: S-CG reproduces CG's iterate count
-        _, rcg, _ = plan.solve(y, plan.params(eps=eps, gamma0=0.0, variant="CG"), trace=False)
-        _, rnp, _ = plan.solve(y, plan.params(eps=eps, gamma0=gamma0,
-                                              flags=scg.SCG_FLAG_NO_PERTURB), trace=False)
-        assert rnp.k - 1 == rcg.k
+        # no-perturbation flag: the unperturbed step sequence of the oracle.
+        # Unperturbed, the iteration is CG and as sensitive to rounding as CG
+        # (a 1e-15 change of y moves the oracle's 27-step output by 7e-4),
+        # so the iterates are compared after 10 steps.
+        ref = alg.scg(prob, np.zeros(g.J), eps=1e-6 * eps, pp=alg.PerturbParams(0.0),
+                      max_iter=10)
+        y64 = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
+        xnp, rnp, _ = plan.solve(y64, plan.params(eps=1e-6 * eps, gamma0=gamma0,
+                                                  prec=scg.SCG_F64, max_iter=10,
+                                                  flags=scg.SCG_FLAG_NO_PERTURB), trace=False)
+        assert rnp.k == ref.k and rnp.trials_total == 0 and rnp.status == scg.SCG_ENOCONV
+        assert _rel(xnp.cpu().numpy(), ref.x) <= 1e-9
 
 
 def test_solver_deterministic(scg, torch_mod, oracle_lib):
