@@ -154,13 +154,15 @@ def main():
     plan.profile(())
     assert rep.status == scg.SCG_OK and rep.f_out <= eps, rep
 
-    launches, ms = prof[dominant]
+    launches, ms, tail_launches, tail_ms = prof[dominant]
     avg_s = ms / max(launches, 1) / 1e3
     nnz = count_nnz(N, N_ANGLES, N_BINS)
     achieved = OPS_PER_NNZ * nnz / avg_s
     err = float(np.linalg.norm(out.double().cpu().numpy() - w.x_true.reshape(-1))
                 / np.linalg.norm(w.x_true))
-    per_class = {c: {"launches": int(v[0]), "avg_us": (1e3 * v[1] / v[0]) if v[0] else 0.0}
+    per_class = {c: {"launches": int(v[0]), "avg_us": (1e3 * v[1] / v[0]) if v[0] else 0.0,
+                     "tail_launches": int(v[2]),
+                     "tail_avg_us": (1e3 * v[3] / v[2]) if v[2] else 0.0}
                  for c, v in prof_all.items()}
     compulsory = 4 * (N * N + N_ANGLES * N_BINS)
 
@@ -196,7 +198,7 @@ def main():
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": None,
             "per_launch": {"nnz": nnz, "ops_per_nnz": OPS_PER_NNZ, "avg_us": avg_s * 1e6,
-                           "launches": int(launches),
+                           "launches": int(launches), "tail_launches": int(tail_launches),
                            "compulsory_hbm_GBs": compulsory / avg_s / 1e9,
                            "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM},
         },

@@ -172,6 +172,32 @@ int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const voi
               scg_trace_entry *trace, int32_t trace_cap, const int32_t *forced,
               int32_t forced_len, void *stream);
 
+/* ---- launch shapes ----------------------------------------------------- */
+
+/* Launch shapes of the two operators; results do not depend on them beyond
+ * FP rounding order (the backprojector's angle split adds the groups' partial
+ * sums in a fixed order, so each choice is itself deterministic). */
+typedef struct {
+    int32_t project_groups;     /* 2 or 4: angle groups of 128 rays per projector block
+                                   (256 or 512 threads)                               */
+    int32_t backproject_split;  /* 1, 2 or 4: angle split inside each 16 x 16 pixel tile
+                                   (128, 256 or 512 threads)                          */
+} scg_tuning;
+
+/* Current shapes for precision prec (defaults: 4 and 2). */
+int scg_plan_get_tuning(const scg_plan *plan, int prec, scg_tuning *out);
+
+/* Sets the shapes used by every later call on the plan for precision prec.
+ * SCG_EINVAL for values other than the ones listed above. */
+int scg_plan_set_tuning(scg_plan *plan, int prec, const scg_tuning *in);
+
+/* Times A and A^T once per candidate shape on the plan's geometry (ones as
+ * input, HIP events on `stream`, 5 launches each after one untimed launch),
+ * keeps the fastest for precision prec and writes it to *chosen (may be
+ * NULL). Allocates and frees one image and one sinogram of scratch;
+ * synchronises the stream. */
+int scg_plan_autotune(scg_plan *plan, int prec, void *stream, scg_tuning *chosen);
+
 /* ---- kernel timing ----------------------------------------------------- */
 
 /* Kernel classes for scg_profile. */
@@ -186,8 +212,11 @@ int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const voi
 #define SCG_KC_COUNT       8
 
 typedef struct {
-    int64_t launches;
-    double  total_ms;
+    int64_t launches;       /* launches that did their work                  */
+    double  total_ms;       /* their summed event-to-event time              */
+    int64_t tail_launches;  /* launches enqueued after the solve had stopped  */
+    double  tail_ms;        /* (the last batch of iterations ran past the stop
+                               and its kernels returned at once)              */
 } scg_kernel_time;
 
 /* Times every kernel launch of the classes in class_mask (bit c = class c)

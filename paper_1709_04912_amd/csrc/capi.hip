@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <climits>
 #include <vector>
 
 #include "scg_internal.h"
@@ -35,18 +36,23 @@ struct scg_plan {
     unsigned *counter = nullptr;
     double *tvbuf = nullptr;
     void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
+    scg_tuning tune[2] = {{4, 2}, {4, 2}};  // launch shapes per precision
     double kern_mu = -1.0;
     // kernel timing (scg_profile): HIP events around launches of chosen classes
     struct ProfRec {
         int cls;
+        int iter;   // loop iteration that enqueued the launch (0: initial step)
         hipEvent_t a, b;
     };
     uint32_t prof_mask = 0;
+    int prof_iter = 0;
     std::vector<hipEvent_t> ev_free;
     std::vector<ProfRec> prof_pending;
     hipEvent_t prof_open[SCG_KC_COUNT] = {};
     int64_t prof_count[SCG_KC_COUNT] = {};
     double prof_ms[SCG_KC_COUNT] = {};
+    int64_t prof_tail_count[SCG_KC_COUNT] = {};
+    double prof_tail_ms[SCG_KC_COUNT] = {};
 };
 
 namespace {
@@ -262,23 +268,31 @@ void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin)
     if (begin) {
         p->prof_open[cls] = e;
     } else if (p->prof_open[cls] != nullptr) {
-        p->prof_pending.push_back({cls, p->prof_open[cls], e});
+        p->prof_pending.push_back({cls, p->prof_iter, p->prof_open[cls], e});
         p->prof_open[cls] = nullptr;
     } else {
         p->ev_free.push_back(e);
     }
 }
 
-// Accumulates the elapsed times of recorded launches (the stream must have
-// passed them).
-void prof_drain(scg_plan *p)
+// Accumulates the elapsed times of recorded launches. Launches enqueued by
+// loop iterations past `last_iter` (the solve had already stopped; their
+// kernels returned at once) are kept apart, except the TV kernel of the
+// iteration after it, which still closes the last step.
+void prof_drain(scg_plan *p, int last_iter = INT_MAX)
 {
     for (const auto &r : p->prof_pending) {
         float ms = 0.0f;
         if (hipEventSynchronize(r.b) == hipSuccess &&
             hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-            p->prof_ms[r.cls] += ms;
-            p->prof_count[r.cls] += 1;
+            const int lim = last_iter == INT_MAX ? INT_MAX : last_iter + (r.cls == SCG_KC_TV);
+            if (r.iter <= lim) {
+                p->prof_ms[r.cls] += ms;
+                p->prof_count[r.cls] += 1;
+            } else {
+                p->prof_tail_ms[r.cls] += ms;
+                p->prof_tail_count[r.cls] += 1;
+            }
         }
         p->ev_free.push_back(r.a);
         p->ev_free.push_back(r.b);
@@ -295,7 +309,7 @@ void prof_drain(scg_plan *p)
 
 // Workspace layout of scg_solve.
 struct Layout {
-    size_t x, xh, p, g, h, s, z, r, q, rt, xs, partials, counter, state, forced, trace, tv,
+    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, counter, state, forced, trace, tv,
         total;
 };
 
@@ -320,8 +334,9 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
     L.q = take(S * esz);
     L.rt = take(S * esz);
     L.xs = take(G.staged_elems() * esz);
+    L.pt = take(G.staged_elems() * esz);
     L.partials = take(scg::kMaxPartials * sizeof(double));
-    L.counter = take(64);
+    L.counter = take(scg::kCounterBytes);
     L.state = take(sizeof(DevState));
     L.forced = take((size_t)2 * (max_iter + 1) * sizeof(int32_t));
     L.trace = take((size_t)(max_iter + 1) * sizeof(scg_trace_entry));
@@ -366,7 +381,8 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     T *r = reinterpret_cast<T *>(ws + Lw.r);
     T *q = reinterpret_cast<T *>(ws + Lw.q);
     T *rt = reinterpret_cast<T *>(ws + Lw.rt);
-    T *xs = reinterpret_cast<T *>(ws + Lw.xs);
+    T *xs = reinterpret_cast<T *>(ws + Lw.xs);   // transpose of x_{k+1/2} (or of x in CG)
+    T *pt = reinterpret_cast<T *>(ws + Lw.pt);   // transpose of p
     double *partials = reinterpret_cast<double *>(ws + Lw.partials);
     unsigned *counter = reinterpret_cast<unsigned *>(ws + Lw.counter);
     DevState *st = reinterpret_cast<DevState *>(ws + Lw.state);
@@ -390,7 +406,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     scg::launch_fill<T>(q, S, T(0), st0);
     scg::launch_fill<T>(rt, S, T(0), st0);
     scg::launch_fill<T>(xs, G.staged_elems(), T(0), st0);
-    HIP_TRY(hipMemsetAsync(counter, 0, 64, st0));
+    HIP_TRY(hipMemsetAsync(counter, 0, scg::kCounterBytes, st0));
 
     DevState hs{};
     hs.eps = pr->eps;
@@ -404,6 +420,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     hs.k = 0;
     hs.steps = is_cg ? 0 : -1;   // the initial step of the S- variants is not counted
     hs.accepted = -1;
+    hs.is_f32 = sizeof(T) == 4 ? 1 : 0;
     hs.trace_cap = std::min<int32_t>(trace_cap > 0 ? trace_cap : 0, pr->max_iter + 1);
     if (trace_host == nullptr) hs.trace_cap = pr->max_iter + 1;
     const int nf = forced_host ? std::min<int32_t>(std::max<int32_t>(forced_len, 0), pr->max_iter + 1) : 0;
@@ -413,7 +430,6 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
         HIP_TRY(hipMemcpyAsync(forced, forced_host, (size_t)2 * nf * sizeof(int32_t),
                                hipMemcpyHostToDevice, st0));
     const int32_t *forced_d = nf > 0 ? forced : nullptr;
-    const int is_f32 = sizeof(T) == 4;
 
     // x_{1/2} = x0 (S- variants) or x_0 (CG).
     T *x_start = is_cg ? x : xh;
@@ -421,25 +437,29 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     else scg::launch_fill<T>(x_start, J, T(0), st0);
 
     const int rs = G.rs, off = scg::kSinoPadL;
+    const scg_tuning tn = plan->tune[prec_index<T>()];
+    // Forward projections read an image and its transpose: x_{k+1/2} with
+    // xs (written by the perturbation), p with pt (written by the direction
+    // update); x0 and the CG iterate are transposed explicitly.
     auto project_res = [&](const T *img, int mode) {
-        PROF(SCG_KC_STAGE, scg::launch_stage<T>(img, xs, G, st, st0));
         PROF(SCG_KC_PROJECT, scg::launch_project<T>(img, xs, G, plan->ptab, y, G.nb, r, rs, off,
-                                                    partials, counter, st, mode, trace, st0));
+                                                    partials, counter, st, mode, trace, tn.project_groups,
+                                                    st0));
     };
     auto project_q = [&](int mode) {
-        PROF(SCG_KC_STAGE, scg::launch_stage<T>(p, xs, G, st, st0));
-        PROF(SCG_KC_PROJECT, scg::launch_project<T>(p, xs, G, plan->ptab, nullptr, 0, q, rs, off,
-                                                    partials, counter, st, mode, trace, st0));
+        PROF(SCG_KC_PROJECT, scg::launch_project<T>(p, pt, G, plan->ptab, nullptr, 0, q, rs, off,
+                                                    partials, counter, st, mode, trace,
+                                                    tn.project_groups, st0));
     };
     auto backproject = [&](const T *src, const T *src2, T *dst, T *dst2, const T *dotv,
                             int mode) {
         PROF(SCG_KC_BACKPROJECT, scg::launch_backproject<T>(src, src2, G, plan->bang, dst, dst2,
                                                             dotv, partials, counter, st, mode,
-                                                            st0));
+                                                            tn.backproject_split, st0));
     };
     auto p_update = [&](const T *src_z, int rule, int init) {
-        PROF(SCG_KC_VECTOR, scg::launch_p_update<T>(g, src_z, p, G, partials, counter, st, rule,
-                                                    init, trace, st0));
+        PROF(SCG_KC_VECTOR, scg::launch_p_update<T>(g, src_z, p, pt, G, partials, counter, st,
+                                                    rule, init, trace, st0));
     };
     auto filter = [&]() {
         PROF(SCG_KC_FILTER, scg::launch_filter<T>(r, rt, kern, G, 1, st, st0));
@@ -448,12 +468,15 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     // ---- initial step -------------------------------------------------
     if (is_cg) {
         // Alg. CG: g0 = A^T(A x0 - y), p0 = -g0, delta0 = ||g0||^2.
+        PROF(SCG_KC_STAGE, scg::launch_stage<T>(x, xs, G, st, st0));
         project_res(x, scg::kRedResidual);
         backproject(r, nullptr, g, nullptr, nullptr, scg::kRedDotGG);
         p_update(nullptr, 3, 1);
     } else {
-        // S-CG / S-CG-CD / S-PCG steps 1-7: x_{1/2} = x0, g0, (z0), p0, h0,
-        // alpha = -g0^T p0 / p0^T h0, x1 = x0 + alpha p0, k = 1.
+        // S-CG / S-CG-CD / S-PCG steps 1-6: x_{1/2} = x0, g0, (z0), p0, h0,
+        // alpha = -g0^T p0 / p0^T h0. x1 = x0 + alpha p0 and k = 1 are formed
+        // by the first loop kernel, which closes every step.
+        PROF(SCG_KC_STAGE, scg::launch_stage<T>(xh, xs, G, st, st0));
         project_res(xh, scg::kRedResidual);
         if (variant == SCG_S_PCG) {
             filter();
@@ -465,29 +488,29 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
         }
         project_q(scg::kRedNormQ);
         if (variant != SCG_S_CG_CD) backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
-        PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0,
-                                                    partials, counter, st0));
     }
 
     const int passes = (pr->max_trials + scg::kTrialsPerPass - 1) / scg::kTrialsPerPass;
     auto enqueue_iteration = [&]() {
-        PROF(SCG_KC_CONTROL, scg::launch_iter_begin(st, forced_d, trace, is_f32, st0));
         if (is_cg) {
+            PROF(SCG_KC_CONTROL, scg::launch_iter_begin(st, st0));
             project_q(scg::kRedNormQCG);
             backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
-            PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(x, p, x, h, g, G, st, 1, partials,
-                                                        counter, st0));
+            PROF(SCG_KC_VECTOR, scg::launch_x_update_cg<T>(x, p, h, g, G, st, partials, counter,
+                                                           st0));
             p_update(nullptr, 3, 0);
+            PROF(SCG_KC_STAGE, scg::launch_stage<T>(x, xs, G, st, st0));
             project_res(x, scg::kRedResidual);
             return;
         }
-        // perturbed(x_k)
-        PROF(SCG_KC_TV, scg::launch_tv<T>(x, s, G, pr->tv_kappa, partials, counter, st, 1,
-                                          nullptr, st0));
+        // close the previous step (x_{k+1} = x_{k+1/2} + alpha p) and start
+        // perturbed(x_k): TV subgradient, then the trials
+        PROF(SCG_KC_TV, scg::launch_xtv<T>(xh, p, x, s, G, partials, counter, st, forced_d, trace,
+                                           st0));
         for (int ps = 0; ps < passes; ++ps)
             PROF(SCG_KC_TRIALS, scg::launch_trials<T>(x, s, G, partials, counter, st, trace, st0));
-        PROF(SCG_KC_VECTOR, scg::launch_perturb<T>(x, s, xh, G, st, st0));
-        // the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP)
+        PROF(SCG_KC_VECTOR, scg::launch_perturb<T>(x, s, xh, xs, G, st, st0));
+        // the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP) from x_{k+1/2}
         project_res(xh, scg::kRedResidualStep);
         if (variant == SCG_S_PCG) {
             filter();
@@ -502,8 +525,6 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
         }
         project_q(scg::kRedNormQ);
         if (variant != SCG_S_CG_CD) backproject(q, nullptr, h, nullptr, nullptr, scg::kRedNone);
-        PROF(SCG_KC_VECTOR, scg::launch_x_update<T>(xh, p, x, nullptr, nullptr, G, st, 0,
-                                                    partials, counter, st0));
     };
 
     // ---- loop: chunks of iterations, device decides when to stop ---------
@@ -513,21 +534,21 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
     HIP_TRY(hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
     HIP_TRY(hipStreamSynchronize(st0));
     while (!done && issued <= (long)pr->max_iter) {
-        for (int c = 0; c < chunk; ++c) enqueue_iteration();
+        for (int c = 0; c < chunk; ++c) {
+            plan->prof_iter = (int)std::min<long>(issued + c + 1, INT_MAX - 1);
+            enqueue_iteration();
+        }
         issued += chunk;
         chunk = std::min(chunk * 2, 16);
         HIP_TRY(hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
         HIP_TRY(hipStreamSynchronize(st0));
-        prof_drain(plan);
     }
-    if (!done) {   // only reachable if the cap check never fired; close it now
-        scg::launch_iter_begin(st, forced_d, trace, is_f32, st0);
-    }
+    plan->prof_iter = INT_MAX;
 
     // ---- output ---------------------------------------------------------
     const T *out = is_cg ? x : xh;
     scg::launch_copy<T>(xout, out, J, nullptr, st0);
-    scg::launch_tv<T>(out, nullptr, G, pr->tv_kappa, partials, counter, nullptr, 0, tvd, st0);
+    scg::launch_tv<T>(out, nullptr, G, pr->tv_kappa, partials, counter, tvd, st0);
     DevState fs{};
     double tv_out = 0.0;
     HIP_TRY(hipMemcpyAsync(&fs, st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
@@ -538,6 +559,8 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
                                hipMemcpyDeviceToHost, st0));
     }
     HIP_TRY(hipStreamSynchronize(st0));
+    prof_drain(plan, std::max(fs.steps, 0));
+    plan->prof_iter = 0;
     if (rep != nullptr) {
         std::memset(rep, 0, sizeof(*rep));
         rep->status = fs.done ? fs.status : SCG_ENOCONV;
@@ -549,6 +572,88 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y_, const void 
         rep->tv_out = tv_out;
     }
     return fs.done ? fs.status : SCG_ENOCONV;
+}
+
+}  // namespace
+
+namespace {
+
+bool tuning_valid(const scg_tuning &t)
+{
+    return (t.project_groups == 2 || t.project_groups == 4) &&
+           (t.backproject_split == 1 || t.backproject_split == 2 ||
+            t.backproject_split == 4);
+}
+
+// Mean time of `reps` launches of `fn` on stream s, after one untimed launch.
+template <typename F> float time_launches(F fn, hipStream_t s, int reps)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    float ms = -1.0f;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) goto out;
+    fn();
+    if (hipEventRecord(a, s) != hipSuccess) goto out;
+    for (int i = 0; i < reps; ++i) fn();
+    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        ms = -1.0f;
+    else
+        ms /= (float)reps;
+out:
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return ms;
+}
+
+template <typename T>
+int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
+{
+    const Geo &G = plan->G;
+    const int pi = prec_index<T>();
+    T *x = nullptr, *y = nullptr;
+    if (hipMalloc(&x, G.img_elems() * sizeof(T)) != hipSuccess) return SCG_ENOMEM;
+    if (hipMalloc(&y, G.sino_elems() * sizeof(T)) != hipSuccess) {
+        (void)hipFree(x);
+        return SCG_ENOMEM;
+    }
+    scg::launch_fill<T>(x, G.img_elems(), T(1), s);
+    scg::launch_fill<T>(y, G.sino_elems(), T(1), s);
+    T *xs = static_cast<T *>(plan->xs[pi]);
+    scg::launch_stage<T>(x, xs, G, nullptr, s);
+    constexpr int kReps = 5;
+    scg_tuning best = plan->tune[pi];
+    float best_pj = -1.0f, best_bp = -1.0f;
+    for (int nq : {2, 4}) {
+        const float ms = time_launches(
+            [&] {
+                scg::launch_project<T>(x, xs, G, plan->ptab, nullptr, 0, y, G.rs, scg::kSinoPadL,
+                                       nullptr, nullptr, nullptr, scg::kRedNone, nullptr, nq, s);
+            },
+            s, kReps);
+        if (ms > 0.0f && (best_pj < 0.0f || ms < best_pj)) {
+            best_pj = ms;
+            best.project_groups = nq;
+        }
+    }
+    for (int sp : {1, 2, 4}) {
+        const float ms = time_launches(
+            [&] {
+                scg::launch_backproject<T>(y, nullptr, G, plan->bang, x, nullptr, nullptr, nullptr,
+                                           nullptr, nullptr, scg::kRedNone, sp, s);
+            },
+            s, kReps);
+        if (ms > 0.0f && (best_bp < 0.0f || ms < best_bp)) {
+            best_bp = ms;
+            best.backproject_split = sp;
+        }
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    if (e != hipSuccess || best_pj < 0.0f || best_bp < 0.0f) return SCG_EDEVICE;
+    plan->tune[pi] = best;
+    if (chosen != nullptr) *chosen = best;
+    return SCG_OK;
 }
 
 }  // namespace
@@ -632,7 +737,7 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
               hipMalloc(&p->rpad[0], G.sino_elems() * sizeof(float)) == hipSuccess &&
               hipMalloc(&p->rpad[1], G.sino_elems() * sizeof(double)) == hipSuccess &&
               hipMalloc(&p->partials, scg::kMaxPartials * sizeof(double)) == hipSuccess &&
-              hipMalloc(&p->counter, 64) == hipSuccess &&
+              hipMalloc(&p->counter, scg::kCounterBytes) == hipSuccess &&
               hipMalloc(&p->tvbuf, sizeof(double)) == hipSuccess;
     if (!ok) {
         scg_plan_destroy(p);
@@ -646,7 +751,7 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
          hipMemset(p->xs[1], 0, G.staged_elems() * sizeof(double)) == hipSuccess &&
          hipMemset(p->rpad[0], 0, G.sino_elems() * sizeof(float)) == hipSuccess &&
          hipMemset(p->rpad[1], 0, G.sino_elems() * sizeof(double)) == hipSuccess &&
-         hipMemset(p->counter, 0, 64) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+         hipMemset(p->counter, 0, scg::kCounterBytes) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         scg_plan_destroy(p);
         return SCG_EDEVICE;
@@ -691,6 +796,8 @@ int scg_profile(scg_plan *plan, uint32_t class_mask)
     for (int c = 0; c < SCG_KC_COUNT; ++c) {
         plan->prof_count[c] = 0;
         plan->prof_ms[c] = 0.0;
+        plan->prof_tail_count[c] = 0;
+        plan->prof_tail_ms[c] = 0.0;
         if (plan->prof_open[c] != nullptr) plan->ev_free.push_back(plan->prof_open[c]);
         plan->prof_open[c] = nullptr;
     }
@@ -706,6 +813,8 @@ int scg_profile_read(scg_plan *plan, scg_kernel_time *out)
     for (int c = 0; c < SCG_KC_COUNT; ++c) {
         out[c].launches = plan->prof_count[c];
         out[c].total_ms = plan->prof_ms[c];
+        out[c].tail_launches = plan->prof_tail_count[c];
+        out[c].tail_ms = plan->prof_tail_ms[c];
     }
     return SCG_OK;
 }
@@ -732,13 +841,15 @@ int scg_project(scg_plan *plan, int prec, const void *x, void *y, void *stream)
         const float *xf = static_cast<const float *>(x);
         scg::launch_stage<float>(xf, xs, G, nullptr, s);
         scg::launch_project<float>(xf, xs, G, plan->ptab, nullptr, 0, static_cast<float *>(y),
-                                   G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+                                   G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr,
+                                   plan->tune[0].project_groups, s);
     } else {
         double *xs = static_cast<double *>(plan->xs[1]);
         const double *xd = static_cast<const double *>(x);
         scg::launch_stage<double>(xd, xs, G, nullptr, s);
         scg::launch_project<double>(xd, xs, G, plan->ptab, nullptr, 0, static_cast<double *>(y),
-                                    G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr, s);
+                                    G.nb, 0, nullptr, nullptr, nullptr, scg::kRedNone, nullptr,
+                                    plan->tune[1].project_groups, s);
     }
     return hip_status(hipGetLastError());
 }
@@ -754,15 +865,42 @@ int scg_backproject(scg_plan *plan, int prec, const void *y, void *x, void *stre
         float *rp = static_cast<float *>(plan->rpad[0]);
         scg::launch_pad_sino<float>(static_cast<const float *>(y), rp, G, s);
         scg::launch_backproject<float>(rp, nullptr, G, plan->bang, static_cast<float *>(x), nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, scg::kRedNone, s);
+                                       nullptr, nullptr, nullptr, nullptr, scg::kRedNone,
+                                       plan->tune[0].backproject_split, s);
     } else {
         double *rp = static_cast<double *>(plan->rpad[1]);
         scg::launch_pad_sino<double>(static_cast<const double *>(y), rp, G, s);
         scg::launch_backproject<double>(rp, nullptr, G, plan->bang, static_cast<double *>(x),
                                         nullptr, nullptr, nullptr, nullptr, nullptr, scg::kRedNone,
-                                        s);
+                                        plan->tune[1].backproject_split, s);
     }
     return hip_status(hipGetLastError());
+}
+
+int scg_plan_get_tuning(const scg_plan *plan, int prec, scg_tuning *out)
+{
+    if (plan == nullptr || out == nullptr || (prec != SCG_F32 && prec != SCG_F64))
+        return SCG_EINVAL;
+    *out = plan->tune[prec == SCG_F32 ? 0 : 1];
+    return SCG_OK;
+}
+
+int scg_plan_set_tuning(scg_plan *plan, int prec, const scg_tuning *in)
+{
+    if (plan == nullptr || in == nullptr || (prec != SCG_F32 && prec != SCG_F64) ||
+        !tuning_valid(*in))
+        return SCG_EINVAL;
+    plan->tune[prec == SCG_F32 ? 0 : 1] = *in;
+    return SCG_OK;
+}
+
+int scg_plan_autotune(scg_plan *plan, int prec, void *stream, scg_tuning *chosen)
+{
+    if (plan == nullptr || (prec != SCG_F32 && prec != SCG_F64)) return SCG_EINVAL;
+    Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return prec == SCG_F32 ? autotune_impl<float>(plan, s, chosen)
+                           : autotune_impl<double>(plan, s, chosen);
 }
 
 int scg_tv(scg_plan *plan, int prec, const void *x, double kappa, void *s_out, double *tv_host,
@@ -776,10 +914,10 @@ int scg_tv(scg_plan *plan, int prec, const void *x, double kappa, void *s_out, d
     const Geo &G = plan->G;
     if (prec == SCG_F32)
         scg::launch_tv<float>(static_cast<const float *>(x), static_cast<float *>(s_out), G, kappa,
-                              plan->partials, plan->counter, nullptr, 0, plan->tvbuf, s);
+                              plan->partials, plan->counter, plan->tvbuf, s);
     else
         scg::launch_tv<double>(static_cast<const double *>(x), static_cast<double *>(s_out), G,
-                               kappa, plan->partials, plan->counter, nullptr, 0, plan->tvbuf, s);
+                               kappa, plan->partials, plan->counter, plan->tvbuf, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(tv_host, plan->tvbuf, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

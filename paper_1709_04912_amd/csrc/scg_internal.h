@@ -37,6 +37,9 @@ constexpr int kSinoPadR = 3;
 
 constexpr int kTrialsPerPass = 16;   // TV trials evaluated per pass of perturbed()
 constexpr int kMaxPartials = 16384;  // block partials per reduction (max blocks x values)
+constexpr int kRedGroups = 32;       // first-level arrival counters of a reduction
+constexpr int kRedStride = 64;       // counters are 256 bytes apart
+constexpr int kCounterBytes = (kRedGroups + 1) * kRedStride * 4;
 
 struct Geo {
     int n, na, nb;
@@ -99,6 +102,8 @@ struct DevState {
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
     double tv_out;
+    double gam[16];     // gamma0 a^(l+m), m < kTrialsPerPass, for the next trial pass
+    int is_f32, pad1;
 };
 
 enum RedMode : int {
@@ -121,33 +126,36 @@ template <typename T> void launch_stage(const T *x, T *xs, const Geo &G, const D
 template <typename T>
 void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, const T *y,
                     int y_stride, T *out, int out_stride, int out_off, double *partials,
-                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace,
+                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace, int nq,
                     hipStream_t s);
 template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
 template <typename T>
 void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,
                         T *out2, const T *dotv, double *partials, unsigned *counter,
-                        DevState *st, int mode, hipStream_t s);
+                        DevState *st, int mode, int split, hipStream_t s);
 template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
-               unsigned *counter, DevState *st, int mode, double *tv_dst, hipStream_t s);
+               unsigned *counter, double *tv_dst, hipStream_t s);
+template <typename T>
+void launch_xtv(const T *xh, const T *p, T *x, T *s_out, const Geo &G, double *partials,
+                unsigned *counter, DevState *st, const int32_t *forced, scg_trace_entry *trace,
+                hipStream_t s);
 template <typename T>
 void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsigned *counter,
                    DevState *st, scg_trace_entry *trace, hipStream_t stream);
 template <typename T>
-void launch_perturb(const T *x, const T *s, T *xh, const Geo &G, DevState *st,
+void launch_perturb(const T *x, const T *s, T *xh, T *xht, const Geo &G, DevState *st,
                     hipStream_t stream);
 template <typename T>
-void launch_p_update(const T *g, const T *z, T *p, const Geo &G, double *partials,
+void launch_p_update(const T *g, const T *z, T *p, T *pt, const Geo &G, double *partials,
                      unsigned *counter, DevState *st, int rule, int init,
                      scg_trace_entry *trace, hipStream_t s);
 template <typename T>
-void launch_x_update(const T *xh, const T *p, T *x, const T *h, T *g, const Geo &G, DevState *st,
-                     int cg_mode, double *partials, unsigned *counter, hipStream_t s);
+void launch_x_update_cg(T *x, const T *p, const T *h, T *g, const Geo &G, DevState *st,
+                        double *partials, unsigned *counter, hipStream_t s);
 template <typename T>
 void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
                    const DevState *st, hipStream_t s);
-void launch_iter_begin(DevState *st, const int32_t *forced, scg_trace_entry *trace,
-                       int is_f32, hipStream_t s);
+void launch_iter_begin(DevState *st, hipStream_t s);
 
 }  // namespace scg

@@ -48,7 +48,12 @@ class scg_trace_entry(C.Structure):
 
 
 class scg_kernel_time(C.Structure):
-    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double)]
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double),
+                ("tail_launches", C.c_int64), ("tail_ms", C.c_double)]
+
+
+class scg_tuning(C.Structure):
+    _fields_ = [("project_groups", C.c_int32), ("backproject_split", C.c_int32)]
 
 
 KERNEL_CLASSES = ("project", "backproject", "tv", "trials", "vector", "stage", "filter",
@@ -79,12 +84,16 @@ def _load() -> C.CDLL:
                             C.POINTER(i32), i32, vp]
     L.scg_profile.argtypes = [vp, C.c_uint32]
     L.scg_profile_read.argtypes = [vp, C.POINTER(scg_kernel_time)]
+    L.scg_plan_get_tuning.argtypes = [vp, C.c_int, C.POINTER(scg_tuning)]
+    L.scg_plan_set_tuning.argtypes = [vp, C.c_int, C.POINTER(scg_tuning)]
+    L.scg_plan_autotune.argtypes = [vp, C.c_int, vp, C.POINTER(scg_tuning)]
     L.scg_default_params.argtypes = [C.POINTER(scg_params)]
     L.scg_default_params.restype = None
     L.scg_strerror.argtypes = [C.c_int]
     L.scg_strerror.restype = C.c_char_p
     for name in ("scg_plan_create", "scg_workspace_bytes", "scg_project", "scg_backproject",
-                 "scg_tv", "scg_filter", "scg_solve", "scg_profile", "scg_profile_read"):
+                 "scg_tv", "scg_filter", "scg_solve", "scg_profile", "scg_profile_read",
+                 "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -205,6 +214,24 @@ class Plan:
                "scg_filter")
         return out
 
+    # -- launch shapes -----------------------------------------------------
+    def tuning(self, prec: int = SCG_F32) -> dict:
+        t = scg_tuning()
+        _check(lib.scg_plan_get_tuning(self._h, prec, C.byref(t)), "scg_plan_get_tuning")
+        return {"project_groups": t.project_groups, "backproject_split": t.backproject_split}
+
+    def set_tuning(self, prec: int = SCG_F32, project_groups: int = 4,
+                   backproject_split: int = 2):
+        t = scg_tuning(project_groups, backproject_split)
+        _check(lib.scg_plan_set_tuning(self._h, prec, C.byref(t)), "scg_plan_set_tuning")
+
+    def autotune(self, prec: int = SCG_F32, stream=None) -> dict:
+        """Times every launch shape of A and A^T and keeps the fastest."""
+        t = scg_tuning()
+        _check(lib.scg_plan_autotune(self._h, prec, C.c_void_p(_stream_handle(stream)),
+                                     C.byref(t)), "scg_plan_autotune")
+        return {"project_groups": t.project_groups, "backproject_split": t.backproject_split}
+
     # -- kernel timing -----------------------------------------------------
     def profile(self, classes=()):
         """Times the named kernel classes inside scg_solve (scg_profile)."""
@@ -214,9 +241,11 @@ class Plan:
         _check(lib.scg_profile(self._h, mask), "scg_profile")
 
     def profile_read(self) -> dict:
+        """Per class: (launches, total_ms, tail_launches, tail_ms); the tail
+        launches were enqueued after the solve had stopped and did no work."""
         arr = (scg_kernel_time * len(KERNEL_CLASSES))()
         _check(lib.scg_profile_read(self._h, arr), "scg_profile_read")
-        return {name: (arr[i].launches, arr[i].total_ms)
+        return {name: (arr[i].launches, arr[i].total_ms, arr[i].tail_launches, arr[i].tail_ms)
                 for i, name in enumerate(KERNEL_CLASSES)}
 
     # -- solver ------------------------------------------------------------

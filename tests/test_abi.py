@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every function include/scg.h declares
+(no GPU needed: only host-side entry points are called)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "scg.h")
+LIB = os.path.join(ROOT, "paper_1709_04912_amd", "libscg.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(scg_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libscg.so is not built: run __graft_entry__.build()")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for required in ("scg_plan_create", "scg_plan_destroy", "scg_workspace_bytes",
+                     "scg_project", "scg_backproject", "scg_tv", "scg_filter", "scg_solve",
+                     "scg_profile", "scg_profile_read", "scg_default_params", "scg_strerror",
+                     "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune"):
+        assert required in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_symbol_exported(lib, name):
+    assert hasattr(lib, name), name
+
+
+def test_host_only_entry_points(lib):
+    lib.scg_strerror.restype = C.c_char_p
+    lib.scg_strerror.argtypes = [C.c_int]
+    assert lib.scg_strerror(0) and lib.scg_strerror(-1) != lib.scg_strerror(0)
+    # null plans are rejected before any device call
+    vp = C.c_void_p
+    lib.scg_project.argtypes = [vp, C.c_int, vp, vp, vp]
+    assert lib.scg_project(None, 0, None, None, None) == -1
+    lib.scg_plan_get_tuning.argtypes = [vp, C.c_int, vp]
+    assert lib.scg_plan_get_tuning(None, 0, None) == -1

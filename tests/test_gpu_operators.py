@@ -167,3 +167,44 @@ def test_errors(scg, torch_mod):
         with pytest.raises(scg.ScgError) as e:
             plan.workspace_bytes(p)
         assert e.value.status == scg.SCG_EINVAL
+
+
+SHAPES = [(pg, bs) for pg in (2, 4) for bs in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("geom", [(33, 45, 49), (128, 180, 183), (100, 13, 200)])
+def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
+    """Every projector group count and backprojector angle split gives the
+    oracle's A and A^T (FP32 1e-5, FP64 1e-12, dual A^T of S-PCG included via
+    the solver tests) and is bitwise repeatable."""
+    torch = torch_mod
+    n, na, nb = geom
+    pg, bs = shape
+    print(f"[op shapes] geom={geom} project_groups={pg} backproject_split={bs}", flush=True)
+    g = oracle_lib.Geometry(n, na, nb)
+    x, y = _inputs(geom, 3 * n + nb, "uniform")
+    ax_ref, aty_ref = g.project(x), g.backproject(y)
+    with scg.Plan(n, na, nb) as plan:
+        for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
+                              (scg.SCG_F64, torch.float64, 1e-12)):
+            plan.set_tuning(prec, project_groups=pg, backproject_split=bs)
+            assert plan.tuning(prec) == {"project_groups": pg, "backproject_split": bs}
+            xd = torch.tensor(x, dtype=dt, device="cuda")
+            yd = torch.tensor(y, dtype=dt, device="cuda")
+            ax, aty = plan.project(xd), plan.backproject(yd)
+            assert _rel(ax.cpu().numpy(), ax_ref) <= tol
+            assert _rel(aty.cpu().numpy(), aty_ref) <= tol
+            assert torch.equal(ax, plan.project(xd)) and torch.equal(aty, plan.backproject(yd))
+
+
+def test_autotune_and_bad_shapes(scg, torch_mod):
+    torch = torch_mod
+    with scg.Plan(64, 90, 95) as plan:
+        for prec in (scg.SCG_F32, scg.SCG_F64):
+            t = plan.autotune(prec)
+            assert t["project_groups"] in (2, 4) and t["backproject_split"] in (1, 2, 4)
+            assert plan.tuning(prec) == t
+        for bad in ((3, 2), (4, 3), (0, 1)):
+            with pytest.raises(scg.ScgError):
+                plan.set_tuning(scg.SCG_F32, *bad)
