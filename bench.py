@@ -98,8 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path "
+              "(one solve runs on one device)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -115,6 +115,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     plan = scg.Plan(N, N_ANGLES, N_BINS, device=0)
+    tuning = plan.autotune(scg.SCG_F32)
+    log(f"launch shapes: {tuning}")
     xt = torch.tensor(w.x_true.reshape(-1), dtype=torch.float32, device=dev)
     res = plan.project(xt).double() - y.double()
     eps = 0.5 * float((res * res).sum())
@@ -183,6 +185,7 @@ def main():
             "workload": ("512x512 S-CG solve to eps: 720 angles x 729 bins, 30 random ellipses "
                          "+ texture 0.02, transmission noise I0=1e5, eps = f(x_true)"),
             "variant": "S_CG", "scalars": "f64", "steps_per_solve": rep.steps, "k": rep.k,
+            "launch_shapes": tuning,
             "gamma0": gamma0, "rho": RHO, "a": 0.975, "eps": eps, "f_out": rep.f_out,
             "tv_out": rep.tv_out, "rel_err_vs_phantom": err,
             "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),

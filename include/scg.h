@@ -182,9 +182,12 @@ typedef struct {
                                    (256 or 512 threads)                               */
     int32_t backproject_split;  /* 1, 2 or 4: angle split inside each 16 x 16 pixel tile
                                    (128, 256 or 512 threads)                          */
+    int32_t project_angles;     /* 8 or 4: angles per projector block                 */
+    int32_t swizzle;            /* 1: consecutive blocks of a launch share an XCD
+                                   (chiplet and its L2), 0: hardware order            */
 } scg_tuning;
 
-/* Current shapes for precision prec (defaults: 4 and 2). */
+/* Current shapes for precision prec. */
 int scg_plan_get_tuning(const scg_plan *plan, int prec, scg_tuning *out);
 
 /* Sets the shapes used by every later call on the plan for precision prec.
@@ -228,6 +231,74 @@ int scg_profile(scg_plan *plan, uint32_t class_mask);
 /* Accumulated launches and milliseconds per class since the last
  * scg_profile call; out must hold SCG_KC_COUNT entries. */
 int scg_profile_read(scg_plan *plan, scg_kernel_time *out);
+
+/* ---- batch engine ------------------------------------------------------ */
+
+/* Many solves resident on one device at once, of any geometry, precision and
+ * variant, advanced together: each call of scg_batch_step runs `iters` loop
+ * iterations of every active solve with one kernel launch per phase of the
+ * iteration covering all solves of a group (same precision, variant and
+ * launch shape), the whole iteration captured as a HIP graph that is reused
+ * until the set of solves changes. A solve's result is bitwise the one
+ * scg_solve gives for the same inputs, parameters and launch shape.
+ *
+ * Workspaces come from one device arena allocated at creation; a solve is
+ * admitted when a slot is free and the arena has room for its workspace
+ * (scg_workspace_bytes), otherwise scg_batch_submit returns SCG_EAGAIN.
+ * Buffers passed to scg_batch_submit (y, x0, x_out) and the plan must stay
+ * valid until the ticket has been retired (scg_batch_poll no longer returns
+ * SCG_EINPROGRESS). Work runs on the batch's own stream (scg_batch_stream);
+ * callers that produce y on another stream must order it before submitting.
+ * A batch is not thread-safe. */
+typedef struct scg_batch scg_batch;
+
+#define SCG_BATCH_NO_GRAPH 1u   /* enqueue iterations kernel by kernel          */
+
+typedef struct {
+    int32_t  active;        /* solves on the device                             */
+    int32_t  slots;         /* max_slots                                        */
+    int32_t  groups;        /* groups of the current set                       */
+    int32_t  reserved;
+    uint64_t arena_bytes;
+    uint64_t arena_used;    /* workspace bytes of the active solves             */
+    uint64_t submitted;
+    uint64_t retired;
+    uint64_t macro_steps;   /* iterations run (each over all active solves)     */
+    uint64_t graph_builds;  /* graphs captured (one per change of the set)      */
+} scg_batch_stats;
+
+/* Creates a batch on `device` with an arena of arena_bytes and at most
+ * max_slots concurrent solves (flags: SCG_BATCH_*). */
+int scg_batch_create(int device, size_t arena_bytes, int max_slots, uint32_t flags,
+                     scg_batch **out);
+
+/* Waits for the batch's stream and frees everything it owns. */
+void scg_batch_destroy(scg_batch *batch);
+
+/* Admits a solve: allocates its workspace and enqueues its initial step
+ * (scg_solve's arguments without trace and replay). *ticket identifies it.
+ * SCG_EAGAIN: no slot or arena room now (retry after a step). */
+int scg_batch_submit(scg_batch *batch, scg_plan *plan, const scg_params *params,
+                     const void *y, const void *x0, void *x_out, uint64_t *ticket);
+
+/* Runs `iters` iterations of every active solve (a finished solve's kernels
+ * return at once), then reads all solves' states and retires the finished
+ * ones: their output image and TV are written and their reports kept for
+ * scg_batch_poll. Returns the number of solves still active (>= 0) or a
+ * negative status. Synchronises the batch's stream. */
+int scg_batch_step(scg_batch *batch, int iters);
+
+/* SCG_OK and *rep (may be NULL) for a retired ticket, whose report is then
+ * dropped; SCG_EINPROGRESS while it runs; SCG_ENOTFOUND otherwise. */
+int scg_batch_poll(scg_batch *batch, uint64_t ticket, scg_report *rep);
+
+/* Removes an active solve without a report (SCG_ENOTFOUND if unknown). */
+int scg_batch_cancel(scg_batch *batch, uint64_t ticket);
+
+int scg_batch_get_stats(const scg_batch *batch, scg_batch_stats *out);
+
+/* The hipStream_t the batch runs on. */
+void *scg_batch_stream(const scg_batch *batch);
 
 /* Fills *params with the library's defaults: S-CG, FP32, a = 0.975,
  * max_iter = 1000, max_trials = 100, kappa = 0, mu = 2 pi / P; eps and

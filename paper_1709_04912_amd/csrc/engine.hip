@@ -1,0 +1,1030 @@
+// Solver driver of libscg. A solve lives in one workspace on the device: its
+// vectors, its FP64 scalars and control state, and a descriptor the kernels
+// read. Every iteration is a fixed sequence of phase launches, each followed
+// where needed by a finisher that turns block partial sums into the
+// algorithm's scalars; kernels return at once when their solve's `done` flag
+// is set, so the host enqueues iterations without reading anything back and
+// the iteration count is decided on the device.
+//
+// scg_solve runs one solve, enqueuing iterations in growing chunks and
+// reading the flag between chunks. The batch engine (scg_batch_*) keeps many
+// solves resident in one device arena and advances all of them with one
+// launch per phase (solves grouped by precision, variant and launch shape),
+// the whole iteration captured once as a HIP graph per set of solves;
+// finished solves retire between steps and new ones are admitted as slots
+// and arena memory free up.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "plan.h"
+
+using scg::BlkMap;
+using scg::Solve;
+
+namespace scg {
+
+namespace {
+
+// Workspace layout of one solve.
+struct Layout {
+    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, state, forced, trace, tv, gtab, desc,
+        total;
+};
+
+Layout layout(const Geo &G, size_t esz, int max_iter)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t J = G.img_elems(), S = G.sino_elems();
+    L.x = take(J * esz);
+    L.xh = take(J * esz);
+    L.p = take(J * esz);
+    L.g = take(J * esz);
+    L.h = take(J * esz);
+    L.s = take(J * esz);
+    L.z = take(J * esz);
+    L.r = take(S * esz);
+    L.q = take(S * esz);
+    L.rt = take(S * esz);
+    L.xs = take(G.staged_elems() * esz);
+    L.pt = take(G.staged_elems() * esz);
+    L.partials = take(kMaxPartials * sizeof(double));
+    L.state = take(sizeof(DevState));
+    L.forced = take((size_t)2 * (max_iter + 1) * sizeof(int32_t));
+    L.trace = take((size_t)(max_iter + 1) * sizeof(scg_trace_entry));
+    L.tv = take(sizeof(double));
+    L.gtab = take(kMaxTrials * sizeof(double));
+    L.desc = take(sizeof(Solve<double>));
+    L.total = off;
+    return L;
+}
+
+// Block kinds of the phase launches.
+enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKinds };
+
+template <typename T> int count_of(const Solve<T> &d, int kind)
+{
+    switch (kind) {
+    case kKT32: return d.nb_t32;
+    case kKXtv: return d.nb_xtv;
+    case kKTrA: return d.nb_trA;
+    case kKTrB: return d.nb_trB;
+    case kKPj: return d.nb_pj;
+    case kKBp: return d.nb_bp;
+    case kKVec: return d.nb_vec;
+    case kKFilt: return d.G.na;
+    default: return 0;
+    }
+}
+
+// A set of solves advanced together: same precision, variant and launch shapes.
+template <typename T> struct Group {
+    int ns = 0;
+    int variant = SCG_S_CG;
+    scg_tuning tune{4, 2, 8, 0};
+    int max_nb = 1;
+    const Solve<T> *S = nullptr;            // device descriptors
+    const BlkMap *map[kKinds] = {};         // device block maps (null for a single solve)
+    int nblk[kKinds] = {};
+    bool any_trB = false;
+    scg_plan *prof = nullptr;               // event timing (single solves only)
+};
+
+struct Prof {
+    scg_plan *p;
+    int cls;
+    hipStream_t s;
+    Prof(scg_plan *p_, int cls_, hipStream_t s_) : p(p_), cls(cls_), s(s_)
+    {
+        if (p) prof_mark(p, cls, s, true);
+    }
+    ~Prof()
+    {
+        if (p) prof_mark(p, cls, s, false);
+    }
+};
+
+template <typename T> struct Enq {
+    const Group<T> &g;
+    hipStream_t s;
+    const BlkMap *m(int k) const { return g.map[k]; }
+    int n(int k) const { return g.nblk[k]; }
+    void stage(int phase) const
+    {
+        Prof t(g.prof, SCG_KC_STAGE, s);
+        launch_b_stage<T>(g.S, m(kKT32), n(kKT32), phase, s);
+    }
+    void project(int phase) const
+    {
+        Prof t(g.prof, SCG_KC_PROJECT, s);
+        launch_b_project<T>(g.S, m(kKPj), n(kKPj), phase, g.tune.project_groups,
+                            g.tune.project_angles, g.tune.swizzle, s);
+    }
+    void backproject(int phase, int dot) const
+    {
+        Prof t(g.prof, SCG_KC_BACKPROJECT, s);
+        launch_b_backproject<T>(g.S, m(kKBp), n(kKBp), phase, dot, g.tune.backproject_split,
+                                g.tune.swizzle, s);
+    }
+    void finish(int fin, int a0 = 0, int a1 = 0) const
+    {
+        Prof t(g.prof, SCG_KC_CONTROL, s);
+        launch_finish<T>(g.S, g.ns, fin, a0, a1, s);
+    }
+    void p_update(int rule, int init) const
+    {
+        {
+            Prof t(g.prof, SCG_KC_VECTOR, s);
+            launch_b_p_update<T>(g.S, m(kKT32), n(kKT32), rule, init, s);
+        }
+        finish(kFinPUpdate, rule, init);
+    }
+    void filter() const
+    {
+        Prof t(g.prof, SCG_KC_FILTER, s);
+        launch_b_filter<T>(g.S, m(kKFilt), n(kKFilt), g.max_nb, s);
+    }
+};
+
+// Initial step. S- variants (steps 1-6 of the algorithms): x_{1/2} = x0, g0
+// (and z0), p0, h0 and alpha; x1 = x0 + alpha p0 and k = 1 are formed by the
+// first loop launch, which closes every step. CG: g0 = A^T(A x0 - y), p0 =
+// -g0, delta0 = ||g0||^2.
+template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
+{
+    const Enq<T> e{g, s};
+    if (g.variant == SCG_CG) {
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        e.backproject(kBpG, 2);
+        e.finish(kFinDotGG);
+        e.p_update(3, 1);
+        return;
+    }
+    e.stage(kStageXh);
+    e.project(kPjResXh);
+    e.finish(kFinResidual);
+    if (g.variant == SCG_S_PCG) {
+        e.filter();
+        e.backproject(kBpGZ, 0);
+        e.p_update(2, 1);
+    } else {
+        e.backproject(kBpG, 0);
+        e.p_update(0, 1);
+    }
+    e.project(kPjQ);
+    e.finish(kFinNormQ);
+    if (g.variant != SCG_S_CG_CD) e.backproject(kBpH, 0);
+}
+
+// One loop iteration. S- variants: close the previous step (x_{k+1} =
+// x_{k+1/2} + alpha p), perturbed(x_k) (TV subgradient, trials, x_{k+1/2}),
+// then the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP) from x_{k+1/2}.
+// CG: the cap test, then CG-STEP.
+template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
+{
+    const Enq<T> e{g, s};
+    if (g.variant == SCG_CG) {
+        e.finish(kFinCGCap);
+        e.project(kPjQ);
+        e.finish(kFinNormQCG);
+        e.backproject(kBpH, 0);
+        {
+            Prof t(g.prof, SCG_KC_VECTOR, s);
+            launch_b_x_update_cg<T>(g.S, e.m(kKVec), e.n(kKVec), s);
+        }
+        e.finish(kFinXUpdateCG);
+        e.p_update(3, 0);
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        return;
+    }
+    {
+        Prof t(g.prof, SCG_KC_TV, s);
+        launch_b_xtv<T>(g.S, e.m(kKXtv), e.n(kKXtv), s);
+    }
+    e.finish(kFinXtv);
+    {
+        Prof t(g.prof, SCG_KC_TRIALS, s);
+        launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, s);
+    }
+    e.finish(kFinTrials, 0);
+    if (g.any_trB) {
+        {
+            Prof t(g.prof, SCG_KC_TRIALS, s);
+            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
+        }
+        e.finish(kFinTrials, kTrialsPerPass);
+    }
+    {
+        Prof t(g.prof, SCG_KC_VECTOR, s);
+        launch_b_perturb<T>(g.S, e.m(kKT32), e.n(kKT32), s);
+    }
+    e.project(kPjResXh);
+    e.finish(kFinResidualStep);
+    if (g.variant == SCG_S_PCG) {
+        e.filter();
+        e.backproject(kBpGZ, 1);
+        e.finish(kFinDotGH);
+        e.p_update(2, 0);
+    } else if (g.variant == SCG_S_CG_CD) {
+        e.backproject(kBpG, 2);
+        e.finish(kFinDotGG);
+        e.p_update(1, 0);
+    } else {
+        e.backproject(kBpG, 1);
+        e.finish(kFinDotGH);
+        e.p_update(0, 0);
+    }
+    e.project(kPjQ);
+    e.finish(kFinNormQ);
+    if (g.variant != SCG_S_CG_CD) e.backproject(kBpH, 0);
+}
+
+// Output image (x_{k+1/2} of the S- variants, x of CG) and its TV.
+template <typename T> void enqueue_final(const Group<T> &g, hipStream_t s)
+{
+    launch_b_copy_out<T>(g.S, g.map[kKVec], g.nblk[kKVec], g.variant != SCG_CG, s);
+    launch_b_tv<T>(g.S, g.map[kKVec], g.nblk[kKVec], s);
+    launch_finish<T>(g.S, g.ns, kFinTV, 0, 0, s);
+}
+
+// Sets up one solve in workspace `ws`: zero pads, the start image, the
+// device state and the descriptor (host copy in *d, device copy in the
+// workspace). Enqueued on s; host arrays are staged before this returns.
+// Host staging of the uploads of prepare_solve; it must stay valid until the
+// stream has passed them.
+template <typename T> struct Staging {
+    DevState st;
+    Solve<T> desc;
+};
+
+template <typename T>
+int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, char *ws,
+                  const void *y_, const void *x0_, void *xout_, int trace_cap,
+                  const int32_t *forced_host, int forced_len, Staging<T> *stage, hipStream_t s)
+{
+    const Geo &G = plan->G;
+    const size_t J = G.img_elems(), S = G.sino_elems();
+    const Layout L = layout(G, sizeof(T), pr->max_iter);
+    auto at = [&](size_t off) { return reinterpret_cast<T *>(ws + off); };
+    Solve<T> &h = stage->desc;
+    h = Solve<T>{};
+    h.G = G;
+    h.P = proj_tables(plan, tune);
+    h.bang = plan->bang;
+    h.kern = static_cast<const T *>(plan->kern[prec_index<T>()]);
+    h.y = static_cast<const T *>(y_);
+    h.x = at(L.x);
+    h.xh = at(L.xh);
+    h.p = at(L.p);
+    h.g = at(L.g);
+    h.h = at(L.h);
+    h.s = at(L.s);
+    h.z = at(L.z);
+    h.r = at(L.r);
+    h.q = at(L.q);
+    h.rt = at(L.rt);
+    h.xs = at(L.xs);
+    h.pt = at(L.pt);
+    h.xout = static_cast<T *>(xout_);
+    h.partials = reinterpret_cast<double *>(ws + L.partials);
+    h.gtab = reinterpret_cast<double *>(ws + L.gtab);
+    h.tvd = reinterpret_cast<double *>(ws + L.tv);
+    h.st = reinterpret_cast<DevState *>(ws + L.state);
+    h.trace = reinterpret_cast<scg_trace_entry *>(ws + L.trace);
+    int32_t *forced = reinterpret_cast<int32_t *>(ws + L.forced);
+    h.nb_xtv = blocks_xtv(G);
+    h.nb_t32 = blocks_t32(G);
+    h.nb_vec = blocks_vec(J);
+    h.nb_pj = h.P.n_chunks * h.P.n_groups;
+    h.nb_bp = blocks_bp(G);
+    h.trB_chunks = (std::max(pr->max_trials - kTrialsPerPass, 0) + kTrialsPerPass - 1) /
+                   kTrialsPerPass;
+    h.nb_trA = blocks_trials(G, 1);
+    h.nb_trB = h.trB_chunks > 0 ? blocks_trials(G, h.trB_chunks) : 0;
+
+    // Pads of the staged image and of the sinograms must be zero.
+    launch_fill<T>(h.r, S, T(0), s);
+    launch_fill<T>(h.q, S, T(0), s);
+    launch_fill<T>(h.rt, S, T(0), s);
+    launch_fill<T>(h.xs, G.staged_elems(), T(0), s);
+
+    const bool is_cg = pr->variant == SCG_CG;
+    DevState &hs = stage->st;
+    hs = DevState{};
+    hs.eps = pr->eps;
+    hs.gamma0 = pr->gamma0;
+    hs.a = pr->a;
+    hs.kappa = pr->tv_kappa;
+    hs.max_iter = pr->max_iter;
+    hs.max_trials = pr->max_trials;
+    hs.variant = pr->variant;
+    hs.flags = (int)pr->flags;
+    hs.k = 0;
+    hs.steps = is_cg ? 0 : -1;   // the initial step of the S- variants is not counted
+    hs.accepted = -1;
+    hs.is_f32 = sizeof(T) == 4 ? 1 : 0;
+    hs.trace_cap = std::min<int32_t>(std::max(trace_cap, 0), pr->max_iter + 1);
+    const int nf = forced_host ? std::min<int32_t>(std::max<int32_t>(forced_len, 0),
+                                                   pr->max_iter + 1)
+                               : 0;
+    hs.forced_len = nf;
+    h.forced = nf > 0 ? forced : nullptr;
+    HIP_TRY(hipMemcpyAsync(h.st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+    if (nf > 0)
+        HIP_TRY(hipMemcpyAsync(forced, forced_host, (size_t)2 * nf * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + L.desc, &h, sizeof(h), hipMemcpyHostToDevice, s));
+
+    // x_{1/2} = x0 (S- variants) or x_0 (CG).
+    T *x_start = is_cg ? h.x : h.xh;
+    if (x0_ != nullptr) launch_copy<T>(x_start, static_cast<const T *>(x0_), J, nullptr, s);
+    else launch_fill<T>(x_start, J, T(0), s);
+    return SCG_OK;
+}
+
+template <typename T>
+Group<T> single_group(const scg_params *pr, const scg_tuning &tune, const Solve<T> &h, char *ws)
+{
+    Group<T> g;
+    g.ns = 1;
+    g.variant = pr->variant;
+    g.tune = tune;
+    g.max_nb = h.G.nb;
+    g.S = reinterpret_cast<const Solve<T> *>(ws + layout(h.G, sizeof(T), pr->max_iter).desc);
+    for (int k = 0; k < kKinds; ++k) g.nblk[k] = count_of(h, k);
+    g.any_trB = h.trB_chunks > 0;
+    return g;
+}
+
+template <typename T>
+int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *x0, void *xout,
+               char *ws, scg_report *rep, scg_trace_entry *trace_host, int32_t trace_cap,
+               const int32_t *forced_host, int32_t forced_len, hipStream_t st0)
+{
+    if (pr->variant == SCG_S_PCG) {
+        int rc = ensure_filter(plan, pr->precond_mu);
+        if (rc) return rc;
+    }
+    Staging<T> stage{};
+    const int cap = trace_host != nullptr ? trace_cap : pr->max_iter + 1;
+    const scg_tuning tune = plan->tune[prec_index<T>()];
+    int rc = prepare_solve<T>(plan, pr, tune, ws, y, x0, xout, cap, forced_host, forced_len,
+                              &stage, st0);
+    if (rc) return rc;
+    const Solve<T> &h = stage.desc;
+    Group<T> g = single_group<T>(pr, tune, h, ws);
+    g.prof = plan;
+
+    plan->prof_iter = 0;
+    enqueue_init(g, st0);
+    // loop: chunks of iterations, the device decides when to stop
+    int done = 0;
+    long issued = 0;
+    int chunk = 2;
+    HIP_TRY(hipMemcpyAsync(&done, &h.st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipStreamSynchronize(st0));
+    while (!done && issued <= (long)pr->max_iter) {
+        for (int c = 0; c < chunk; ++c) {
+            plan->prof_iter = (int)std::min<long>(issued + c + 1, INT_MAX - 1);
+            enqueue_iteration(g, st0);
+        }
+        issued += chunk;
+        chunk = std::min(chunk * 2, 16);
+        HIP_TRY(hipMemcpyAsync(&done, &h.st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
+        HIP_TRY(hipStreamSynchronize(st0));
+    }
+    plan->prof_iter = INT_MAX;
+    g.prof = nullptr;
+    enqueue_final(g, st0);
+
+    DevState fs{};
+    double tv_out = 0.0;
+    HIP_TRY(hipMemcpyAsync(&fs, h.st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipMemcpyAsync(&tv_out, h.tvd, sizeof(double), hipMemcpyDeviceToHost, st0));
+    if (trace_host != nullptr && trace_cap > 0) {
+        const int n = std::min<int>(trace_cap, pr->max_iter + 1);
+        HIP_TRY(hipMemcpyAsync(trace_host, h.trace, (size_t)n * sizeof(scg_trace_entry),
+                               hipMemcpyDeviceToHost, st0));
+    }
+    HIP_TRY(hipStreamSynchronize(st0));
+    prof_drain(plan, std::max(fs.steps, 0));
+    plan->prof_iter = 0;
+    const bool is_cg = pr->variant == SCG_CG;
+    if (rep != nullptr) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->status = fs.done ? fs.status : SCG_ENOCONV;
+        rep->k = is_cg ? fs.k : std::max(fs.k, 1);
+        rep->steps = std::max(fs.steps, 0);
+        rep->trials_total = fs.trials_total;
+        rep->ell = fs.ell;
+        rep->f_out = fs.f_half;
+        rep->tv_out = tv_out;
+    }
+    return fs.done ? fs.status : SCG_ENOCONV;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const Geo &G, int prec, int max_iter)
+{
+    return layout(G, prec == SCG_F64 ? sizeof(double) : sizeof(float), max_iter).total;
+}
+
+}  // namespace scg
+
+// ---------------------------------------------------------------------------
+// Batch engine
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// First-fit allocator over one device allocation (256-byte granules).
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+    void reset(char *b, size_t n)
+    {
+        base = b;
+        size = n;
+        used = 0;
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = scg::align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used += bytes;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = scg::align256(bytes);
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Slot {
+    uint64_t ticket = 0;
+    scg_plan *plan = nullptr;
+    scg_params params{};
+    scg_tuning tune{};           // launch shapes fixed at admission
+    size_t off = 0, bytes = 0;
+    int staging = -1;            // index of the slot's pinned staging entry
+    Solve<float> df{};
+    Solve<double> dd{};
+};
+
+// Pinned staging entry of a slot: the uploads of its set-up.
+struct StagingEntry {
+    scg::Staging<float> f;
+    scg::Staging<double> d;
+};
+
+}  // namespace
+
+struct scg_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t flags = 0;
+    int max_slots = 0;
+    char *arena_mem = nullptr;
+    Arena arena;
+    std::vector<Slot> active;
+    std::map<uint64_t, scg_report> finished;
+    uint64_t next_ticket = 1;
+    // the current set of solves on the device
+    bool dirty = true;
+    char *comp = nullptr;
+    size_t comp_bytes = 0;
+    std::vector<scg::Group<float>> gf;
+    std::vector<scg::Group<double>> gd;
+    std::vector<std::vector<int>> members_f, members_d;   // slot indices per group
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // state read-back
+    DevState *dstates = nullptr;
+    double *dtv = nullptr;
+    DevState *hstates = nullptr;   // pinned
+    double *htv = nullptr;         // pinned
+    char *fin_dev = nullptr;       // descriptors and maps of retiring solves
+    size_t fin_bytes = 0;
+    StagingEntry *staging = nullptr;   // pinned, one entry per slot
+    std::vector<int> staging_free;
+    scg_batch_stats stats{};
+};
+
+namespace {
+
+template <typename T> scg::Staging<T> &staging_of(StagingEntry &e);
+template <> scg::Staging<float> &staging_of<float>(StagingEntry &e) { return e.f; }
+template <> scg::Staging<double> &staging_of<double>(StagingEntry &e) { return e.d; }
+
+template <typename T> Solve<T> &desc_of(Slot &s);
+template <> Solve<float> &desc_of<float>(Slot &s) { return s.df; }
+template <> Solve<double> &desc_of<double>(Slot &s) { return s.dd; }
+
+// Host image of a set of groups: descriptors and block maps, packed for one
+// upload; device pointers are assigned by `place`.
+struct Packer {
+    std::vector<char> bytes;
+    template <typename V> size_t put(const std::vector<V> &v)
+    {
+        const size_t off = scg::align256(bytes.size());
+        bytes.resize(off + v.size() * sizeof(V));
+        if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(V));
+        return off;
+    }
+};
+
+template <typename T> struct GroupImage {
+    scg::Group<T> g;
+    size_t desc_off = 0;
+    size_t map_off[scg::kKinds] = {};
+};
+
+template <typename T>
+GroupImage<T> pack_group(Packer &pk, std::vector<Slot> &slots, const std::vector<int> &members,
+                         int variant, scg_tuning tune, bool with_maps)
+{
+    GroupImage<T> gi;
+    std::vector<Solve<T>> descs;
+    for (int i : members) descs.push_back(desc_of<T>(slots[i]));
+    gi.g.ns = (int)descs.size();
+    gi.g.variant = variant;
+    gi.g.tune = tune;
+    gi.desc_off = pk.put(descs);
+    for (int k = 0; k < scg::kKinds; ++k) {
+        std::vector<BlkMap> map;
+        for (int si = 0; si < (int)descs.size(); ++si) {
+            const int c = scg::count_of(descs[si], k);
+            for (int l = 0; l < c; ++l) map.push_back(BlkMap{si, l});
+        }
+        gi.g.nblk[k] = (int)map.size();
+        gi.map_off[k] = with_maps ? pk.put(map) : 0;
+    }
+    for (const auto &d : descs) {
+        gi.g.max_nb = std::max(gi.g.max_nb, d.G.nb);
+        gi.g.any_trB = gi.g.any_trB || d.trB_chunks > 0;
+    }
+    return gi;
+}
+
+template <typename T> void place(GroupImage<T> &gi, char *dev)
+{
+    gi.g.S = reinterpret_cast<const Solve<T> *>(dev + gi.desc_off);
+    for (int k = 0; k < scg::kKinds; ++k)
+        gi.g.map[k] = gi.g.nblk[k] ? reinterpret_cast<const BlkMap *>(dev + gi.map_off[k])
+                                   : nullptr;
+}
+
+int ensure_buf(char **buf, size_t *cap, size_t need)
+{
+    if (need <= *cap && *buf != nullptr) return SCG_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc(buf, need) != hipSuccess) {
+        *buf = nullptr;
+        return SCG_ENOMEM;
+    }
+    *cap = need;
+    return SCG_OK;
+}
+
+void drop_graph(scg_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Groups the active solves, uploads their descriptors and block maps and
+// (unless disabled) captures one iteration of all groups as a graph.
+int rebuild(scg_batch *b)
+{
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->gf.clear();
+    b->gd.clear();
+    b->members_f.clear();
+    b->members_d.clear();
+    // group key: precision, variant, launch shape
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> keys;
+    for (int i = 0; i < (int)b->active.size(); ++i) {
+        const Slot &s = b->active[i];
+        const int pi = s.params.prec == SCG_F64 ? 1 : 0;
+        const scg_tuning t = s.tune;
+        keys[std::make_tuple(pi, (int)s.params.variant, t.project_groups * 100 +
+                                                           t.backproject_split * 10 + t.swizzle,
+                             t.project_angles)]
+            .push_back(i);
+    }
+    Packer pk;
+    std::vector<GroupImage<float>> imf;
+    std::vector<GroupImage<double>> imd;
+    for (auto &kv : keys) {
+        const int pi = std::get<0>(kv.first), variant = std::get<1>(kv.first);
+        const scg_tuning t = b->active[kv.second.front()].tune;
+        if (pi == 0) {
+            imf.push_back(pack_group<float>(pk, b->active, kv.second, variant, t, true));
+            b->members_f.push_back(kv.second);
+        } else {
+            imd.push_back(pack_group<double>(pk, b->active, kv.second, variant, t, true));
+            b->members_d.push_back(kv.second);
+        }
+    }
+    int rc = ensure_buf(&b->comp, &b->comp_bytes, std::max<size_t>(pk.bytes.size(), 256));
+    if (rc) return rc;
+    if (!pk.bytes.empty())
+        HIP_TRY(hipMemcpy(b->comp, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
+    for (auto &gi : imf) {
+        place(gi, b->comp);
+        b->gf.push_back(gi.g);
+    }
+    for (auto &gi : imd) {
+        place(gi, b->comp);
+        b->gd.push_back(gi.g);
+    }
+    if (!(b->flags & SCG_BATCH_NO_GRAPH) && !b->active.empty()) {
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        for (auto &g : b->gf) scg::enqueue_iteration(g, b->stream);
+        for (auto &g : b->gd) scg::enqueue_iteration(g, b->stream);
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(b->stream, &graph) != hipSuccess || graph == nullptr)
+            return SCG_EDEVICE;
+        b->graph = graph;
+        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            return SCG_EDEVICE;
+        }
+        b->stats.graph_builds += 1;
+    }
+    b->stats.groups = (int32_t)(b->gf.size() + b->gd.size());
+    b->dirty = false;
+    return SCG_OK;
+}
+
+template <typename T>
+void gather(const scg::Group<T> &g, DevState *dst, double *tv, hipStream_t s)
+{
+    scg::launch_gather<T>(g.S, g.ns, dst, tv, s);
+}
+
+void fill_report(const Slot &s, const DevState &fs, double tv, scg_report *rep)
+{
+    std::memset(rep, 0, sizeof(*rep));
+    const bool is_cg = s.params.variant == SCG_CG;
+    rep->status = fs.done ? fs.status : SCG_ENOCONV;
+    rep->k = is_cg ? fs.k : std::max(fs.k, 1);
+    rep->steps = std::max(fs.steps, 0);
+    rep->trials_total = fs.trials_total;
+    rep->ell = fs.ell;
+    rep->f_out = fs.f_half;
+    rep->tv_out = tv;
+}
+
+// Output copy, TV and report of the solves `idx` (indices into active),
+// then frees their slots.
+int retire(scg_batch *b, const std::vector<int> &idx)
+{
+    if (idx.empty()) return SCG_OK;
+    // per (precision, CG or not): one finalize group without graph
+    Packer pk;
+    std::vector<GroupImage<float>> imf;
+    std::vector<GroupImage<double>> imd;
+    std::vector<std::vector<int>> mf, md;
+    for (int pi = 0; pi < 2; ++pi)
+        for (int cg = 0; cg < 2; ++cg) {
+            std::vector<int> sel;
+            for (int i : idx) {
+                const Slot &s = b->active[i];
+                if ((s.params.prec == SCG_F64 ? 1 : 0) == pi &&
+                    (s.params.variant == SCG_CG ? 1 : 0) == cg)
+                    sel.push_back(i);
+            }
+            if (sel.empty()) continue;
+            const int variant = cg ? SCG_CG : SCG_S_CG;
+            if (pi == 0) {
+                imf.push_back(pack_group<float>(pk, b->active, sel, variant, {4, 2, 8, 0}, true));
+                mf.push_back(sel);
+            } else {
+                imd.push_back(pack_group<double>(pk, b->active, sel, variant, {4, 2, 8, 0}, true));
+                md.push_back(sel);
+            }
+        }
+    int rc = ensure_buf(&b->fin_dev, &b->fin_bytes, std::max<size_t>(pk.bytes.size(), 256));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(b->fin_dev, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice,
+                           b->stream));
+    int at = 0;
+    std::vector<int> order;
+    for (size_t k = 0; k < imf.size(); ++k) {
+        place(imf[k], b->fin_dev);
+        scg::enqueue_final(imf[k].g, b->stream);
+        gather(imf[k].g, b->dstates + at, b->dtv + at, b->stream);
+        at += imf[k].g.ns;
+        order.insert(order.end(), mf[k].begin(), mf[k].end());
+    }
+    for (size_t k = 0; k < imd.size(); ++k) {
+        place(imd[k], b->fin_dev);
+        scg::enqueue_final(imd[k].g, b->stream);
+        gather(imd[k].g, b->dstates + at, b->dtv + at, b->stream);
+        at += imd[k].g.ns;
+        order.insert(order.end(), md[k].begin(), md[k].end());
+    }
+    HIP_TRY(hipMemcpyAsync(b->hstates, b->dstates, at * sizeof(DevState), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->htv, b->dtv, at * sizeof(double), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int k = 0; k < at; ++k) {
+        const Slot &s = b->active[order[k]];
+        scg_report rep;
+        fill_report(s, b->hstates[k], b->htv[k], &rep);
+        b->finished[s.ticket] = rep;
+        b->arena.release(s.off, s.bytes);
+        b->staging_free.push_back(s.staging);
+        b->stats.retired += 1;
+    }
+    std::vector<int> sorted = idx;
+    std::sort(sorted.rbegin(), sorted.rend());
+    for (int i : sorted) b->active.erase(b->active.begin() + i);
+    b->dirty = true;
+    return SCG_OK;
+}
+
+template <typename T>
+int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *y,
+                const void *x0, void *x_out, Slot &slot)
+{
+    if (pr->variant == SCG_S_PCG) {
+        int rc = scg::ensure_filter(plan, pr->precond_mu);
+        if (rc) return rc;
+    }
+    char *ws = b->arena.base + slot.off;
+    scg::Staging<T> &stage = staging_of<T>(b->staging[slot.staging]);
+    slot.tune = plan->tune[scg::prec_index<T>()];
+    int rc = scg::prepare_solve<T>(plan, pr, slot.tune, ws, y, x0, x_out, 0, nullptr, 0, &stage,
+                                   b->stream);
+    if (rc) return rc;
+    const Solve<T> &h = stage.desc;
+    desc_of<T>(slot) = h;
+    scg::Group<T> g = scg::single_group<T>(pr, slot.tune, h, ws);
+    scg::enqueue_init(g, b->stream);
+    return SCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scg_workspace_bytes(const scg_plan *plan, const scg_params *params, size_t *bytes)
+{
+    if (plan == nullptr || bytes == nullptr) return SCG_EINVAL;
+    int rc = scg::check_params(params);
+    if (rc) return rc;
+    *bytes = scg::workspace_bytes(plan->G, params->prec, params->max_iter);
+    return SCG_OK;
+}
+
+int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const void *x0,
+              void *x_out, void *ws, size_t ws_bytes, scg_report *rep, scg_trace_entry *trace,
+              int32_t trace_cap, const int32_t *forced, int32_t forced_len, void *stream)
+{
+    if (plan == nullptr || y == nullptr || x_out == nullptr || ws == nullptr) return SCG_EINVAL;
+    int rc = scg::check_params(params);
+    if (rc) return rc;
+    if (ws_bytes < scg::workspace_bytes(plan->G, params->prec, params->max_iter))
+        return SCG_ENOMEM;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SCG_EINVAL;
+    scg::Device dg(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (params->prec == SCG_F32)
+        rc = scg::solve_impl<float>(plan, params, y, x0, x_out, static_cast<char *>(ws), rep,
+                                    trace, trace_cap, forced, forced_len, s);
+    else
+        rc = scg::solve_impl<double>(plan, params, y, x0, x_out, static_cast<char *>(ws), rep,
+                                     trace, trace_cap, forced, forced_len, s);
+    if (hipGetLastError() != hipSuccess) return SCG_EDEVICE;
+    return rc;
+}
+
+int scg_batch_create(int device, size_t arena_bytes, int max_slots, uint32_t flags,
+                     scg_batch **out)
+{
+    if (out == nullptr) return SCG_EINVAL;
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 4096 || arena_bytes < 4096) return SCG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SCG_EDEVICE;
+    scg::Device dg(device);
+    scg_batch *b = new (std::nothrow) scg_batch();
+    if (b == nullptr) return SCG_ENOMEM;
+    b->device = device;
+    b->flags = flags;
+    b->max_slots = max_slots;
+    arena_bytes = scg::align256(arena_bytes);
+    bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    b->own_stream = ok;
+    ok = ok && hipMalloc(&b->arena_mem, arena_bytes) == hipSuccess &&
+         hipMalloc(&b->dstates, (size_t)max_slots * sizeof(DevState)) == hipSuccess &&
+         hipMalloc(&b->dtv, (size_t)max_slots * sizeof(double)) == hipSuccess &&
+         hipHostMalloc(&b->hstates, (size_t)max_slots * sizeof(DevState), hipHostMallocDefault) ==
+             hipSuccess &&
+         hipHostMalloc(&b->htv, (size_t)max_slots * sizeof(double), hipHostMallocDefault) ==
+             hipSuccess &&
+         hipHostMalloc(&b->staging, (size_t)max_slots * sizeof(StagingEntry),
+                       hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        scg_batch_destroy(b);
+        return SCG_ENOMEM;
+    }
+    b->arena.reset(b->arena_mem, arena_bytes);
+    for (int i = max_slots - 1; i >= 0; --i) b->staging_free.push_back(i);
+    b->stats.slots = max_slots;
+    b->stats.arena_bytes = arena_bytes;
+    *out = b;
+    return SCG_OK;
+}
+
+void scg_batch_destroy(scg_batch *b)
+{
+    if (b == nullptr) return;
+    scg::Device dg(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    (void)hipFree(b->arena_mem);
+    (void)hipFree(b->comp);
+    (void)hipFree(b->fin_dev);
+    (void)hipFree(b->dstates);
+    (void)hipFree(b->dtv);
+    if (b->hstates) (void)hipHostFree(b->hstates);
+    if (b->htv) (void)hipHostFree(b->htv);
+    if (b->staging) (void)hipHostFree(b->staging);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int scg_batch_submit(scg_batch *b, scg_plan *plan, const scg_params *params, const void *y,
+                     const void *x0, void *x_out, uint64_t *ticket)
+{
+    if (b == nullptr || plan == nullptr || y == nullptr || x_out == nullptr || ticket == nullptr)
+        return SCG_EINVAL;
+    int rc = scg::check_params(params);
+    if (rc) return rc;
+    if (plan->device != b->device) return SCG_EINVAL;
+    if ((int)b->active.size() >= b->max_slots) return SCG_EAGAIN;
+    scg::Device dg(b->device);
+    Slot slot;
+    slot.plan = plan;
+    slot.params = *params;
+    slot.bytes = scg::workspace_bytes(plan->G, params->prec, params->max_iter);
+    if (b->staging_free.empty()) return SCG_EAGAIN;
+    if (!b->arena.alloc(slot.bytes, &slot.off)) return SCG_EAGAIN;
+    slot.staging = b->staging_free.back();
+    b->staging_free.pop_back();
+    rc = params->prec == SCG_F32 ? submit_impl<float>(b, plan, params, y, x0, x_out, slot)
+                                 : submit_impl<double>(b, plan, params, y, x0, x_out, slot);
+    if (rc == SCG_OK && hipGetLastError() != hipSuccess) rc = SCG_EDEVICE;
+    if (rc) {
+        (void)hipStreamSynchronize(b->stream);
+        b->arena.release(slot.off, slot.bytes);
+        b->staging_free.push_back(slot.staging);
+        return rc;
+    }
+    slot.ticket = b->next_ticket++;
+    *ticket = slot.ticket;
+    b->active.push_back(slot);
+    b->dirty = true;
+    b->stats.submitted += 1;
+    return SCG_OK;
+}
+
+int scg_batch_step(scg_batch *b, int iters)
+{
+    if (b == nullptr || iters < 0) return SCG_EINVAL;
+    scg::Device dg(b->device);
+    if (b->active.empty()) return 0;
+    if (b->dirty) {
+        int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    for (int it = 0; it < iters; ++it) {
+        if (b->exec) {
+            HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+        } else {
+            for (auto &g : b->gf) scg::enqueue_iteration(g, b->stream);
+            for (auto &g : b->gd) scg::enqueue_iteration(g, b->stream);
+        }
+        b->stats.macro_steps += 1;
+    }
+    // read every solve's state; retire the finished ones
+    int at = 0;
+    std::vector<int> order;
+    for (size_t k = 0; k < b->gf.size(); ++k) {
+        gather(b->gf[k], b->dstates + at, b->dtv + at, b->stream);
+        at += b->gf[k].ns;
+        order.insert(order.end(), b->members_f[k].begin(), b->members_f[k].end());
+    }
+    for (size_t k = 0; k < b->gd.size(); ++k) {
+        gather(b->gd[k], b->dstates + at, b->dtv + at, b->stream);
+        at += b->gd[k].ns;
+        order.insert(order.end(), b->members_d[k].begin(), b->members_d[k].end());
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(b->hstates, b->dstates, at * sizeof(DevState), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<int> fin;
+    for (int k = 0; k < at; ++k) {
+        const DevState &fs = b->hstates[k];
+        const Slot &s = b->active[order[k]];
+        (void)s;
+        if (fs.done) fin.push_back(order[k]);
+    }
+    int rc = retire(b, fin);
+    if (rc) return rc;
+    return (int)b->active.size();
+}
+
+int scg_batch_poll(scg_batch *b, uint64_t ticket, scg_report *rep)
+{
+    if (b == nullptr) return SCG_EINVAL;
+    auto it = b->finished.find(ticket);
+    if (it != b->finished.end()) {
+        if (rep != nullptr) *rep = it->second;
+        b->finished.erase(it);
+        return SCG_OK;
+    }
+    for (const Slot &s : b->active)
+        if (s.ticket == ticket) return SCG_EINPROGRESS;
+    return SCG_ENOTFOUND;
+}
+
+int scg_batch_cancel(scg_batch *b, uint64_t ticket)
+{
+    if (b == nullptr) return SCG_EINVAL;
+    scg::Device dg(b->device);
+    for (size_t i = 0; i < b->active.size(); ++i) {
+        if (b->active[i].ticket != ticket) continue;
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        b->arena.release(b->active[i].off, b->active[i].bytes);
+        b->staging_free.push_back(b->active[i].staging);
+        b->active.erase(b->active.begin() + i);
+        b->dirty = true;
+        return SCG_OK;
+    }
+    b->finished.erase(ticket);
+    return SCG_ENOTFOUND;
+}
+
+int scg_batch_get_stats(const scg_batch *b, scg_batch_stats *out)
+{
+    if (b == nullptr || out == nullptr) return SCG_EINVAL;
+    *out = b->stats;
+    out->active = (int32_t)b->active.size();
+    out->arena_used = b->arena.used;
+    return SCG_OK;
+}
+
+void *scg_batch_stream(const scg_batch *b) { return b ? static_cast<void *>(b->stream) : nullptr; }
+
+}  // extern "C"

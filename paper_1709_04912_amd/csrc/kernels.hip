@@ -2,10 +2,13 @@
 // and its subgradient, the perturbation trials, the CG vector updates and the
 // preconditioning filter.
 //
-// Every reduction is deterministic: per-thread partial sums, a fixed 64-lane
-// butterfly, per-block partials in FP64 and a fixed-order final sum done by
-// the last block to finish (a counter decides which block is last; there are
-// no floating-point atomics), so results are bitwise reproducible.
+// Solver kernels are written as block bodies and launched two ways: for one
+// solve, or batched, where one launch covers a phase of many solves and a
+// block map gives each block its solve and local block index. Scalars come
+// from reductions that are deterministic and free of atomics: every block
+// stores its partial sums (fixed 64-lane butterflies, FP64), and a finisher
+// launch (one block per solve) sums them in a fixed order and applies the
+// scalar logic of the algorithm to the solve's device state.
 #include "scg_internal.h"
 
 namespace scg {
@@ -63,29 +66,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ double load_relaxed(const double *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Block partial sums of NV values; the last block to finish sums all partials
-// in a fixed order. Returns true in every thread of the last block; `tot` is
-// valid in its thread 0. Every thread of the block must call this.
-//
-// Arrivals are counted in two levels (kRedGroups counters, 256 bytes apart,
-// then one top counter) so that no single counter takes more than
-// max(blocks / kRedGroups, kRedGroups) atomic increments; a single shared
-// counter serialises every block's increment.
+// Block sum of NV values into dst[0..NV) (thread k < NV writes dst[k]).
+// Every thread of the block must call this.
 template <int NV, typename A>
-__device__ bool reduce_finish(const A (&v)[NV], double *partials, unsigned *counter,
-                              double *tot)
+__device__ void block_store(const A (&v)[NV], double *dst)
 {
     __shared__ double sh[NV][16];   // up to 1024 threads
-    __shared__ int s_last;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
-    const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
-    const unsigned bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = wave_sum((double)v[k]);
@@ -95,44 +83,25 @@ __device__ bool reduce_finish(const A (&v)[NV], double *partials, unsigned *coun
     if (threadIdx.x < NV) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
-        partials[(size_t)bid * NV + threadIdx.x] = s;
+        dst[threadIdx.x] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned g = bid % kRedGroups;
-        const unsigned members = (nblk - g + kRedGroups - 1) / kRedGroups;
-        int last = 0;
-        if (atomicAdd(&counter[g * kRedStride], 1u) == members - 1) {
-            __hip_atomic_store(&counter[g * kRedStride], 0u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const unsigned groups = nblk < kRedGroups ? nblk : kRedGroups;
-            last = atomicAdd(&counter[kRedGroups * kRedStride], 1u) == groups - 1;
-            if (last)
-                __hip_atomic_store(&counter[kRedGroups * kRedStride], 0u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_last = last;
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    for (int k = 0; k < NV; ++k) {
+}
+
+// tot[k] = sum over blocks b of partials[b * stride + k], k < nv: lane-strided
+// runs, then a fixed butterfly; one wave per value so that all loads are in
+// flight together. tot is in shared memory and valid in every thread after.
+__device__ void final_sums(const double *partials, int nblk, int stride, int nv, double *tot)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int k = wid; k < nv; k += nw) {
         double acc = 0.0;
-        for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x)
-            acc += load_relaxed(&partials[(size_t)b * NV + k]);
+        for (int b = lane; b < nblk; b += 64) acc += partials[(size_t)b * stride + k];
         acc = wave_sum(acc);
-        __syncthreads();
-        if (lane == 0) sh[0][wid] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += sh[0][w];
-            tot[k] = s;
-        }
+        if (lane == 0) tot[k] = acc;
     }
-    return true;
+    __syncthreads();
 }
 
 __device__ __forceinline__ bool stopped(const DevState *st) { return st != nullptr && st->done; }
@@ -149,13 +118,17 @@ __device__ __forceinline__ void set_done(DevState *st, int status)
     st->status = status;
 }
 
-// gamma_l = gamma0 a^l for the next kTrialsPerPass trials (threads 0..15 of a
-// block, one power each).
-__device__ __forceinline__ void fill_gammas(DevState *st, int ell)
+// gtab[m] = gamma0 a^(l+m), m < max_trials: the step sizes of the trials of
+// the step that starts with counter value l (rounded to the image precision,
+// the value the trials and the accepted perturbation use). All threads of
+// the block take part.
+__device__ __forceinline__ void fill_gtab(double *gtab, const DevState *st, int ell)
 {
-    if (threadIdx.x < kTrialsPerPass) {
-        double g = st->gamma0 * pow(st->a, (double)(ell + (int)threadIdx.x));
-        st->gam[threadIdx.x] = st->is_f32 ? (double)(float)g : g;
+    const double g0 = st->gamma0, a = st->a;
+    const int mt = st->max_trials, f32 = st->is_f32;
+    for (int m = threadIdx.x; m < mt; m += blockDim.x) {
+        const double g = g0 * pow(a, (double)(ell + m));
+        gtab[m] = f32 ? (double)(float)g : g;
     }
 }
 
@@ -167,7 +140,61 @@ inline int vec_blocks(size_t n)
     return (int)b;
 }
 
+// Block coordinates of a body: (x, y) in an (nx, ny) grid.
+struct VBlk {
+    int x, y, nx, ny;
+    __device__ int id() const { return y * nx + x; }
+    __device__ int count() const { return nx * ny; }
+};
+
+__device__ __forceinline__ VBlk vblk_of(int local, int nx, int ny)
+{
+    return VBlk{local % nx, local / nx, nx, ny};
+}
+
+__device__ __forceinline__ VBlk grid_vblk()
+{
+    return VBlk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y};
+}
+
+// Launch-order block index. With swz, consecutive indices go to the same
+// XCD: the hardware hands workgroup b to XCD b mod 8, so the blocks the
+// hardware places on one XCD get one contiguous range of indices and share
+// that XCD's L2 for the data neighbouring blocks read.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int launch_index(int swz)
+{
+    const int b = blockIdx.x, n = gridDim.x;
+    if (!swz) return b;
+    const int per = n / kXcds, rem = n % kXcds;
+    const int xcd = b % kXcds, idx = b / kXcds;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// The solve and the local block index of a batched launch's block.
+__device__ __forceinline__ BlkMap locate(const BlkMap *map, int swz = 0)
+{
+    const int b = launch_index(swz);
+    if (map == nullptr) return BlkMap{0, b};
+    return map[b];
+}
+
 }  // namespace
+
+int blocks_xtv(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 7) / 8); }
+int blocks_t32(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 31) / 32); }
+int blocks_vec(size_t n) { return vec_blocks(n); }
+int blocks_bp(const Geo &G)
+{
+    const int t = (G.n + kBpTile - 1) / kBpTile;
+    return t * t;
+}
+int blocks_trials(const Geo &G, int nchunks)
+{
+    const int b = vec_blocks((size_t)(G.n - 1) * (G.n - 1));
+    const int cap = kMaxPartials / (1 + kTrialsPerPass * nchunks);
+    return b < cap ? b : cap;
+}
 
 // ---------------------------------------------------------------------------
 // Elementwise helpers
@@ -203,19 +230,40 @@ void launch_copy(T *dst, const T *src, size_t n, const DevState *st, hipStream_t
     hipLaunchKernelGGL(k_copy<T>, dim3(vec_blocks(n)), dim3(kBlock), 0, s, dst, src, n, st);
 }
 
+// Output copy of every solve of a batch (x_{k+1/2} for the S- variants, x
+// for CG), run after the loop whether or not the solve stopped.
+template <typename T>
+__global__ __launch_bounds__(256) void kb_copy_out(const Solve<T> *S, const BlkMap *map,
+                                                    int from_xh)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    const T *src = from_xh ? d.xh : d.x;
+    T *dst = d.xout;
+    const size_t J = (size_t)d.G.n * d.G.n;
+    for (size_t i = m.local * (size_t)blockDim.x + threadIdx.x; i < J;
+         i += (size_t)d.nb_vec * blockDim.x)
+        dst[i] = src[i];
+}
+
+template <typename T>
+void launch_b_copy_out(const Solve<T> *S, const BlkMap *map, int nblocks, int from_xh,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_copy_out<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map, from_xh);
+}
+
 // ---------------------------------------------------------------------------
 // Image staging: the transposed copy that angles stepping over columns read
 // (32x32 tiles through LDS so both the read and the write are coalesced).
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__restrict__ xt,
-                                                Geo G, const DevState *st)
+__device__ void stage_body(const T *__restrict__ x, T *__restrict__ xt, const Geo &G, VBlk vb)
 {
-    if (stopped(st)) return;
     __shared__ T tile[32][33];
     const int n = G.n;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, j = bx + tx;
@@ -229,49 +277,65 @@ __global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__res
 }
 
 template <typename T>
-void launch_stage(const T *x, T *xt, const Geo &G, const DevState *st, hipStream_t s)
+__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ x, T *__restrict__ xt, Geo G)
+{
+    stage_body(x, xt, G, grid_vblk());
+}
+
+template <typename T> void launch_stage(const T *x, T *xt, const Geo &G, hipStream_t s)
 {
     dim3 grid((G.n + 31) / 32, (G.n + 31) / 32);
-    hipLaunchKernelGGL(k_stage<T>, grid, dim3(256), 0, s, x, xt, G, st);
+    hipLaunchKernelGGL(k_stage<T>, grid, dim3(256), 0, s, x, xt, G);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_stage(const Solve<T> *S, const BlkMap *map, int phase)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    const int nt = (d.G.n + 31) / 32;
+    stage_body(phase == kStageX ? d.x : d.xh, d.xs, d.G, vblk_of(m.local, nt, nt));
+}
+
+template <typename T>
+void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_stage<T>, dim3(nblocks), dim3(256), 0, s, S, map, phase);
 }
 
 // ---------------------------------------------------------------------------
 // Forward projector A (ray-driven, banded). Block (bin chunk, angle group):
-// thread t owns bin b = chunk*kPjBins + (t & 127) for the group's angles
-// (t >> 7) + 2m, m = 0..3 (each wavefront has one angle per slot). The block
-// walks bands of kPjBand steps along the group's major axis (rows of x, or
-// rows of x^T for angles stepping over columns), staging kPjWin columns of
-// each band in LDS, column-major with a stride of kPjBand + 1 elements so
-// neighbouring columns fall in different banks; the next band is prefetched
-// into registers while the current one is consumed. Within a band a ray's
-// crossing coordinate is an integer anchor plus an FP32 fraction (the anchor
-// from FP64), so the split weights stay accurate near the axes where the
-// chord ramp is steep. Per step: the crossing, its floor and fraction, one
-// clamped FMA for the split weight, two LDS reads and three FMAs/adds.
+// NQ groups of kPjBins threads; thread t owns bin b = chunk*kPjBins +
+// (t % kPjBins) for the group's angles (t / kPjBins) + NQ m (each wavefront
+// has one angle per slot). The block walks bands of kPjBand steps along the
+// group's major axis (rows of x, or rows of x^T for angles stepping over
+// columns), staging kPjWin columns of each band in LDS, column-major with a
+// stride of kPjBand + 1 elements so neighbouring columns fall in different
+// banks; the next band is prefetched into registers while the current one
+// is consumed. Within a band a ray's crossing coordinate is an integer anchor
+// plus an FP32 fraction (the anchor from FP64), so the split weights stay
+// accurate near the axes where the chord ramp is steep. Per step: the
+// crossing, its floor and fraction, one clamped FMA for the split weight, two
+// LDS reads and three FMAs/adds. With y given, out = A x - y. With partials
+// given, the block stores its sum of out^2.
 // ---------------------------------------------------------------------------
 
-template <typename T, int NQ>
-__global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ x,
-                                                          const T *__restrict__ xt, Geo G,
-                                                          ProjTables P, const T *__restrict__ y,
-                                                          int y_stride, T *__restrict__ out,
-                                                          int out_stride, int out_off,
-                                                          double *partials, unsigned *counter,
-                                                          DevState *st, int mode,
-                                                          scg_trace_entry *trace)
+template <typename T, int NQ, int GA>
+__device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, const Geo &G,
+                             const ProjTables &P, const T *__restrict__ y, int y_stride,
+                             T *__restrict__ out, int out_stride, int out_off, double *partials,
+                             VBlk vb)
 {
-    if (stopped(st)) return;
-    // NQ groups of kPjBins threads; group q traces angles q, q + NQ, ... of
-    // the block's angle group for one bin each.
     constexpr int NT = kPjBins * NQ;
     constexpr int LS = kPjBand + 1;               // LDS column stride (elements)
-    constexpr int SLOTS = kPjGroup / NQ;
+    constexpr int SLOTS = GA / NQ;
     constexpr int RPT = kPjWin * kPjBand / NT;    // staged rows per thread
-    static_assert(kPjGroup % NQ == 0 && NT % kPjWin == 0 && kPjBand % RPT == 0,
+    static_assert(GA % NQ == 0 && GA <= kPjGroup && NT % kPjWin == 0 && kPjBand % RPT == 0,
                   "projector tiling");
     __shared__ T lds[kPjWin * LS];
     const int t = threadIdx.x;
-    const int chunk = blockIdx.x, gi = blockIdx.y;
+    const int chunk = vb.x, gi = vb.y;
     const PjGroup grp = P.groups[gi];
     const int quarter = __builtin_amdgcn_readfirstlane(t / kPjBins);
     const int b_raw = chunk * kPjBins + (t & (kPjBins - 1));
@@ -364,53 +428,86 @@ __global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ 
             sq += (double)val * (double)val;
         }
     }
-    if (mode == kRedNone) return;
-    double v[1] = {sq}, tot[1];
-    if (!reduce_finish(v, partials, counter, tot) || threadIdx.x != 0) return;
-    const double s = tot[0];
-    if (mode == kRedResidual || mode == kRedResidualStep) {
-        const double f = 0.5 * s;
-        st->f_half = f;
-        if (mode == kRedResidualStep)
-            if (scg_trace_entry *tr = trace_at(st, trace, st->k)) tr->f_half = f;
-        if (!isfinite(f)) {
-            set_done(st, SCG_ENAN);
-        } else if (f <= st->eps) {
-            // Inside a step, the next loop test f(x_{k+1/2}) <= eps ends the
-            // solve at k+1 with output x_{k+1/2}; the rest of the step is not
-            // needed for the output and is skipped.
-            if (mode == kRedResidualStep) {
-                st->steps += 1;
-                st->k += 1;
-            }
-            set_done(st, SCG_OK);
-        }
-    } else if (mode == kRedNormQ || mode == kRedInitNormQ || mode == kRedNormQCG) {
-        st->qq = s;
-        if (!isfinite(s)) {
-            set_done(st, SCG_ENAN);
-        } else if (s == 0.0) {
-            set_done(st, SCG_EBREAKDOWN);
-        } else {
-            st->alpha = (mode == kRedNormQCG) ? st->delta / s : -st->gp / s;
-            if (scg_trace_entry *tr = trace_at(st, trace, st->k)) tr->alpha = st->alpha;
-        }
+    if (partials == nullptr) return;
+    double v[1] = {sq};
+    block_store(v, partials + vb.id());
+}
+
+template <typename T, int NQ, int GA>
+__global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ x,
+                                                          const T *__restrict__ xt, Geo G,
+                                                          ProjTables P, T *__restrict__ out,
+                                                          int out_stride, int out_off, int swz)
+{
+    project_body<T, NQ, GA>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr,
+                            vblk_of(launch_index(swz), P.n_chunks, P.n_groups));
+}
+
+template <typename T>
+void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, T *out,
+                    int out_stride, int out_off, int nq, int swz, hipStream_t s)
+{
+    dim3 grid(P.n_chunks * P.n_groups);
+    if (P.group_max <= 4) {
+        if (nq == 4)
+            hipLaunchKernelGGL((k_project<T, 4, 4>), grid, dim3(kPjBins * 4), 0, s, x, xt, G, P,
+                               out, out_stride, out_off, swz);
+        else
+            hipLaunchKernelGGL((k_project<T, 2, 4>), grid, dim3(kPjBins * 2), 0, s, x, xt, G, P,
+                               out, out_stride, out_off, swz);
+    } else {
+        if (nq == 4)
+            hipLaunchKernelGGL((k_project<T, 4, 8>), grid, dim3(kPjBins * 4), 0, s, x, xt, G, P,
+                               out, out_stride, out_off, swz);
+        else
+            hipLaunchKernelGGL((k_project<T, 2, 8>), grid, dim3(kPjBins * 2), 0, s, x, xt, G, P,
+                               out, out_stride, out_off, swz);
+    }
+}
+
+template <typename T, int NQ, int GA>
+__global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, const BlkMap *map,
+                                                           int phase, int swz)
+{
+    const BlkMap m = locate(map, swz);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    // descriptor fields into registers: the body's stores cannot alias them
+    const Geo G = d.G;
+    const ProjTables P = d.P;
+    const VBlk vb = vblk_of(m.local, P.n_chunks, P.n_groups);
+    if (phase == kPjQ) {
+        const T *img = d.p, *imgt = d.pt;
+        T *out = d.q;
+        double *part = d.partials;
+        project_body<T, NQ, GA>(img, imgt, G, P, nullptr, 0, out, G.rs, kSinoPadL, part, vb);
+    } else {
+        const T *img = phase == kPjResX ? d.x : d.xh, *imgt = d.xs, *y = d.y;
+        T *out = d.r;
+        double *part = d.partials;
+        project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, part, vb);
     }
 }
 
 template <typename T>
-void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, const T *y,
-                    int y_stride, T *out, int out_stride, int out_off, double *partials,
-                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace,
-                    int nq, hipStream_t s)
+void launch_b_project(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int nq,
+                      int ga, int swz, hipStream_t s)
 {
-    dim3 grid(P.n_chunks, P.n_groups);
-    if (nq == 4)
-        hipLaunchKernelGGL((k_project<T, 4>), grid, dim3(kPjBins * 4), 0, s, x, xt, G, P, y,
-                           y_stride, out, out_stride, out_off, partials, counter, st, mode, trace);
-    else
-        hipLaunchKernelGGL((k_project<T, 2>), grid, dim3(kPjBins * 2), 0, s, x, xt, G, P, y,
-                           y_stride, out, out_stride, out_off, partials, counter, st, mode, trace);
+    if (ga <= 4) {
+        if (nq == 4)
+            hipLaunchKernelGGL((kb_project<T, 4, 4>), dim3(nblocks), dim3(kPjBins * 4), 0, s, S,
+                               map, phase, swz);
+        else
+            hipLaunchKernelGGL((kb_project<T, 2, 4>), dim3(nblocks), dim3(kPjBins * 2), 0, s, S,
+                               map, phase, swz);
+    } else {
+        if (nq == 4)
+            hipLaunchKernelGGL((kb_project<T, 4, 8>), dim3(nblocks), dim3(kPjBins * 4), 0, s, S,
+                               map, phase, swz);
+        else
+            hipLaunchKernelGGL((kb_project<T, 2, 8>), dim3(nblocks), dim3(kPjBins * 2), 0, s, S,
+                               map, phase, swz);
+    }
 }
 
 // Copies an unpadded sinogram into the padded layout (pads stay zero).
@@ -432,35 +529,30 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 }
 
 // ---------------------------------------------------------------------------
-// Backprojector A^T (pixel-driven, tiled). A block owns a 16 x 16 pixel tile;
-// thread t owns the pixels (t >> 3, 2(t & 7)) and (t >> 3, 2(t & 7) + 1).
+// Backprojector A^T (pixel-driven, tiled). A tile of 16 x 16 pixels is owned
+// by NS groups of 128 threads; thread t of a group owns the pixels (t >> 3,
+// 2(t & 7)) and (t >> 3, 2(t & 7) + 1), and group gs takes the angle chunks
+// gs, gs + NS, ... (the groups' sums are added in a fixed order at the end).
 // Angles are processed in chunks of kBpChunk: for each angle the kBpWin bins
 // around the tile centre's projection are staged in LDS, already scaled by
 // 1/m, next to the angle's parameters (cos, sin, the two weight constants and
 // the centre's fractional position); the next chunk is prefetched into
 // registers while the current one is consumed. A pixel's footprint centre is
 // an FP32 offset from the tile centre (it stays in (4, 27) bins), its two
-// bins are one paired LDS read and its two weights two clamped FMAs. DUAL
+// bins are two LDS reads and its two weights two clamped FMAs. DUAL
 // backprojects a second sinogram with the same weights (S-PCG: g' and z').
+// With partials given, the block stores its part of a dot product: dot = 1,
+// out (or out2 when DUAL) against dotv; dot = 2, out against itself.
 // ---------------------------------------------------------------------------
 
 constexpr int kBpPrm = 8;   // per-angle parameters staged in LDS
 
 template <typename T, bool DUAL, int NS>
-__global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__restrict__ r,
-                                                                  const T *__restrict__ r2, Geo G,
-                                                                  const BpAngle *__restrict__ ang,
-                                                                  T *__restrict__ out,
-                                                                  T *__restrict__ out2,
-                                                                  const T *__restrict__ dotv,
-                                                                  double *partials,
-                                                                  unsigned *counter, DevState *st,
-                                                                  int mode)
+__device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ r2, const Geo &G,
+                                 const BpAngle *__restrict__ ang, T *__restrict__ out,
+                                 T *__restrict__ out2, const T *__restrict__ dotv, int dot,
+                                 double *partials, VBlk vb)
 {
-    if (stopped(st)) return;
-    // NS groups of kBpThreads threads share one tile; group gs takes angle
-    // chunks gs, gs + NS, ... and the groups' sums are added in a fixed order
-    // at the end.
     constexpr int NW = DUAL ? 2 : 1;
     constexpr int NE = kBpChunk * kBpWin / kBpThreads;   // staged bins per thread and sinogram
     __shared__ T win[NS][NW][kBpChunk * kBpWin];
@@ -470,7 +562,7 @@ __global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__rest
     const int gs = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBpThreads);
     const int t = threadIdx.x % kBpThreads;
     const int ty = t >> 3, tx = (t & 7) * 2;
-    const int i0 = blockIdx.y * kBpTile, j0 = blockIdx.x * kBpTile;
+    const int i0 = vb.y * kBpTile, j0 = vb.x * kBpTile;
     const double xc = ((double)j0 + 7.5) - G.h, yc = G.h - ((double)i0 + 7.5);
     const T dx = (T)((double)tx - 7.5), dy = (T)(7.5 - (double)ty);
     T acc0 = T(0), acc1 = T(0), bcc0 = T(0), bcc1 = T(0);
@@ -590,57 +682,103 @@ __global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__rest
     }
 
     const int i = i0 + ty, j = j0 + tx;
-    double d = 0.0;
+    double dsum = 0.0;
     if (gs == 0 && i < G.n) {
         const size_t p = (size_t)i * G.n + j;
         if (j < G.n) {
             out[p] = acc0;
             if (DUAL) out2[p] = bcc0;
-            if (mode == kRedDotGH) d += (double)(DUAL ? bcc0 : acc0) * (double)dotv[p];
-            else if (mode == kRedDotGG) d += (double)acc0 * (double)acc0;
+            if (dot == 1) dsum += (double)(DUAL ? bcc0 : acc0) * (double)dotv[p];
+            else if (dot == 2) dsum += (double)acc0 * (double)acc0;
         }
         if (j + 1 < G.n) {
             out[p + 1] = acc1;
             if (DUAL) out2[p + 1] = bcc1;
-            if (mode == kRedDotGH) d += (double)(DUAL ? bcc1 : acc1) * (double)dotv[p + 1];
-            else if (mode == kRedDotGG) d += (double)acc1 * (double)acc1;
+            if (dot == 1) dsum += (double)(DUAL ? bcc1 : acc1) * (double)dotv[p + 1];
+            else if (dot == 2) dsum += (double)acc1 * (double)acc1;
         }
     }
-    if (mode == kRedNone) return;
-    double v[1] = {d}, tot[1];
-    if (!reduce_finish(v, partials, counter, tot) || threadIdx.x != 0) return;
-    if (mode == kRedDotGH) st->gh = tot[0];
-    else st->gg = tot[0];
+    if (partials == nullptr || dot == 0) return;
+    double v[1] = {dsum};
+    block_store(v, partials + vb.id());
 }
 
-template <typename T, bool DUAL>
-void launch_bp_split(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out, T *out2,
-                     const T *dotv, double *partials, unsigned *counter, DevState *st, int mode,
-                     int split, hipStream_t s)
+template <typename T, int NS>
+__global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__restrict__ r, Geo G,
+                                                                  const BpAngle *__restrict__ ang,
+                                                                  T *__restrict__ out, int swz)
 {
-    dim3 grid((G.n + kBpTile - 1) / kBpTile, (G.n + kBpTile - 1) / kBpTile);
-    if (split >= 4)
-        hipLaunchKernelGGL((k_backproject<T, DUAL, 4>), grid, dim3(kBpThreads * 4), 0, s, r, r2, G,
-                           ang, out, out2, dotv, partials, counter, st, mode);
-    else if (split == 2)
-        hipLaunchKernelGGL((k_backproject<T, DUAL, 2>), grid, dim3(kBpThreads * 2), 0, s, r, r2, G,
-                           ang, out, out2, dotv, partials, counter, st, mode);
-    else
-        hipLaunchKernelGGL((k_backproject<T, DUAL, 1>), grid, dim3(kBpThreads), 0, s, r, r2, G,
-                           ang, out, out2, dotv, partials, counter, st, mode);
+    const int nt = (G.n + kBpTile - 1) / kBpTile;
+    backproject_body<T, false, NS>(r, nullptr, G, ang, out, nullptr, nullptr, 0, nullptr,
+                                   vblk_of(launch_index(swz), nt, nt));
 }
 
 template <typename T>
-void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,
-                        T *out2, const T *dotv, double *partials, unsigned *counter,
-                        DevState *st, int mode, int split, hipStream_t s)
+void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, T *out, int split, int swz,
+                        hipStream_t s)
 {
-    if (r2 != nullptr)
-        launch_bp_split<T, true>(r, r2, G, ang, out, out2, dotv, partials, counter, st, mode,
-                                 split, s);
+    const int nt = (G.n + kBpTile - 1) / kBpTile;
+    dim3 grid(nt * nt);
+    if (split >= 4)
+        hipLaunchKernelGGL((k_backproject<T, 4>), grid, dim3(kBpThreads * 4), 0, s, r, G, ang, out,
+                           swz);
+    else if (split == 2)
+        hipLaunchKernelGGL((k_backproject<T, 2>), grid, dim3(kBpThreads * 2), 0, s, r, G, ang, out,
+                           swz);
     else
-        launch_bp_split<T, false>(r, r2, G, ang, out, out2, dotv, partials, counter, st, mode,
-                                  split, s);
+        hipLaunchKernelGGL((k_backproject<T, 1>), grid, dim3(kBpThreads), 0, s, r, G, ang, out,
+                           swz);
+}
+
+template <typename T, bool DUAL, int NS>
+__global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T> *S,
+                                                                   const BlkMap *map, int phase,
+                                                                   int dot, int swz)
+{
+    const BlkMap m = locate(map, swz);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    // descriptor fields into registers: the body's stores cannot alias them
+    const Geo G = d.G;
+    const BpAngle *ang = d.bang;
+    const int nt = (G.n + kBpTile - 1) / kBpTile;
+    const VBlk vb = vblk_of(m.local, nt, nt);
+    if (phase == kBpH) {
+        const T *src = d.q;
+        T *dst = d.h;
+        backproject_body<T, false, NS>(src, nullptr, G, ang, dst, nullptr, nullptr, 0, nullptr,
+                                       vb);
+    } else {   // kBpG, kBpGZ: g' = A^T r (and z' = A^T rt); dot against h or g'
+        const T *src = d.r, *src2 = d.rt, *dotv = d.h;
+        T *dst = d.g, *dst2 = d.z;
+        double *part = d.partials;
+        backproject_body<T, DUAL, NS>(src, src2, G, ang, dst, dst2, dotv, dot, part, vb);
+    }
+}
+
+template <typename T, bool DUAL>
+void launch_b_bp_split(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int dot,
+                       int split, int swz, hipStream_t s)
+{
+    if (split >= 4)
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 4>), dim3(nblocks), dim3(kBpThreads * 4), 0,
+                           s, S, map, phase, dot, swz);
+    else if (split == 2)
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 2>), dim3(nblocks), dim3(kBpThreads * 2), 0,
+                           s, S, map, phase, dot, swz);
+    else
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 1>), dim3(nblocks), dim3(kBpThreads), 0, s,
+                           S, map, phase, dot, swz);
+}
+
+template <typename T>
+void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int dot,
+                          int split, int swz, hipStream_t s)
+{
+    if (phase == kBpGZ)
+        launch_b_bp_split<T, true>(S, map, nblocks, phase, dot, split, swz, s);
+    else
+        launch_b_bp_split<T, false>(S, map, nblocks, phase, dot, split, swz, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,18 +822,17 @@ __device__ __forceinline__ T tv_pixel(const T (&X)[3][3], int i, int j, int n, T
     return sg;
 }
 
-// TV(x) into *tv_dst and optionally the subgradient (scg_tv, solver output).
+// TV(x) block partials and optionally the subgradient (grid-stride over the
+// image with the body's block count).
 template <typename T>
-__global__ __launch_bounds__(256) void k_tv(const T *__restrict__ x, T *__restrict__ s_out,
-                                             Geo G, double kappa, double *partials,
-                                             unsigned *counter, double *tv_dst)
+__device__ void tv_body(const T *__restrict__ x, T *__restrict__ s_out, const Geo &G, T k2,
+                        double *partials, VBlk vb)
 {
     const int n = G.n;
-    const T k2 = (T)(kappa * kappa);
     double tv = 0.0;
     const size_t J = (size_t)n * n;
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < J;
-         p += (size_t)gridDim.x * blockDim.x) {
+    for (size_t p = vb.id() * (size_t)blockDim.x + threadIdx.x; p < J;
+         p += (size_t)vb.count() * blockDim.x) {
         const int i = (int)(p / n), j = (int)(p % n);
         T X[3][3];
 #pragma unroll
@@ -710,40 +847,67 @@ __global__ __launch_bounds__(256) void k_tv(const T *__restrict__ x, T *__restri
         tv += (double)own;
         if (s_out != nullptr) s_out[p] = sg;
     }
-    double v[1] = {tv}, tot[1];
-    if (!reduce_finish(v, partials, counter, tot) || threadIdx.x != 0) return;
-    *tv_dst = tot[0];
+    double v[1] = {tv};
+    block_store(v, partials + vb.id());
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tv(const T *__restrict__ x, T *__restrict__ s_out, Geo G,
+                                             double kappa, double *partials)
+{
+    tv_body(x, s_out, G, (T)(kappa * kappa), partials, grid_vblk());
+}
+
+__global__ __launch_bounds__(256) void k_sum_to(const double *partials, int nblk, double *dst)
+{
+    __shared__ double tot[1];
+    final_sums(partials, nblk, 1, 1, tot);
+    if (threadIdx.x == 0) *dst = tot[0];
 }
 
 template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
-               unsigned *counter, double *tv_dst, hipStream_t s)
+               double *tv_dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tv<T>, dim3(vec_blocks((size_t)G.n * G.n)), dim3(kBlock), 0, s, x, s_out,
-                       G, kappa, partials, counter, tv_dst);
+    const int nb = vec_blocks((size_t)G.n * G.n);
+    hipLaunchKernelGGL(k_tv<T>, dim3(nb), dim3(kBlock), 0, s, x, s_out, G, kappa, partials);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, s, partials, nb, tv_dst);
+}
+
+// TV of every solve's output image (after the loop; runs whether or not the
+// solve stopped).
+template <typename T>
+__global__ __launch_bounds__(256) void kb_tv(const Solve<T> *S, const BlkMap *map)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    const T k2 = (T)(d.st->kappa * d.st->kappa);
+    tv_body<T>(d.xout, nullptr, d.G, k2, d.partials, vblk_of(m.local, d.nb_vec, 1));
+}
+
+template <typename T>
+void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_tv<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map);
 }
 
 // ---------------------------------------------------------------------------
 // Step boundary of the superiorized solvers, fused with the TV work that opens
 // the next step: x_{k+1} = x_{k+1/2} + alpha p' (the last line of the previous
 // step) on a 32 x 8 tile plus a one-pixel halo held in LDS, then the TV
-// subgradient s at x_{k+1}, ||s||^2 and TV(x_{k+1}). The last block closes the
-// previous step (k, the carried ||A p||^2 and g^T p), applies the iteration
-// cap, opens the new step (replayed decisions, trace) and prepares the first
-// pass of trials (v = -s/||s||, gamma0 a^(l+m)).
+// subgradient s at x_{k+1}; the block stores its parts of TV(x_{k+1}) and
+// ||s||^2. The finisher closes the previous step and opens the next.
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_xtv(const T *__restrict__ xh, const T *__restrict__ p,
-                                              T *__restrict__ x, T *__restrict__ s_out, Geo G,
-                                              double *partials, unsigned *counter, DevState *st,
-                                              const int32_t *forced, scg_trace_entry *trace)
+__device__ void xtv_body(const T *__restrict__ xh, const T *__restrict__ p, T *__restrict__ x,
+                         T *__restrict__ s_out, const Geo &G, double *partials,
+                         const DevState *st, VBlk vb)
 {
-    if (st->done) return;
     constexpr int TW = 32, TH = 8;
     __shared__ T tile[TH + 2][TW + 2];
     const int n = G.n;
-    const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
+    const int i0 = vb.y * TH, j0 = vb.x * TW;
     const T al = (T)st->alpha;
     const T k2 = (T)(st->kappa * st->kappa);
     for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
@@ -773,172 +937,103 @@ __global__ __launch_bounds__(256) void k_xtv(const T *__restrict__ xh, const T *
         tv = (double)own;
         ss = (double)sg * (double)sg;
     }
-    double v[2] = {tv, ss}, tot[2];
-    if (!reduce_finish(v, partials, counter, tot)) return;
-    __shared__ int s_go, s_ell;
-    if (threadIdx.x == 0) {
-        // close the previous step
-        st->qq_prev = st->qq;
-        st->gp_prev = st->gp;
-        st->k += 1;
-        st->steps += 1;
-        s_go = 0;
-        if (st->steps >= st->max_iter) {
-            set_done(st, SCG_ENOCONV);
-        } else {
-            // open step k: perturbed(x_k) starts here
-            const int k = st->k;
-            st->trials_step = 0;
-            st->accepted = -1;
-            st->gamma = 0.0;
-            st->search_done = (st->flags & SCG_FLAG_NO_PERTURB) ? 1 : 0;
-            st->tv_x = tot[0];
-            st->s_norm2 = tot[1];
-            const bool dir = tot[1] > 0.0 && isfinite(tot[1]);
-            st->inv_snorm = dir ? 1.0 / sqrt(tot[1]) : 0.0;
-            if (scg_trace_entry *tr = trace_at(st, trace, k)) {
-                tr->k = k;
-                tr->accepted = -1;
-                tr->trials = 0;
-                tr->ell = st->ell;
-                tr->gamma = 0.0;
-                tr->beta = 0.0;
-                tr->alpha = 0.0;
-                tr->tv_x = tot[0];
-                tr->f_half = 0.0;
-            }
-            if (!st->search_done && forced != nullptr && k - 1 < st->forced_len) {
-                const int nt = forced[2 * (k - 1)], am = forced[2 * (k - 1) + 1];
-                const int l0 = st->ell;
-                double g = 0.0;
-                if (am >= 0 && dir) {
-                    g = st->gamma0 * pow(st->a, (double)(l0 + am));
-                    g = st->is_f32 ? (double)(float)g : g;
-                }
-                st->ell = l0 + nt;
-                st->trials_step = nt;
-                st->trials_total += nt;
-                st->accepted = dir ? am : -1;
-                st->gamma = g;
-                st->search_done = 1;
-                if (scg_trace_entry *tr = trace_at(st, trace, k)) {
-                    tr->accepted = st->accepted;
-                    tr->trials = nt;
-                    tr->ell = st->ell;
-                    tr->gamma = g;
-                }
-            }
-            if (!st->search_done && !dir) {
-                // No nonascending direction: x_{k+1/2} = x_k and l is unchanged.
-                st->search_done = 1;
-            }
-            s_go = !st->search_done;
-            s_ell = st->ell;
-        }
-    }
-    __syncthreads();
-    if (s_go) fill_gammas(st, s_ell);
+    double v[2] = {tv, ss};
+    block_store(v, partials + 2 * (size_t)vb.id());
 }
 
 template <typename T>
-void launch_xtv(const T *xh, const T *p, T *x, T *s_out, const Geo &G, double *partials,
-                unsigned *counter, DevState *st, const int32_t *forced, scg_trace_entry *trace,
-                hipStream_t s)
+__global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *map)
 {
-    dim3 grid((G.n + 31) / 32, (G.n + 7) / 8);
-    hipLaunchKernelGGL(k_xtv<T>, grid, dim3(256), 0, s, xh, p, x, s_out, G, partials, counter, st,
-                       forced, trace);
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials, d.st,
+             vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
+}
+
+template <typename T>
+void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_xtv<T>, dim3(nblocks), dim3(256), 0, s, S, map);
 }
 
 // ---------------------------------------------------------------------------
-// perturbed(): one pass evaluates TV(x + gamma_m v) for kTrialsPerPass
-// successive values gamma_m = gamma0 a^(l+m), v = -s/||s||, together with
-// TV(x) summed in the same order; the last block takes the first m with
-// TV(x + gamma_m v) <= TV(x), exactly as trying them one after another.
+// perturbed(): the trials of one step, TV(x + gamma_m v) for gamma_m =
+// gtab[m] (gamma0 a^(l+m)) and v = -s/||s||, in two launches. The first
+// evaluates trials 0..kTrialsPerPass-1 together with TV(x), summed in the
+// same order; the second, which returns at once when the first accepted,
+// evaluates the remaining ones up to max_trials in chunks of kTrialsPerPass.
+// The finisher takes the first m with TV(x + gamma_m v) <= TV(x), exactly as
+// trying the values one after another; l advances by the trials used.
+// Partials per block: [TV(x), trial first_m, first_m + 1, ...].
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trials(const T *__restrict__ x, const T *__restrict__ s,
-                                                 Geo G, double *partials, unsigned *counter,
-                                                 DevState *st, scg_trace_entry *trace)
+__device__ void trials_body(const T *__restrict__ x, const T *__restrict__ s, const Geo &G,
+                            const double *__restrict__ gtab, double *partials,
+                            const DevState *st, int first_m, int nchunks, VBlk vb)
 {
-    if (st->done || st->search_done) return;
     constexpr int M = kTrialsPerPass;
-    T gam[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) gam[m] = (T)st->gam[m];
+    const int max_trials = st->max_trials;
+    const int stride = 1 + M * nchunks;
     const T inv = (T)st->inv_snorm;
     const T k2 = (T)(st->kappa * st->kappa);
     const int n = G.n, m1 = n - 1;
-    T acc[M + 1];
-#pragma unroll
-    for (int m = 0; m <= M; ++m) acc[m] = T(0);
     const size_t terms = (size_t)m1 * m1;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < terms;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q / m1), j = (int)(q % m1);
-        const size_t c = (size_t)i * n + j;
-        const T xc = x[c], xd = x[c + n], xr = x[c + 1];
-        const T vc = -s[c] * inv, vd = -s[c + n] * inv, vr = -s[c + 1] * inv;
-        acc[M] += tv_term(xd - xc, xr - xc, k2);
+    const int bid = vb.id(), nblk = vb.count();
+    const bool with_tvx = first_m == 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const int m0 = first_m + M * c;
+        T gam[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const T g = gam[m];
-            const T zc = fma(g, vc, xc), zd = fma(g, vd, xd), zr = fma(g, vr, xr);
-            acc[m] += tv_term(zd - zc, zr - zc, k2);
-        }
-    }
-    __shared__ double tot[M + 1];
-    if (!reduce_finish(acc, partials, counter, tot)) return;
-    __shared__ int s_more, s_ell;
-    if (threadIdx.x == 0) {
-        const double tvx = tot[M];
-        st->tv_x = tvx;
-        const int left = st->max_trials - st->trials_step;
-        const int nv = left < M ? left : M;
-        int hit = -1;
-        for (int m = 0; m < nv; ++m)
-            if (tot[m] <= tvx) {
-                hit = m;
-                break;
-            }
-        const int used = hit >= 0 ? hit + 1 : nv;
-        const int first = st->trials_step;
-        st->ell += used;
-        st->trials_step += used;
-        st->trials_total += used;
-        if (hit >= 0) {
-            st->accepted = first + hit;
-            st->gamma = (double)gam[hit];
-            st->search_done = 1;
-        } else if (st->trials_step >= st->max_trials) {
-            st->accepted = -1;
-            st->gamma = 0.0;
-            st->search_done = 1;
-        }
-        if (st->search_done) {
-            if (scg_trace_entry *tr = trace_at(st, trace, st->k)) {
-                tr->accepted = st->accepted;
-                tr->trials = st->trials_step;
-                tr->ell = st->ell;
-                tr->gamma = st->gamma;
-                tr->tv_x = tvx;
+        for (int m = 0; m < M; ++m) gam[m] = (T)gtab[min(m0 + m, max_trials - 1)];
+        T acc[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M; ++m) acc[m] = T(0);
+        for (size_t q = bid * (size_t)blockDim.x + threadIdx.x; q < terms;
+             q += (size_t)nblk * blockDim.x) {
+            const int i = (int)(q / m1), j = (int)(q % m1);
+            const size_t cq = (size_t)i * n + j;
+            const T xc = x[cq], xd = x[cq + n], xr = x[cq + 1];
+            const T vc = -s[cq] * inv, vd = -s[cq + n] * inv, vr = -s[cq + 1] * inv;
+            if (with_tvx && c == 0) acc[M] += tv_term(xd - xc, xr - xc, k2);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const T g = gam[m];
+                const T zc = fma(g, vc, xc), zd = fma(g, vd, xd), zr = fma(g, vr, xr);
+                acc[m] += tv_term(zd - zc, zr - zc, k2);
             }
         }
-        s_more = !st->search_done;
-        s_ell = st->ell;
+        double *dst = partials + (size_t)bid * stride;
+        if (c == 0) {
+            T tvx[1] = {acc[M]};
+            block_store(tvx, dst);
+        }
+        T tr[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) tr[m] = acc[m];
+        block_store(tr, dst + 1 + M * c);
     }
-    __syncthreads();
-    if (s_more) fill_gammas(st, s_ell);
 }
 
 template <typename T>
-void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsigned *counter,
-                   DevState *st, scg_trace_entry *trace, hipStream_t stream)
+__global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap *map,
+                                                  int first_m)
 {
-    size_t terms = (size_t)(G.n - 1) * (G.n - 1);
-    hipLaunchKernelGGL(k_trials<T>, dim3(vec_blocks(terms)), dim3(kBlock), 0, stream, x, s, G,
-                       partials, counter, st, trace);
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (d.st->done || d.st->search_done) return;
+    const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
+    const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
+    trials_body(d.x, d.s, d.G, d.gtab, d.partials, d.st, first_m, nchunks,
+                vblk_of(m.local, nblk, 1));
+}
+
+template <typename T>
+void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_trials<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map, first_m);
 }
 
 // ---------------------------------------------------------------------------
@@ -954,16 +1049,15 @@ void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsig
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_perturb(const T *__restrict__ x, const T *__restrict__ s,
-                                                  T *__restrict__ xh, T *__restrict__ xht, Geo G,
-                                                  DevState *st)
+__device__ void perturb_body(const T *__restrict__ x, const T *__restrict__ s,
+                             T *__restrict__ xh, T *__restrict__ xht, const Geo &G,
+                             const DevState *st, VBlk vb)
 {
-    if (st->done) return;
     __shared__ T tile[32][33];
     const bool move = st->accepted >= 0 && st->gamma != 0.0;
     const T g = (T)st->gamma, inv = (T)st->inv_snorm;
     const int n = G.n;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, j = bx + tx;
@@ -984,32 +1078,39 @@ __global__ __launch_bounds__(256) void k_perturb(const T *__restrict__ x, const 
 }
 
 template <typename T>
-void launch_perturb(const T *x, const T *s, T *xh, T *xht, const Geo &G, DevState *st,
-                    hipStream_t stream)
+__global__ __launch_bounds__(256) void kb_perturb(const Solve<T> *S, const BlkMap *map)
 {
-    dim3 grid((G.n + 31) / 32, (G.n + 31) / 32);
-    hipLaunchKernelGGL(k_perturb<T>, grid, dim3(256), 0, stream, x, s, xh, xht, G, st);
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    const int nt = (d.G.n + 31) / 32;
+    perturb_body(d.x, d.s, d.xh, d.xs, d.G, d.st, vblk_of(m.local, nt, nt));
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_p_update(const T *__restrict__ g, const T *__restrict__ z,
-                                                   T *__restrict__ p, T *__restrict__ pt, Geo G,
-                                                   double *partials, unsigned *counter,
-                                                   DevState *st, int rule, int init,
-                                                   scg_trace_entry *trace)
+void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
 {
-    if (st->done) return;
+    hipLaunchKernelGGL(kb_perturb<T>, dim3(nblocks), dim3(256), 0, s, S, map);
+}
+
+__device__ __forceinline__ double beta_of(const DevState *st, int rule, int init)
+{
+    if (init) return 0.0;
+    if (rule == 0 || rule == 2) return st->gh / st->qq_prev;
+    if (rule == 1) return -st->gg / st->gp_prev;
+    return st->gg / st->delta;
+}
+
+template <typename T>
+__device__ void p_update_body(const T *__restrict__ g, const T *__restrict__ z,
+                              T *__restrict__ p, T *__restrict__ pt, const Geo &G,
+                              double *partials, const DevState *st, int rule, int init, VBlk vb)
+{
     __shared__ T tile[32][33];
-    double beta = 0.0;
-    if (!init) {
-        if (rule == 0 || rule == 2) beta = st->gh / st->qq_prev;
-        else if (rule == 1) beta = -st->gg / st->gp_prev;
-        else beta = st->gg / st->delta;
-    }
-    const T bt = (T)beta;
+    const T bt = (T)beta_of(st, rule, init);
     const T *src = (rule == 2) ? z : g;
     const int n = G.n;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double acc = 0.0;
     for (int r = ty; r < 32; r += 8) {
@@ -1024,78 +1125,59 @@ __global__ __launch_bounds__(256) void k_p_update(const T *__restrict__ g, const
         tile[r][tx] = pn;
     }
     __syncthreads();
-    if (pt != nullptr) {
-        for (int r = ty; r < 32; r += 8) {
-            const int j = bx + r, i = by + tx;
-            if (i < n && j < n) pt[(size_t)j * n + i] = tile[tx][r];
-        }
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (i < n && j < n) pt[(size_t)j * n + i] = tile[tx][r];
     }
-    double v[1] = {acc}, tot[1];
-    if (!reduce_finish(v, partials, counter, tot) || threadIdx.x != 0) return;
-    st->beta = beta;
-    st->gp = tot[0];
-    if (rule == 3) st->delta = st->gg;
-    if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
-    if (!init)
-        if (scg_trace_entry *tr = trace_at(st, trace, st->k)) tr->beta = beta;
+    double v[1] = {acc};
+    block_store(v, partials + vb.id());
 }
 
 template <typename T>
-void launch_p_update(const T *g, const T *z, T *p, T *pt, const Geo &G, double *partials,
-                     unsigned *counter, DevState *st, int rule, int init,
-                     scg_trace_entry *trace, hipStream_t s)
+__global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkMap *map,
+                                                    int rule, int init)
 {
-    dim3 grid((G.n + 31) / 32, (G.n + 31) / 32);
-    hipLaunchKernelGGL(k_p_update<T>, grid, dim3(256), 0, s, g, z, p, pt, G, partials, counter,
-                       st, rule, init, trace);
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    const int nt = (d.G.n + 31) / 32;
+    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials, d.st, rule, init,
+                  vblk_of(m.local, nt, nt));
+}
+
+template <typename T>
+void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init);
 }
 
 // Plain CG (Alg. CG, CG-STEP): x' = x + alpha p and the recursive gradient
-// g' = g + alpha h with ||g'||^2; closes the step.
+// g' = g + alpha h with the partials of ||g'||^2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_x_update_cg(T *__restrict__ x, const T *__restrict__ p,
-                                                      const T *__restrict__ h, T *__restrict__ g,
-                                                      size_t J, DevState *st, double *partials,
-                                                      unsigned *counter)
+__global__ __launch_bounds__(256) void kb_x_update_cg(const Solve<T> *S, const BlkMap *map)
 {
-    if (st->done) return;
-    const T al = (T)st->alpha;
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    const T al = (T)d.st->alpha;
+    const size_t J = (size_t)d.G.n * d.G.n;
     double acc = 0.0;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < J;
-         q += (size_t)gridDim.x * blockDim.x) {
-        x[q] = fma(al, p[q], x[q]);
-        const T gn = fma(al, h[q], g[q]);
-        g[q] = gn;
+    for (size_t q = m.local * (size_t)blockDim.x + threadIdx.x; q < J;
+         q += (size_t)d.nb_vec * blockDim.x) {
+        d.x[q] = fma(al, d.p[q], d.x[q]);
+        const T gn = fma(al, d.h[q], d.g[q]);
+        d.g[q] = gn;
         acc += (double)gn * (double)gn;
     }
-    double v[1] = {acc}, tot[1];
-    if (!reduce_finish(v, partials, counter, tot) || threadIdx.x != 0) return;
-    st->gg = tot[0];
-    st->qq_prev = st->qq;
-    st->k += 1;
-    st->steps += 1;
+    double v[1] = {acc};
+    block_store(v, d.partials + m.local);
 }
 
 template <typename T>
-void launch_x_update_cg(T *x, const T *p, const T *h, T *g, const Geo &G, DevState *st,
-                        double *partials, unsigned *counter, hipStream_t s)
+void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
 {
-    size_t J = (size_t)G.n * G.n;
-    hipLaunchKernelGGL(k_x_update_cg<T>, dim3(vec_blocks(J)), dim3(kBlock), 0, s, x, p, h, g, J,
-                       st, partials, counter);
-}
-
-// Plain CG: the iteration cap at the top of the loop.
-__global__ void k_iter_begin(DevState *st)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (st->done) return;
-    if (st->steps >= st->max_iter) set_done(st, SCG_ENOCONV);
-}
-
-void launch_iter_begin(DevState *st, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(kb_x_update_cg<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,15 +1189,13 @@ void launch_iter_begin(DevState *st, hipStream_t s)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__restrict__ out,
-                                                 const T *__restrict__ kern, Geo G,
-                                                 int out_padded, const DevState *st)
+__device__ void filter_body(const T *__restrict__ r, T *__restrict__ out,
+                            const T *__restrict__ kern, const Geo &G, int out_padded, int a)
 {
-    if (stopped(st)) return;
     extern __shared__ unsigned char smem[];
     T *row = reinterpret_cast<T *>(smem);
     T *kk = row + G.nb;                  // kk[d + nb - 1] = k[|d|], d in (-nb, nb)
-    const int a = blockIdx.x, nb = G.nb;
+    const int nb = G.nb;
     const T *ra = r + (size_t)a * G.rs + kSinoPadL;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) row[b] = ra[b];
     for (int d = threadIdx.x; d < 2 * nb - 1; d += blockDim.x) {
@@ -1143,42 +1223,305 @@ __global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__re
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__restrict__ out,
+                                                 const T *__restrict__ kern, Geo G,
+                                                 int out_padded)
+{
+    filter_body(r, out, kern, G, out_padded, (int)blockIdx.x);
+}
+
+template <typename T>
 void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
-                   const DevState *st, hipStream_t s)
+                   hipStream_t s)
 {
     size_t shm = (size_t)(3 * G.nb) * sizeof(T);
-    hipLaunchKernelGGL(k_filter<T>, dim3(G.na), dim3(256), shm, s, r, out, kernel, G, out_padded,
-                       st);
+    hipLaunchKernelGGL(k_filter<T>, dim3(G.na), dim3(256), shm, s, r, out, kernel, G, out_padded);
+}
+
+// r~ = F^T C F r of every solve (rt, padded), one block per angle.
+template <typename T>
+__global__ __launch_bounds__(256) void kb_filter(const Solve<T> *S, const BlkMap *map)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> &d = S[m.solve];
+    if (stopped(d.st)) return;
+    filter_body(d.r, d.rt, d.kern, d.G, 1, m.local);
+}
+
+template <typename T>
+void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
+                     hipStream_t s)
+{
+    size_t shm = (size_t)(3 * max_nb) * sizeof(T);
+    hipLaunchKernelGGL(kb_filter<T>, dim3(nblocks), dim3(256), shm, s, S, map);
+}
+
+// ---------------------------------------------------------------------------
+// Finishers: block b serves solve b. Each sums the partials of the launch
+// before it (fixed order) and applies that phase's scalar logic; a finisher
+// whose launch did not run (the solve had stopped, the trials were over)
+// leaves the state alone.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
+{
+    const Solve<T> &d = S[blockIdx.x];
+    DevState *st = d.st;
+    __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
+    __shared__ int s_go, s_ell;
+
+    if (fin == kFinTV) {
+        final_sums(d.partials, d.nb_vec, 1, 1, tot);
+        if (threadIdx.x == 0) *d.tvd = tot[0];
+        return;
+    }
+    if (st->done) return;
+    if (fin == kFinCGCap) {
+        if (threadIdx.x == 0 && st->steps >= st->max_iter) set_done(st, SCG_ENOCONV);
+        return;
+    }
+
+    switch (fin) {
+    case kFinResidual:
+    case kFinResidualStep: {
+        final_sums(d.partials, d.nb_pj, 1, 1, tot);
+        if (threadIdx.x != 0) return;
+        const double f = 0.5 * tot[0];
+        st->f_half = f;
+        if (fin == kFinResidualStep)
+            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->f_half = f;
+        if (!isfinite(f)) {
+            set_done(st, SCG_ENAN);
+        } else if (f <= st->eps) {
+            // Inside a step, the next loop test f(x_{k+1/2}) <= eps ends the
+            // solve at k+1 with output x_{k+1/2}; the rest of the step is not
+            // needed for the output and is skipped.
+            if (fin == kFinResidualStep) {
+                st->steps += 1;
+                st->k += 1;
+            }
+            set_done(st, SCG_OK);
+        }
+        return;
+    }
+    case kFinNormQ:
+    case kFinNormQCG: {
+        final_sums(d.partials, d.nb_pj, 1, 1, tot);
+        if (threadIdx.x != 0) return;
+        const double s = tot[0];
+        st->qq = s;
+        if (!isfinite(s)) {
+            set_done(st, SCG_ENAN);
+        } else if (s == 0.0) {
+            set_done(st, SCG_EBREAKDOWN);
+        } else {
+            st->alpha = (fin == kFinNormQCG) ? st->delta / s : -st->gp / s;
+            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->alpha = st->alpha;
+        }
+        return;
+    }
+    case kFinDotGH:
+    case kFinDotGG: {
+        final_sums(d.partials, d.nb_bp, 1, 1, tot);
+        if (threadIdx.x != 0) return;
+        if (fin == kFinDotGH) st->gh = tot[0];
+        else st->gg = tot[0];
+        return;
+    }
+    case kFinPUpdate: {
+        // arg0 = rule, arg1 = init
+        final_sums(d.partials, d.nb_t32, 1, 1, tot);
+        if (threadIdx.x != 0) return;
+        const double beta = beta_of(st, arg0, arg1);
+        st->beta = beta;
+        st->gp = tot[0];
+        if (arg0 == 3) st->delta = st->gg;
+        if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
+        if (!arg1)
+            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->beta = beta;
+        return;
+    }
+    case kFinXUpdateCG: {
+        final_sums(d.partials, d.nb_vec, 1, 1, tot);
+        if (threadIdx.x != 0) return;
+        st->gg = tot[0];
+        st->qq_prev = st->qq;
+        st->k += 1;
+        st->steps += 1;
+        return;
+    }
+    case kFinTrials: {
+        // arg0 = first trial of the launch (0 or kTrialsPerPass)
+        const int first_m = arg0;
+        if (st->search_done) return;
+        const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
+        if (nchunks <= 0) return;
+        const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
+        const int stride = 1 + kTrialsPerPass * nchunks;
+        final_sums(d.partials, nblk, stride, stride, tot);
+        if (threadIdx.x != 0) return;
+        const bool with_tvx = first_m == 0;
+        const double tvx = with_tvx ? tot[0] : st->tv_x;
+        if (with_tvx) st->tv_x = tvx;
+        const int left = st->max_trials - first_m;
+        const int cap = kTrialsPerPass * nchunks;
+        const int nv = left < cap ? left : cap;
+        int hit = -1;
+        for (int m = 0; m < nv; ++m)
+            if (tot[1 + m] <= tvx) {
+                hit = m;
+                break;
+            }
+        const int used = hit >= 0 ? hit + 1 : nv;
+        st->ell += used;
+        st->trials_step += used;
+        st->trials_total += used;
+        if (hit >= 0) {
+            st->accepted = first_m + hit;
+            st->gamma = d.gtab[first_m + hit];
+            st->search_done = 1;
+        } else if (st->trials_step >= st->max_trials) {
+            st->accepted = -1;
+            st->gamma = 0.0;
+            st->search_done = 1;
+        }
+        if (st->search_done) {
+            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) {
+                tr->accepted = st->accepted;
+                tr->trials = st->trials_step;
+                tr->ell = st->ell;
+                tr->gamma = st->gamma;
+                tr->tv_x = tvx;
+            }
+        }
+        return;
+    }
+    case kFinXtv: {
+        // Closes the previous step (k, the carried ||A p||^2 and g^T p),
+        // applies the iteration cap, opens the new step (TV(x_k), v =
+        // -s/||s||, replayed decisions, trace) and fills the trials' table.
+        final_sums(d.partials, d.nb_xtv, 2, 2, tot);
+        if (threadIdx.x == 0) {
+            st->qq_prev = st->qq;
+            st->gp_prev = st->gp;
+            st->k += 1;
+            st->steps += 1;
+            s_go = 0;
+            if (st->steps >= st->max_iter) {
+                set_done(st, SCG_ENOCONV);
+            } else {
+                const int k = st->k;
+                st->trials_step = 0;
+                st->accepted = -1;
+                st->gamma = 0.0;
+                st->search_done = (st->flags & SCG_FLAG_NO_PERTURB) ? 1 : 0;
+                st->tv_x = tot[0];
+                st->s_norm2 = tot[1];
+                const bool dir = tot[1] > 0.0 && isfinite(tot[1]);
+                st->inv_snorm = dir ? 1.0 / sqrt(tot[1]) : 0.0;
+                if (scg_trace_entry *tr = trace_at(st, d.trace, k)) {
+                    tr->k = k;
+                    tr->accepted = -1;
+                    tr->trials = 0;
+                    tr->ell = st->ell;
+                    tr->gamma = 0.0;
+                    tr->beta = 0.0;
+                    tr->alpha = 0.0;
+                    tr->tv_x = tot[0];
+                    tr->f_half = 0.0;
+                }
+                if (!st->search_done && d.forced != nullptr && k - 1 < st->forced_len) {
+                    const int nt = d.forced[2 * (k - 1)], am = d.forced[2 * (k - 1) + 1];
+                    const int l0 = st->ell;
+                    double g = 0.0;
+                    if (am >= 0 && dir) {
+                        g = st->gamma0 * pow(st->a, (double)(l0 + am));
+                        g = st->is_f32 ? (double)(float)g : g;
+                    }
+                    st->ell = l0 + nt;
+                    st->trials_step = nt;
+                    st->trials_total += nt;
+                    st->accepted = dir ? am : -1;
+                    st->gamma = g;
+                    st->search_done = 1;
+                    if (scg_trace_entry *tr = trace_at(st, d.trace, k)) {
+                        tr->accepted = st->accepted;
+                        tr->trials = nt;
+                        tr->ell = st->ell;
+                        tr->gamma = g;
+                    }
+                }
+                if (!st->search_done && !dir) {
+                    // No nonascending direction: x_{k+1/2} = x_k and l is unchanged.
+                    st->search_done = 1;
+                }
+                s_go = !st->search_done;
+                s_ell = st->ell;
+            }
+        }
+        __syncthreads();
+        if (s_go) fill_gtab(d.gtab, st, s_ell);
+        return;
+    }
+    default:
+        return;
+    }
+}
+
+template <typename T>
+void launch_finish(const Solve<T> *S, int ns, int fin, int arg0, int arg1, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_finish<T>, dim3(ns), dim3(kBlock), 0, s, S, fin, arg0, arg1);
+}
+
+// Copies every solve's state and output TV into compact arrays for one
+// read-back.
+template <typename T>
+__global__ void kb_gather(const Solve<T> *S, int ns, DevState *out, double *tv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    out[i] = *S[i].st;
+    tv[i] = *S[i].tvd;
+}
+
+template <typename T>
+void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_gather<T>, dim3((ns + 63) / 64), dim3(64), 0, s, S, ns, out, tv);
 }
 
 // ---- explicit instantiations ----------------------------------------------
 #define SCG_INST(T)                                                                            \
     template void launch_fill<T>(T *, size_t, T, hipStream_t);                                 \
     template void launch_copy<T>(T *, const T *, size_t, const DevState *, hipStream_t);       \
-    template void launch_stage<T>(const T *, T *, const Geo &, const DevState *, hipStream_t); \
-    template void launch_project<T>(const T *, const T *, const Geo &, const ProjTables &,      \
-                                    const T *, int, T *, int, int, double *, unsigned *,        \
-                                    DevState *, int, scg_trace_entry *, int, hipStream_t);      \
+    template void launch_stage<T>(const T *, T *, const Geo &, hipStream_t);                   \
+    template void launch_project<T>(const T *, const T *, const Geo &, const ProjTables &, T *, \
+                                    int, int, int, int, hipStream_t);                           \
     template void launch_pad_sino<T>(const T *, T *, const Geo &, hipStream_t);                \
-    template void launch_backproject<T>(const T *, const T *, const Geo &, const BpAngle *,    \
-                                        T *, T *, const T *, double *, unsigned *, DevState *, \
-                                        int, int, hipStream_t);                                 \
-    template void launch_tv<T>(const T *, T *, const Geo &, double, double *, unsigned *,      \
-                               double *, hipStream_t);                                          \
-    template void launch_xtv<T>(const T *, const T *, T *, T *, const Geo &, double *,         \
-                                unsigned *, DevState *, const int32_t *, scg_trace_entry *,     \
-                                hipStream_t);                                                   \
-    template void launch_trials<T>(const T *, const T *, const Geo &, double *, unsigned *,    \
-                                   DevState *, scg_trace_entry *, hipStream_t);                 \
-    template void launch_perturb<T>(const T *, const T *, T *, T *, const Geo &, DevState *,   \
-                                    hipStream_t);                                               \
-    template void launch_p_update<T>(const T *, const T *, T *, T *, const Geo &, double *,    \
-                                     unsigned *, DevState *, int, int, scg_trace_entry *,      \
-                                     hipStream_t);                                              \
-    template void launch_x_update_cg<T>(T *, const T *, const T *, T *, const Geo &,           \
-                                        DevState *, double *, unsigned *, hipStream_t);        \
-    template void launch_filter<T>(const T *, T *, const T *, const Geo &, int,                \
-                                   const DevState *, hipStream_t);
+    template void launch_backproject<T>(const T *, const Geo &, const BpAngle *, T *, int, int, \
+                                        hipStream_t);                                           \
+    template void launch_tv<T>(const T *, T *, const Geo &, double, double *, double *,        \
+                               hipStream_t);                                                    \
+    template void launch_filter<T>(const T *, T *, const T *, const Geo &, int, hipStream_t);  \
+    template void launch_b_stage<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t);  \
+    template void launch_b_project<T>(const Solve<T> *, const BlkMap *, int, int, int, int,    \
+                                      int, hipStream_t);                                        \
+    template void launch_b_backproject<T>(const Solve<T> *, const BlkMap *, int, int, int,     \
+                                          int, int, hipStream_t);                               \
+    template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);         \
+    template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
+    template void launch_b_perturb<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);     \
+    template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int,        \
+                                       hipStream_t);                                            \
+    template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
+    template void launch_b_filter<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
+    template void launch_b_copy_out<T>(const Solve<T> *, const BlkMap *, int, int,             \
+                                       hipStream_t);                                            \
+    template void launch_b_tv<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);          \
+    template void launch_finish<T>(const Solve<T> *, int, int, int, int, hipStream_t);        \
+    template void launch_gather<T>(const Solve<T> *, int, DevState *, double *, hipStream_t);
 
 SCG_INST(float)
 SCG_INST(double)

@@ -1,0 +1,94 @@
+// Host-side plan object and helpers shared by the C-ABI files of libscg.
+#pragma once
+
+#include <climits>
+#include <cstdint>
+#include <vector>
+
+#include "scg_internal.h"
+
+using scg::BpAngle;
+using scg::DevState;
+using scg::Geo;
+using scg::PjGroup;
+using scg::ProjAngle;
+using scg::ProjTables;
+
+struct scg_plan {
+    int device = 0;
+    Geo G{};
+    std::vector<double> cosv, sinv;
+    ProjAngle *pang = nullptr;
+    BpAngle *bang = nullptr;
+    PjGroup *pgroups[2] = {nullptr, nullptr};
+    int *pwin[2] = {nullptr, nullptr};
+    ProjTables ptab[2] = {};              // projector tables, 8 and 4 angles per group
+    void *xs[2] = {nullptr, nullptr};     // transposed-image scratch per precision
+    void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision
+    double *partials = nullptr;           // standalone TV partials
+    double *tvbuf = nullptr;
+    void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
+    scg_tuning tune[2] = {{4, 4, 8, 0}, {4, 2, 8, 0}};  // launch shapes (F32, F64)
+    double kern_mu = -1.0;
+    // kernel timing (scg_profile): HIP events around launches of chosen classes
+    struct ProfRec {
+        int cls;
+        int iter;   // loop iteration that enqueued the launch (0: initial step)
+        hipEvent_t a, b;
+    };
+    uint32_t prof_mask = 0;
+    int prof_iter = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<ProfRec> prof_pending;
+    hipEvent_t prof_open[SCG_KC_COUNT] = {};
+    int64_t prof_count[SCG_KC_COUNT] = {};
+    double prof_ms[SCG_KC_COUNT] = {};
+    int64_t prof_tail_count[SCG_KC_COUNT] = {};
+    double prof_tail_ms[SCG_KC_COUNT] = {};
+};
+
+
+namespace scg {
+
+// Makes `dev` the current device for the scope.
+struct Device {
+    int prev = -1;
+    explicit Device(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~Device()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+template <typename T> inline int prec_index();
+template <> inline int prec_index<float>() { return 0; }
+template <> inline int prec_index<double>() { return 1; }
+
+// Filter taps of the S-PCG preconditioner for mu (<= 0: 2 pi / P) on the plan.
+int ensure_filter(scg_plan *p, double mu);
+
+// Kernel timing of scg_profile: event pairs around launches of timed classes.
+void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin);
+void prof_drain(scg_plan *p, int last_iter = INT_MAX);
+
+int check_params(const scg_params *pr);
+
+// Projector tables of a launch shape.
+inline const ProjTables &proj_tables(const scg_plan *p, const scg_tuning &t)
+{
+    return p->ptab[t.project_angles == 4 ? 1 : 0];
+}
+
+}  // namespace scg
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return SCG_EDEVICE;     \
+    } while (0)

@@ -20,11 +20,11 @@ constexpr int kPjBins = 128;
 constexpr int kPjBand = 16;
 constexpr int kPjWin = 256;
 constexpr int kPjGroup = 8;
-constexpr int kPjThreads = 256;
 constexpr int kWinSkip = -0x40000000;
-// Backprojector tiling: 16 x 16 pixel tiles, 128 threads (two adjacent
-// pixels each), angles staged in LDS in chunks of kBpChunk with a window of
-// kBpWin bins per angle around the tile centre's projection.
+// Backprojector tiling: 16 x 16 pixel tiles, groups of 128 threads (two
+// adjacent pixels each; 1, 2 or 4 groups per tile split the angles), angles
+// staged in LDS in chunks of kBpChunk with a window of kBpWin bins per angle
+// around the tile centre's projection.
 constexpr int kBpTile = 16;
 constexpr int kBpThreads = 128;
 constexpr int kBpChunk = 32;
@@ -35,11 +35,10 @@ constexpr int kBpHalf = 15;       // window start = floor(centre projection) - k
 constexpr int kSinoPadL = 1;
 constexpr int kSinoPadR = 3;
 
-constexpr int kTrialsPerPass = 16;   // TV trials evaluated per pass of perturbed()
-constexpr int kMaxPartials = 16384;  // block partials per reduction (max blocks x values)
-constexpr int kRedGroups = 32;       // first-level arrival counters of a reduction
-constexpr int kRedStride = 64;       // counters are 256 bytes apart
-constexpr int kCounterBytes = (kRedGroups + 1) * kRedStride * 4;
+constexpr int kTrialsPerPass = 16;   // TV trials evaluated per chunk of perturbed()
+constexpr int kMaxTrials = 1024;     // cap on max_trials
+constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPass;
+constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
 
 struct Geo {
     int n, na, nb;
@@ -69,12 +68,12 @@ struct PjGroup {
     int a0, count, major, pad;
 };
 
-// Device tables of the forward projector.
+// Device tables of the forward projector for one angle-group size.
 struct ProjTables {
     const ProjAngle *ang;
     const PjGroup *groups;
     const int *win;      // [group][chunk][band] window start column or kWinSkip
-    int n_groups, n_chunks, n_bands, pad;
+    int n_groups, n_chunks, n_bands, group_max;
 };
 
 // Pixel-driven frame of one angle: pixel centre projects to the bin coordinate
@@ -102,60 +101,128 @@ struct DevState {
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
     double tv_out;
-    double gam[16];     // gamma0 a^(l+m), m < kTrialsPerPass, for the next trial pass
     int is_f32, pad1;
 };
 
-enum RedMode : int {
-    kRedNone = 0,
-    kRedResidual = 1,   // f_half = 1/2 sum r^2, stop test (initial point / plain CG)
-    kRedResidualStep = 7,  // as kRedResidual inside a step; a stop closes the step
-    kRedNormQ = 2,      // qq = sum q^2, alpha = -gp / qq
-    kRedInitNormQ = 3,  // init: qq, alpha, qq_prev
-    kRedDotGH = 4,      // gh = sum g h
-    kRedDotGG = 5,      // gg = sum g g
-    kRedNormQCG = 6,    // plain CG: qq, alpha = delta / qq
+// Device descriptor of one solve: its geometry tables, the workspace
+// vectors and its state. Every solver kernel takes an array of these plus a
+// block map, so one launch advances one phase of every solve of a batch (a
+// single solve is a batch of one).
+template <typename T> struct Solve {
+    Geo G;
+    ProjTables P;
+    const BpAngle *bang;
+    const T *kern;              // filter taps (S-PCG)
+    const T *y;                 // data, n_angles x n_bins
+    T *x, *xh, *p, *g, *h, *s, *z;
+    T *r, *q, *rt;              // padded sinograms (row stride G.rs)
+    T *xs, *pt;                 // transposes of x_{k+1/2} (or x) and of p
+    T *xout;                    // caller's output image
+    double *partials;           // block partial sums of the last reduction
+    double *gtab;               // gamma0 a^(l+m), m < max_trials
+    double *tvd;                // TV of the output
+    DevState *st;
+    scg_trace_entry *trace;
+    const int32_t *forced;      // replayed decisions or null
+    int nb_xtv, nb_trA, nb_trB, nb_t32, nb_pj, nb_bp, nb_vec;
+    int trB_chunks;             // trial chunks of the second trial launch
 };
+
+// Block map entry of a batched launch: the solve and its local block index.
+struct BlkMap {
+    int solve, local;
+};
+
+// Phases of a solver iteration (which vectors a shared kernel body uses).
+enum Phase : int {
+    kPjResXh = 0,     // r = A x_{k+1/2} - y (S- variants)
+    kPjResX = 1,      // r = A x - y (CG)
+    kPjQ = 2,         // q = A p
+    kBpG = 3,         // g = A^T r
+    kBpGZ = 4,        // g = A^T r, z = A^T rt (S-PCG)
+    kBpH = 5,         // h = A^T q
+    kStageXh = 6,     // xs = x_{k+1/2}^T
+    kStageX = 7,      // xs = x^T
+};
+
+// Finishers: one block per solve sums the partials of the previous launch
+// in a fixed order and applies its scalar logic to the solve's state.
+enum Fin : int {
+    kFinResidual = 0,      // f = 1/2 ||r||^2, stop test (initial point / CG)
+    kFinResidualStep = 1,  // same inside an S- step; a stop closes the step
+    kFinNormQ = 2,         // ||q||^2, alpha = -g^T p / ||q||^2
+    kFinNormQCG = 3,       // ||q||^2, alpha = delta / ||q||^2
+    kFinDotGH = 4,         // g^T h
+    kFinDotGG = 5,         // ||g||^2
+    kFinXtv = 6,           // closes a step, opens the next (TV, ||s||, trials table)
+    kFinTrials = 7,        // picks the first accepted trial
+    kFinPUpdate = 8,       // beta and g^T p of the direction update
+    kFinXUpdateCG = 9,     // CG: ||g||^2 and the step count
+    kFinCGCap = 10,        // CG: iteration cap at the loop top
+    kFinTV = 11,           // TV of the output
+};
+
+// Block counts of the solver kernels for one solve.
+int blocks_xtv(const Geo &G);
+int blocks_t32(const Geo &G);
+int blocks_vec(size_t n);
+int blocks_trials(const Geo &G, int nchunks);
+int blocks_bp(const Geo &G);
 
 // ---- launchers (kernels.hip) -------------------------------------------
 template <typename T> void launch_fill(T *p, size_t n, T v, hipStream_t s);
 template <typename T> void launch_copy(T *dst, const T *src, size_t n, const DevState *st,
                                        hipStream_t s);
-template <typename T> void launch_stage(const T *x, T *xs, const Geo &G, const DevState *st,
-                                        hipStream_t s);
+
+// Standalone operators (explicit buffers, no solve state).
+template <typename T> void launch_stage(const T *x, T *xs, const Geo &G, hipStream_t s);
 template <typename T>
-void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, const T *y,
-                    int y_stride, T *out, int out_stride, int out_off, double *partials,
-                    unsigned *counter, DevState *st, int mode, scg_trace_entry *trace, int nq,
-                    hipStream_t s);
+void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, T *out,
+                    int out_stride, int out_off, int nq, int swz, hipStream_t s);
 template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
 template <typename T>
-void launch_backproject(const T *r, const T *r2, const Geo &G, const BpAngle *ang, T *out,
-                        T *out2, const T *dotv, double *partials, unsigned *counter,
-                        DevState *st, int mode, int split, hipStream_t s);
+void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, T *out, int split, int swz,
+                        hipStream_t s);
 template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
-               unsigned *counter, double *tv_dst, hipStream_t s);
-template <typename T>
-void launch_xtv(const T *xh, const T *p, T *x, T *s_out, const Geo &G, double *partials,
-                unsigned *counter, DevState *st, const int32_t *forced, scg_trace_entry *trace,
-                hipStream_t s);
-template <typename T>
-void launch_trials(const T *x, const T *s, const Geo &G, double *partials, unsigned *counter,
-                   DevState *st, scg_trace_entry *trace, hipStream_t stream);
-template <typename T>
-void launch_perturb(const T *x, const T *s, T *xh, T *xht, const Geo &G, DevState *st,
-                    hipStream_t stream);
-template <typename T>
-void launch_p_update(const T *g, const T *z, T *p, T *pt, const Geo &G, double *partials,
-                     unsigned *counter, DevState *st, int rule, int init,
-                     scg_trace_entry *trace, hipStream_t s);
-template <typename T>
-void launch_x_update_cg(T *x, const T *p, const T *h, T *g, const Geo &G, DevState *st,
-                        double *partials, unsigned *counter, hipStream_t s);
+               double *tv_dst, hipStream_t s);   // partials: vec_blocks(n^2) doubles
 template <typename T>
 void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
-                   const DevState *st, hipStream_t s);
-void launch_iter_begin(DevState *st, hipStream_t s);
+                   hipStream_t s);
+
+// Solver phases over `ns` solves (S: device array; map: device block map of
+// `nblocks` entries, or null when ns == 1 and the blocks are the solve's own).
+template <typename T>
+void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, hipStream_t s);
+template <typename T>
+void launch_b_project(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int nq,
+                      int ga, int swz, hipStream_t s);
+template <typename T>
+void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase,
+                          int dot, int split, int swz, hipStream_t s);
+template <typename T>
+void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+template <typename T>
+void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m,
+                     hipStream_t s);
+template <typename T>
+void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+template <typename T>
+void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
+                       hipStream_t s);
+template <typename T>
+void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+template <typename T>
+void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
+                     hipStream_t s);
+template <typename T>
+void launch_b_copy_out(const Solve<T> *S, const BlkMap *map, int nblocks, int from_xh,
+                       hipStream_t s);
+template <typename T>
+void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+template <typename T>
+void launch_finish(const Solve<T> *S, int ns, int fin, int arg0, int arg1, hipStream_t s);
+template <typename T>
+void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStream_t s);
 
 }  // namespace scg

@@ -53,7 +53,11 @@ class scg_kernel_time(C.Structure):
 
 
 class scg_tuning(C.Structure):
-    _fields_ = [("project_groups", C.c_int32), ("backproject_split", C.c_int32)]
+    _fields_ = [("project_groups", C.c_int32), ("backproject_split", C.c_int32),
+                ("project_angles", C.c_int32), ("swizzle", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 KERNEL_CLASSES = ("project", "backproject", "tv", "trials", "vector", "stage", "filter",
@@ -218,11 +222,11 @@ class Plan:
     def tuning(self, prec: int = SCG_F32) -> dict:
         t = scg_tuning()
         _check(lib.scg_plan_get_tuning(self._h, prec, C.byref(t)), "scg_plan_get_tuning")
-        return {"project_groups": t.project_groups, "backproject_split": t.backproject_split}
+        return t.as_dict()
 
     def set_tuning(self, prec: int = SCG_F32, project_groups: int = 4,
-                   backproject_split: int = 2):
-        t = scg_tuning(project_groups, backproject_split)
+                   backproject_split: int = 2, project_angles: int = 8, swizzle: int = 0):
+        t = scg_tuning(project_groups, backproject_split, project_angles, swizzle)
         _check(lib.scg_plan_set_tuning(self._h, prec, C.byref(t)), "scg_plan_set_tuning")
 
     def autotune(self, prec: int = SCG_F32, stream=None) -> dict:
@@ -230,7 +234,7 @@ class Plan:
         t = scg_tuning()
         _check(lib.scg_plan_autotune(self._h, prec, C.c_void_p(_stream_handle(stream)),
                                      C.byref(t)), "scg_plan_autotune")
-        return {"project_groups": t.project_groups, "backproject_split": t.backproject_split}
+        return t.as_dict()
 
     # -- kernel timing -----------------------------------------------------
     def profile(self, classes=()):
@@ -309,3 +313,125 @@ class Plan:
                                 "ell": e.ell, "f_half": e.f_half, "tv_x": e.tv_x,
                                 "gamma": e.gamma, "beta": e.beta, "alpha": e.alpha})
         return out, report, entries
+
+
+# ---------------------------------------------------------------------------
+# Batch engine (scg_batch_*)
+# ---------------------------------------------------------------------------
+
+class scg_batch_stats(C.Structure):
+    _fields_ = [("active", C.c_int32), ("slots", C.c_int32), ("groups", C.c_int32),
+                ("reserved", C.c_int32), ("arena_bytes", C.c_uint64),
+                ("arena_used", C.c_uint64), ("submitted", C.c_uint64),
+                ("retired", C.c_uint64), ("macro_steps", C.c_uint64),
+                ("graph_builds", C.c_uint64)]
+
+
+SCG_BATCH_NO_GRAPH = 1
+
+
+def _bind_batch(L):
+    vp = C.c_void_p
+    L.scg_batch_create.argtypes = [C.c_int, C.c_size_t, C.c_int, C.c_uint32, C.POINTER(vp)]
+    L.scg_batch_destroy.argtypes = [vp]
+    L.scg_batch_destroy.restype = None
+    L.scg_batch_submit.argtypes = [vp, vp, C.POINTER(scg_params), vp, vp, vp,
+                                   C.POINTER(C.c_uint64)]
+    L.scg_batch_step.argtypes = [vp, C.c_int]
+    L.scg_batch_poll.argtypes = [vp, C.c_uint64, C.POINTER(scg_report)]
+    L.scg_batch_cancel.argtypes = [vp, C.c_uint64]
+    L.scg_batch_get_stats.argtypes = [vp, C.POINTER(scg_batch_stats)]
+    L.scg_batch_stream.argtypes = [vp]
+    L.scg_batch_stream.restype = vp
+    for name in ("scg_batch_create", "scg_batch_submit", "scg_batch_step", "scg_batch_poll",
+                 "scg_batch_cancel", "scg_batch_get_stats"):
+        getattr(L, name).restype = C.c_int
+
+
+_bind_batch(lib)
+
+
+class Batch:
+    """Many resident solves advanced together (scg_batch_*). The tensors of a
+    submitted solve are kept referenced until its report has been polled."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, device: int = 0,
+                 graph: bool = True):
+        self.device = device
+        self._h = C.c_void_p()
+        flags = 0 if graph else SCG_BATCH_NO_GRAPH
+        _check(lib.scg_batch_create(device, int(arena_bytes), int(max_slots), flags,
+                                    C.byref(self._h)), "scg_batch_create")
+        self._keep = {}
+        self._stream = torch.cuda.ExternalStream(lib.scg_batch_stream(self._h),
+                                                 device=f"cuda:{device}")
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.scg_batch_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, plan: "Plan", y: torch.Tensor, params: scg_params,
+               x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+        """Admits a solve; returns (ticket, out) or None when the batch has no
+        free slot or arena room (SCG_EAGAIN)."""
+        if _prec_of(y) != params.prec:
+            raise ValueError("params.prec does not match the tensor dtype")
+        if out is None:
+            out = torch.empty(plan.J, dtype=y.dtype, device=y.device)
+        # y (and x0) come from torch's stream: order them before the batch's
+        self._stream.wait_stream(torch.cuda.current_stream(y.device))
+        t = C.c_uint64()
+        rc = lib.scg_batch_submit(self._h, plan._h, C.byref(params), _dev(y, plan.L, "y"),
+                                  _dev(x0, plan.J, "x0") if x0 is not None else None,
+                                  _dev(out, plan.J, "x_out"), C.byref(t))
+        if rc == SCG_EAGAIN:
+            return None
+        _check(rc, "scg_batch_submit")
+        self._keep[t.value] = (plan, y, x0, out)
+        return t.value, out
+
+    def step(self, iters: int = 1) -> int:
+        """Runs `iters` iterations of every active solve and retires the
+        finished ones; returns the number still active."""
+        rc = lib.scg_batch_step(self._h, int(iters))
+        if rc < 0:
+            raise ScgError(rc, "scg_batch_step")
+        return rc
+
+    def poll(self, ticket: int):
+        """The Report of a retired ticket (once), or None while it runs."""
+        rep = scg_report()
+        rc = lib.scg_batch_poll(self._h, int(ticket), C.byref(rep))
+        if rc == SCG_EINPROGRESS:
+            return None
+        _check(rc, "scg_batch_poll")
+        self._keep.pop(int(ticket), None)
+        return Report(rep.status, rep.k, rep.steps, rep.trials_total, rep.ell, rep.f_out,
+                      rep.tv_out)
+
+    def cancel(self, ticket: int):
+        _check(lib.scg_batch_cancel(self._h, int(ticket)), "scg_batch_cancel")
+        self._keep.pop(int(ticket), None)
+
+    def stats(self) -> dict:
+        s = scg_batch_stats()
+        _check(lib.scg_batch_get_stats(self._h, C.byref(s)), "scg_batch_get_stats")
+        return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}

@@ -1,0 +1,169 @@
+"""Serving loop and batched runs on top of the batch engine (scg_batch_*).
+
+A request is one reconstruction: a plan (geometry), a sinogram resident on
+the device, its stopping value eps and its perturbation scale gamma0. The
+served loop admits requests in arrival order as slots and arena memory free
+up (admission by workspace footprint, SCG_EAGAIN otherwise), advances every
+resident solve with `iters` iterations per engine step, and retires finished
+solves between steps; requests that arrive while others are on the device
+join them at the next step. The plain loop runs the same requests one at a
+time with scg_solve, in arrival order. Both report per-request latency
+(completion minus arrival, wall clock) and throughput.
+
+All the solver work runs in libscg; this module schedules and measures.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import scg
+
+
+@dataclass
+class Request:
+    rid: int
+    plan: "scg.Plan"
+    y: torch.Tensor
+    params: "scg.scg_params"
+    arrival: float = 0.0          # seconds after the start of the stream
+
+    @property
+    def n(self) -> int:
+        return self.plan.n
+
+
+class PlanCache:
+    """One plan per geometry (trig tables, projector windows, launch shapes
+    picked by the autotuner on first use)."""
+
+    def __init__(self, device: int = 0, autotune: bool = True):
+        self.device = device
+        self.autotune = autotune
+        self.plans = {}
+
+    def get(self, n: int, n_angles: int, n_bins: int) -> "scg.Plan":
+        key = (n, n_angles, n_bins)
+        if key not in self.plans:
+            p = scg.Plan(n, n_angles, n_bins, device=self.device)
+            if self.autotune:
+                p.autotune(scg.SCG_F32)
+            self.plans[key] = p
+        return self.plans[key]
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+        self.plans.clear()
+
+
+def make_request(rid: int, cache: PlanCache, y_np: np.ndarray, x_true_np: np.ndarray,
+                 n: int, n_angles: int, n_bins: int, rho: float = 0.05,
+                 max_iter: int = 500) -> Request:
+    """Device-resident request with eps = f(x_true) = 1/2 ||y - A x_true||^2
+    and gamma0 = rho ||x_1|| (x_1 the first CG iterate), both computed here
+    with the library, before any timing."""
+    dev = torch.device(f"cuda:{cache.device}")
+    plan = cache.get(n, n_angles, n_bins)
+    y = torch.tensor(np.ascontiguousarray(y_np).reshape(-1), dtype=torch.float32, device=dev)
+    xt = torch.tensor(np.ascontiguousarray(x_true_np).reshape(-1), dtype=torch.float32,
+                      device=dev)
+    res = plan.project(xt).double() - y.double()
+    eps = 0.5 * float((res * res).sum())
+    x1, _, _ = plan.solve(y, plan.params(eps=1e-30, gamma0=0.0, variant="CG", max_iter=1),
+                          trace=False)
+    gamma0 = rho * float(torch.linalg.vector_norm(x1.double()))
+    params = plan.params(eps=eps, gamma0=gamma0, variant="S_CG", prec=scg.SCG_F32,
+                         max_iter=max_iter)
+    return Request(rid, plan, y, params)
+
+
+@dataclass
+class Served:
+    latency_s: np.ndarray     # per request, completion - arrival
+    wall_s: float             # first arrival to last completion
+    reports: dict             # rid -> scg.Report
+    outputs: dict             # rid -> output tensor
+
+    @property
+    def recons_per_s(self) -> float:
+        return len(self.latency_s) / self.wall_s if self.wall_s > 0 else 0.0
+
+    def summary(self) -> dict:
+        lat = 1e3 * self.latency_s
+        return {"requests": int(len(lat)), "recons_per_s": self.recons_per_s,
+                "wall_s": self.wall_s,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99)),
+                               "mean": float(np.mean(lat))}}
+
+
+def serve_plain(requests: list, keep_outputs: bool = False) -> Served:
+    """One solve at a time (scg_solve), in arrival order; a solve starts at
+    its arrival or when the previous one ends, whichever is later."""
+    order = sorted(requests, key=lambda r: r.arrival)
+    ws = {}
+    lat, reports, outputs = [], {}, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in order:
+        now = time.perf_counter() - t0
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        key = id(r.plan)
+        need = r.plan.workspace_bytes(r.params)
+        if key not in ws or ws[key].numel() < need:
+            ws[key] = r.plan.workspace(r.params)
+        out, rep, _ = r.plan.solve(r.y, r.params, ws=ws[key], trace=False)
+        done = time.perf_counter() - t0
+        lat.append(done - r.arrival)
+        reports[r.rid] = rep
+        if keep_outputs:
+            outputs[r.rid] = out
+    wall = (time.perf_counter() - t0) - (order[0].arrival if order else 0.0)
+    return Served(np.asarray(lat), wall, reports, outputs)
+
+
+def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: int = 4,
+                  graph: bool = True, keep_outputs: bool = False) -> Served:
+    """Continuous batching on the batch engine: admit every arrived request
+    that fits (FIFO; a request that does not fit blocks the ones behind it),
+    run `iters` iterations of all resident solves, retire the finished ones,
+    repeat."""
+    order = sorted(requests, key=lambda r: r.arrival)
+    lat, reports, outputs = [], {}, {}
+    inflight = {}
+    nxt = 0
+    with scg.Batch(arena_bytes, max_slots=max_slots, graph=graph) as b:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while nxt < len(order) or inflight:
+            now = time.perf_counter() - t0
+            if not inflight and nxt < len(order) and order[nxt].arrival > now:
+                time.sleep(order[nxt].arrival - now)
+                now = time.perf_counter() - t0
+            while nxt < len(order) and order[nxt].arrival <= now:
+                r = order[nxt]
+                got = b.submit(r.plan, r.y, r.params)
+                if got is None:
+                    if not inflight:
+                        raise RuntimeError(f"request {r.rid} does not fit an empty batch")
+                    break
+                inflight[got[0]] = (r, got[1])
+                nxt += 1
+            b.step(iters)
+            for t in list(inflight):
+                rep = b.poll(t)
+                if rep is None:
+                    continue
+                r, out = inflight.pop(t)
+                lat.append(time.perf_counter() - t0 - r.arrival)
+                reports[r.rid] = rep
+                if keep_outputs:
+                    outputs[r.rid] = out
+        wall = (time.perf_counter() - t0) - (order[0].arrival if order else 0.0)
+    return Served(np.asarray(lat), wall, reports, outputs)

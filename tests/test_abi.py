@@ -30,7 +30,10 @@ def test_header_declares_the_api():
     for required in ("scg_plan_create", "scg_plan_destroy", "scg_workspace_bytes",
                      "scg_project", "scg_backproject", "scg_tv", "scg_filter", "scg_solve",
                      "scg_profile", "scg_profile_read", "scg_default_params", "scg_strerror",
-                     "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune"):
+                     "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune",
+                     "scg_batch_create", "scg_batch_destroy", "scg_batch_submit",
+                     "scg_batch_step", "scg_batch_poll", "scg_batch_cancel",
+                     "scg_batch_get_stats", "scg_batch_stream"):
         assert required in names
 
 
@@ -49,3 +52,7 @@ def test_host_only_entry_points(lib):
     assert lib.scg_project(None, 0, None, None, None) == -1
     lib.scg_plan_get_tuning.argtypes = [vp, C.c_int, vp]
     assert lib.scg_plan_get_tuning(None, 0, None) == -1
+    lib.scg_batch_step.argtypes = [vp, C.c_int]
+    assert lib.scg_batch_step(None, 1) == -1
+    lib.scg_batch_poll.argtypes = [vp, C.c_uint64, vp]
+    assert lib.scg_batch_poll(None, 1, None) == -1

@@ -1,0 +1,219 @@
+"""Batch engine (scg_batch_*): many resident solves of different sizes,
+precisions and variants advanced together with one launch per phase.
+
+Bar: every solve's output image and report are bitwise those of scg_solve on
+the same inputs with the same launch shapes (the batched kernels run the same
+per-solve arithmetic in the same order), alone or in a mix, with the HIP
+graph and without it, and across admissions and retirements while other
+solves run. One mixed batch is also checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import algorithms as alg
+from synth import make_workload, random_ellipses, rasterize, analytic_sinogram
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def scg():
+    from paper_1709_04912_amd import scg as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+# launch shapes per case (project_groups, backproject_split, project_angles,
+# swizzle): solves with different shapes run in different groups of a batch
+SHAPES = [(4, 4, 8, 0), (4, 2, 8, 0), (2, 1, 4, 1), (4, 4, 8, 0), (4, 4, 4, 1), (4, 4, 8, 1),
+          (2, 2, 8, 0)]
+
+# (n, n_angles, n_bins, variant, precision, seed)
+CASES = [
+    (32, 45, 49, "S_CG", "f32", 1),
+    (48, 60, 71, "S_CG", "f64", 2),
+    (40, 50, 61, "S_CG_CD", "f32", 3),
+    (32, 45, 49, "S_PCG", "f32", 4),
+    (36, 40, 55, "CG", "f32", 5),
+    (64, 90, 95, "S_CG", "f32", 6),
+    (24, 30, 37, "S_PCG", "f64", 7),
+]
+
+
+def _problem(oracle_lib, case):
+    n, na, nb, variant, prec, seed = case
+    rng = np.random.default_rng(seed)
+    ells = random_ellipses(rng, 6)
+    x_true = rasterize(ells, n, 2).reshape(-1)
+    y = analytic_sinogram(ells, n, na, nb).reshape(-1)
+    y = y + 0.01 * np.abs(y).max() * rng.standard_normal(y.size)
+    g = oracle_lib.Geometry(n, na, nb)
+    f_true = 0.5 * float(np.sum((g.project(x_true) - y) ** 2))
+    return y, 1.2 * f_true, 0.05 * float(np.linalg.norm(x_true))
+
+
+def _prepared(scg, torch, oracle_lib, cases):
+    out = []
+    for case, shape in zip(cases, SHAPES):
+        n, na, nb, variant, prec, seed = case
+        y, eps, gamma0 = _problem(oracle_lib, case)
+        dt = torch.float32 if prec == "f32" else torch.float64
+        plan = scg.Plan(n, na, nb)
+        plan.set_tuning(scg.SCG_F32 if prec == "f32" else scg.SCG_F64, *shape)
+        p = plan.params(eps=eps, gamma0=gamma0, variant=variant,
+                        prec=scg.SCG_F32 if prec == "f32" else scg.SCG_F64, max_iter=300)
+        out.append((case, plan, torch.tensor(y, dtype=dt, device="cuda"), p))
+    return out
+
+
+def _alone(items):
+    res = []
+    for case, plan, y, p in items:
+        x, rep, _ = plan.solve(y, p, trace=False)
+        res.append((x.clone(), rep))
+    return res
+
+
+def _same(rep_a, rep_b):
+    return (rep_a.status, rep_a.k, rep_a.steps, rep_a.trials_total, rep_a.ell, rep_a.f_out,
+            rep_a.tv_out) == (rep_b.status, rep_b.k, rep_b.steps, rep_b.trials_total,
+                              rep_b.ell, rep_b.f_out, rep_b.tv_out)
+
+
+def _run_batch(scg, items, graph, max_slots=64, iters=3, arena=1 << 30):
+    results = {}
+    with scg.Batch(arena, max_slots=max_slots, graph=graph) as b:
+        pending = list(range(len(items)))
+        tickets = {}
+        steps = 0
+        while pending or tickets:
+            while pending:
+                i = pending[0]
+                _, plan, y, p = items[i]
+                r = b.submit(plan, y, p)
+                if r is None:
+                    break
+                tickets[r[0]] = (i, r[1])
+                pending.pop(0)
+            b.step(iters)
+            steps += 1
+            assert steps < 10000
+            for t in list(tickets):
+                rep = b.poll(t)
+                if rep is not None:
+                    i, out = tickets.pop(t)
+                    results[i] = (out.clone(), rep)
+        stats = b.stats()
+    return results, stats
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_alone(scg, torch_mod, oracle_lib, graph):
+    torch = torch_mod
+    print(f"[batch] mixed batch graph={graph}", flush=True)
+    items = _prepared(scg, torch, oracle_lib, CASES)
+    alone = _alone(items)
+    got, stats = _run_batch(scg, items, graph)
+    assert stats["retired"] == len(items) and stats["active"] == 0
+    if graph:
+        assert stats["graph_builds"] >= 1
+    for i, (x, rep) in enumerate(alone):
+        xb, rb = got[i]
+        assert rep.status == scg.SCG_OK, (CASES[i], rep)
+        assert _same(rep, rb), (CASES[i], rep, rb)
+        assert torch.equal(x, xb), CASES[i]
+    for _, plan, _, _ in items:
+        plan.close()
+
+
+def test_continuous_admission(scg, torch_mod, oracle_lib):
+    """Three slots for seven solves: solves are admitted while others are on
+    the device and retire at different iterations; every result is the one
+    it has alone."""
+    torch = torch_mod
+    print("[batch] continuous admission", flush=True)
+    items = _prepared(scg, torch, oracle_lib, CASES)
+    alone = _alone(items)
+    got, stats = _run_batch(scg, items, graph=True, max_slots=3, iters=2)
+    assert stats["submitted"] == len(items) and stats["graph_builds"] >= 3
+    for i, (x, rep) in enumerate(alone):
+        xb, rb = got[i]
+        assert _same(rep, rb) and torch.equal(x, xb), CASES[i]
+    for _, plan, _, _ in items:
+        plan.close()
+
+
+def test_arena_admission_and_cancel(scg, torch_mod, oracle_lib):
+    torch = torch_mod
+    print("[batch] arena admission and cancel", flush=True)
+    items = _prepared(scg, torch, oracle_lib, CASES[:2])
+    (case0, plan0, y0, p0), (case1, plan1, y1, p1) = items
+    need = plan0.workspace_bytes(p0)
+    # room for one workspace only: the second submit waits for the first
+    with scg.Batch(need + 4096, max_slots=8) as b:
+        t0, out0 = b.submit(plan0, y0, p0)
+        assert b.submit(plan1, y1, p1) is None
+        assert b.poll(t0) is None
+        while b.step(4) > 0:
+            pass
+        rep0 = b.poll(t0)
+        assert rep0 is not None and rep0.status == scg.SCG_OK
+        x_alone, rep_alone, _ = plan0.solve(y0, p0, trace=False)
+        assert _same(rep0, rep_alone) and torch.equal(out0, x_alone)
+        # a ticket's report is delivered once
+        with pytest.raises(scg.ScgError):
+            b.poll(t0)
+        # cancel an active solve
+        t1, _ = b.submit(plan0, y0, p0)
+        b.cancel(t1)
+        with pytest.raises(scg.ScgError):
+            b.poll(t1)
+        assert b.stats()["active"] == 0 and b.stats()["arena_used"] == 0
+    with pytest.raises(scg.ScgError):
+        scg.Batch(1024, max_slots=0)
+    plan0.close()
+    plan1.close()
+
+
+def test_batch_against_oracle(scg, torch_mod, oracle_lib):
+    """Two 64 x 64 workloads in one batch (one with non-default launch
+    shapes) against the FP64 oracle: eps met, and relative L2 1e-4 whenever
+    the stopping k agrees (an FP32 rounding can flip a decision whose FP64
+    margin is tiny; the solver tests replay such decisions)."""
+    torch = torch_mod
+    import json
+    import os
+    gd = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "eps.json")))
+    items, refs = [], []
+    for seed in (0, 1):
+        w = make_workload(1, seed, supersample=2)
+        g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
+        prob = alg.Problem(g, w.y)
+        eps = 1.1 * gd[f"cfg1_s{seed}"]["eps0"]
+        gamma0 = 0.05 * gd[f"cfg1_s{seed}"]["x1_norm"]
+        ref = alg.scg(prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0), max_iter=1000)
+        plan = scg.Plan(w.n, w.n_angles, w.n_bins)
+        if seed == 1:
+            plan.set_tuning(scg.SCG_F32, 2, 2, 4, 1)
+        p = plan.params(eps=eps, gamma0=gamma0, max_iter=1000)
+        items.append(((w.n,), plan, torch.tensor(w.y.reshape(-1), dtype=torch.float32,
+                                                  device="cuda"), p))
+        refs.append((prob, ref, eps))
+    got, _ = _run_batch(scg, items, graph=True)
+    for i, (prob, ref, eps) in enumerate(refs):
+        x, rep = got[i]
+        xg = x.cpu().numpy().astype(np.float64)
+        rel = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x))
+        print(f"  seed {i}: k={rep.k} ref_k={ref.k} rel={rel:.2e}")
+        assert rep.status == scg.SCG_OK and rep.f_out <= eps
+        assert prob.f(xg) <= eps * (1 + 1e-5)
+        if rep.k == ref.k:
+            assert rel <= 1e-4
+    for _, plan, _, _ in items:
+        plan.close()

@@ -169,27 +169,33 @@ def test_errors(scg, torch_mod):
         assert e.value.status == scg.SCG_EINVAL
 
 
-SHAPES = [(pg, bs) for pg in (2, 4) for bs in (1, 2, 4)]
+ALL_SHAPES = [(pg, bs, ga, sw) for pg in (2, 4) for bs in (1, 2, 4) for ga in (8, 4)
+              for sw in (0, 1)]
+SHAPE_CASES = ([((128, 180, 183), sh) for sh in ALL_SHAPES]
+               + [(g, sh) for g in ((33, 45, 49), (100, 13, 200), (50, 7, 30))
+                  for sh in ((2, 1, 8, 0), (4, 4, 4, 1), (2, 2, 4, 1), (4, 2, 8, 1))])
 
 
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("geom", [(33, 45, 49), (128, 180, 183), (100, 13, 200)])
+@pytest.mark.parametrize("geom,shape", SHAPE_CASES)
 def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
-    """Every projector group count and backprojector angle split gives the
-    oracle's A and A^T (FP32 1e-5, FP64 1e-12, dual A^T of S-PCG included via
-    the solver tests) and is bitwise repeatable."""
+    """Every projector group count and angle-group size, backprojector angle
+    split and block order gives the oracle's A and A^T (FP32 1e-5, FP64
+    1e-12; the dual A^T of S-PCG is covered by the solver tests) and is
+    bitwise repeatable."""
     torch = torch_mod
     n, na, nb = geom
-    pg, bs = shape
-    print(f"[op shapes] geom={geom} project_groups={pg} backproject_split={bs}", flush=True)
+    pg, bs, ga, sw = shape
+    print(f"[op shapes] geom={geom} shape={shape}", flush=True)
     g = oracle_lib.Geometry(n, na, nb)
     x, y = _inputs(geom, 3 * n + nb, "uniform")
     ax_ref, aty_ref = g.project(x), g.backproject(y)
     with scg.Plan(n, na, nb) as plan:
         for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
                               (scg.SCG_F64, torch.float64, 1e-12)):
-            plan.set_tuning(prec, project_groups=pg, backproject_split=bs)
-            assert plan.tuning(prec) == {"project_groups": pg, "backproject_split": bs}
+            plan.set_tuning(prec, project_groups=pg, backproject_split=bs, project_angles=ga,
+                            swizzle=sw)
+            assert plan.tuning(prec) == {"project_groups": pg, "backproject_split": bs,
+                                         "project_angles": ga, "swizzle": sw}
             xd = torch.tensor(x, dtype=dt, device="cuda")
             yd = torch.tensor(y, dtype=dt, device="cuda")
             ax, aty = plan.project(xd), plan.backproject(yd)
@@ -204,7 +210,8 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
         for prec in (scg.SCG_F32, scg.SCG_F64):
             t = plan.autotune(prec)
             assert t["project_groups"] in (2, 4) and t["backproject_split"] in (1, 2, 4)
+            assert t["project_angles"] in (8, 4) and t["swizzle"] in (0, 1)
             assert plan.tuning(prec) == t
-        for bad in ((3, 2), (4, 3), (0, 1)):
+        for bad in ((3, 2, 8, 0), (4, 3, 8, 0), (0, 1, 8, 0), (4, 2, 6, 0), (4, 2, 8, 2)):
             with pytest.raises(scg.ScgError):
                 plan.set_tuning(scg.SCG_F32, *bad)
