@@ -15,7 +15,16 @@ Prints one JSON line. `roofline` describes the dominant kernel (its average
 duration measured with HIP events on the solve's stream during the timed
 solves); `cpu_baseline` times the FP64 oracle on the host for a bounded
 sample (the initial step plus two S-CG steps), extrapolated to the GPU's step
-count.
+count. Unless --no-mix is given, two more objects compare the batch engine
+with plain one-at-a-time solves on the same requests (eps = f(x_true) and
+gamma0 = RHO ||x_1|| per request, outputs compared bitwise):
+  `batched`: 64 solves, N in {128, 256, 384, 512}, angles in {180, 360, 540,
+             720} drawn independently, bins ceil(sqrt(2) N) + 1, all submitted
+             at once; recons/s of each way;
+  `served`:  a Poisson stream (mean 200 requests/s) of (N, angles) in
+             {(128, 180), (256, 360), (512, 720), (1024, 1440)} with weights
+             0.4/0.3/0.2/0.1; p50/p99 latency (completion - arrival) and
+             recons/s, continuous batching against a FIFO of plain solves.
 """
 from __future__ import annotations
 
@@ -35,6 +44,7 @@ N, N_ANGLES, N_BINS = 512, 720, 729
 PEAK_LANE_OPS = 256 * 64 * 2.4e9   # VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 OPS_PER_NNZ = 8                    # weight evaluation + multiply-accumulate per nonzero
 PEAK_HBM = 8.0e12
+ARENA = 16 << 30                   # batch engine arena (bytes of HBM)
 
 
 def log(msg):
@@ -90,12 +100,71 @@ def cpu_baseline(w, eps, gamma0, steps_gpu):
                        f"the GPU solve's {steps_gpu} steps")}
 
 
+def mixed_runs(n_serve):
+    """Batched and served runs against plain one-at-a-time solves."""
+    import torch
+    from paper_1709_04912_amd import serve
+    from synth.workloads import make_batch_item, make_serve_item, poisson_arrivals
+
+    def build(items):
+        reqs = []
+        for i, w in enumerate(items):
+            reqs.append(serve.make_request(i, cache, w.y, w.x_true, w.n, w.n_angles, w.n_bins,
+                                           rho=RHO))
+        return reqs
+
+    def warm(reqs):
+        seen = {}
+        for r in reqs:
+            seen.setdefault(id(r.plan), r)
+        w = list(seen.values())
+        serve.serve_plain(w)
+        serve.serve_batched(w, arena_bytes=ARENA, iters=4)
+
+    def same(a, b):
+        return sum(int(torch.equal(a.outputs[i], b.outputs[i])) for i in a.outputs)
+
+    cache = serve.PlanCache()
+    log("batched run: generating 64 solves")
+    reqs = build([make_batch_item(i) for i in range(64)])
+    warm(reqs)
+    b = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, keep_outputs=True)
+    p = serve.serve_plain(reqs, keep_outputs=True)
+    batched = {
+        "workload": "64 S-CG solves, N in {128,256,384,512}, angles in {180,360,540,720}, "
+                    "bins ceil(sqrt(2)N)+1, sigma U[0.5%,3%], eps = f(x_true)",
+        "batched_recons_per_s": b.recons_per_s, "plain_recons_per_s": p.recons_per_s,
+        "speedup": b.recons_per_s / p.recons_per_s,
+        "bitwise_equal_outputs": same(p, b), "solves": len(reqs),
+        "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports))}
+    log(f"batched: {batched}")
+    pool = 120
+    log(f"served run: generating {pool} distinct requests for a stream of {n_serve}")
+    items = [make_serve_item(i) for i in range(pool)]
+    base = build(items)
+    arr = poisson_arrivals(5000, n_serve, 200.0)
+    reqs = [serve.Request(i, base[i % pool].plan, base[i % pool].y, base[i % pool].params,
+                          float(arr[i])) for i in range(n_serve)]
+    warm(base)
+    b = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, keep_outputs=True)
+    p = serve.serve_plain(reqs, keep_outputs=True)
+    served = {
+        "workload": f"{n_serve} requests, Poisson 200/s, (N, angles) in (128,180) (256,360) "
+                    "(512,720) (1024,1440) weights 0.4/0.3/0.2/0.1, eps = f(x_true)",
+        "batched": b.summary(), "plain": p.summary(), "bitwise_equal_outputs": same(p, b)}
+    log(f"served: {served}")
+    cache.close()
+    return batched, served
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mix", action="store_true", help="skip the batched and served runs")
+    ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
@@ -206,6 +275,8 @@ def main():
                            "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM},
         },
     }
+    if not args.no_mix:
+        result["batched"], result["served"] = mixed_runs(args.serve_requests)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(w, eps, gamma0, rep.steps)

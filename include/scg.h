@@ -63,7 +63,9 @@ typedef enum {
     SCG_CG = 0,      /* Alg. CG (unsuperiorized, recursive gradient)           */
     SCG_S_CG = 1,    /* Alg. S-CG with CG-PR-STEP                              */
     SCG_S_CG_CD = 2, /* Alg. S-CG-CD with CG-CD-STEP (conjugate-descent beta)  */
-    SCG_S_PCG = 3    /* Alg. S-PCG with PCG-PR-STEP (filtered preconditioner)  */
+    SCG_S_PCG = 3,   /* Alg. S-PCG with PCG-PR-STEP (filtered preconditioner)  */
+    SCG_S_CG_K = 4   /* Alg. S-CG-K: perturbed(x_k), then CG-K (K = restart_k  */
+                     /* CG-STEPs) restarted from the perturbed point           */
 } scg_variant;
 
 /* flags of scg_params.flags */
@@ -87,13 +89,16 @@ typedef struct {
     double  tv_kappa;    /* 0: exact isotropic TV; > 0: sqrt(a^2+b^2+kappa^2)     */
     double  precond_mu;  /* mu of the filter c(w) (S-PCG); <= 0 selects 2 pi / P  */
     uint32_t flags;      /* SCG_FLAG_*                                            */
+    int32_t restart_k;   /* K of SCG_S_CG_K: CG-STEPs per pass, 1..64 (default 2) */
 } scg_params;
 
 typedef struct {
     int32_t status;       /* SCG_OK, SCG_ENOCONV, SCG_ENAN or SCG_EBREAKDOWN      */
     int32_t k;            /* the paper's counter k when the loop ended; the       */
-                          /* output is x_{k-1/2}                                  */
-    int32_t steps;        /* steps executed after the initial one                 */
+                          /* output is x_{k-1/2} (SCG_S_CG_K: passes made, 0 when */
+                          /* f(x0) <= eps)                                        */
+    int32_t steps;        /* steps executed after the initial one (passes for    */
+                          /* SCG_S_CG_K)                                          */
     int32_t trials_total; /* TV trials made by perturbed()                        */
     int32_t ell;          /* final value of the gamma counter l                   */
     int32_t reserved;

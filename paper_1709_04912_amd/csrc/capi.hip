@@ -247,7 +247,8 @@ void prof_drain(scg_plan *p, int last_iter)
 int check_params(const scg_params *pr)
 {
     if (pr == nullptr) return SCG_EINVAL;
-    if (pr->variant < SCG_CG || pr->variant > SCG_S_PCG) return SCG_EINVAL;
+    if (pr->variant < SCG_CG || pr->variant > SCG_S_CG_K) return SCG_EINVAL;
+    if (pr->variant == SCG_S_CG_K && (pr->restart_k < 1 || pr->restart_k > 64)) return SCG_EINVAL;
     if (pr->prec != SCG_F32 && pr->prec != SCG_F64) return SCG_EINVAL;
     if (!(pr->eps > 0.0) || !std::isfinite(pr->eps)) return SCG_EINVAL;
     if (!(pr->gamma0 >= 0.0) || !std::isfinite(pr->gamma0)) return SCG_EINVAL;
@@ -364,6 +365,7 @@ void scg_default_params(scg_params *p)
     p->tv_kappa = 0.0;
     p->precond_mu = 0.0;
     p->flags = 0;
+    p->restart_k = 2;
 }
 
 const char *scg_strerror(int status)

@@ -93,6 +93,7 @@ template <typename T> struct Group {
     int variant = SCG_S_CG;
     scg_tuning tune{4, 2, 8, 0};
     int max_nb = 1;
+    int restart_k = 2;                      // S-CG-K
     const Solve<T> *S = nullptr;            // device descriptors
     const BlkMap *map[kKinds] = {};         // device block maps (null for a single solve)
     int nblk[kKinds] = {};
@@ -163,6 +164,13 @@ template <typename T> struct Enq {
 template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
 {
     const Enq<T> e{g, s};
+    if (g.variant == SCG_S_CG_K) {
+        // S-CG-K: x_{-1/2} = x_0 = x0 and the loop test f(x0) > eps
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        return;
+    }
     if (g.variant == SCG_CG) {
         e.stage(kStageX);
         e.project(kPjResX);
@@ -234,6 +242,26 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
     }
     e.project(kPjResXh);
     e.finish(kFinResidualStep);
+    if (g.variant == SCG_S_CG_K) {
+        // CG-K from x_{k+1/2} (copied into x by the perturbation): g0 =
+        // A^T r (r formed above), p0 = -g0, delta0 = ||g0||^2, then K
+        // CG-STEPs; the direction update after the last one is not needed
+        e.backproject(kBpG, 2);
+        e.finish(kFinDotGG);
+        e.p_update(3, 1);
+        for (int j = 0; j < g.restart_k; ++j) {
+            e.project(kPjQ);
+            e.finish(kFinNormQCG, 1);
+            e.backproject(kBpH, 0);
+            {
+                Prof t(g.prof, SCG_KC_VECTOR, s);
+                launch_b_x_update_cg<T>(g.S, e.m(kKVec), e.n(kKVec), s);
+            }
+            e.finish(kFinXUpdateCG, 1);
+            if (j + 1 < g.restart_k) e.p_update(3, 0);
+        }
+        return;
+    }
     if (g.variant == SCG_S_PCG) {
         e.filter();
         e.backproject(kBpGZ, 1);
@@ -333,8 +361,14 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     hs.max_trials = pr->max_trials;
     hs.variant = pr->variant;
     hs.flags = (int)pr->flags;
+    const bool is_k = pr->variant == SCG_S_CG_K;
     hs.k = 0;
-    hs.steps = is_cg ? 0 : -1;   // the initial step of the S- variants is not counted
+    // the initial step of S-CG, S-CG-CD and S-PCG is open until the first
+    // loop launch closes it (and is not counted); S-CG-K has none
+    hs.steps = (is_cg || is_k) ? 0 : -1;
+    hs.open = (is_cg || is_k) ? 0 : 1;
+    hs.kofs = is_k ? 1 : 0;
+    hs.restart_k = pr->restart_k;
     hs.accepted = -1;
     hs.is_f32 = sizeof(T) == 4 ? 1 : 0;
     hs.trace_cap = std::min<int32_t>(std::max(trace_cap, 0), pr->max_iter + 1);
@@ -349,8 +383,8 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
                                hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ws + L.desc, &h, sizeof(h), hipMemcpyHostToDevice, s));
 
-    // x_{1/2} = x0 (S- variants) or x_0 (CG).
-    T *x_start = is_cg ? h.x : h.xh;
+    // x_{1/2} = x0 (S-CG, S-CG-CD, S-PCG) or x_0 (CG, S-CG-K).
+    T *x_start = (is_cg || is_k) ? h.x : h.xh;
     if (x0_ != nullptr) launch_copy<T>(x_start, static_cast<const T *>(x0_), J, nullptr, s);
     else launch_fill<T>(x_start, J, T(0), s);
     return SCG_OK;
@@ -364,6 +398,7 @@ Group<T> single_group(const scg_params *pr, const scg_tuning &tune, const Solve<
     g.variant = pr->variant;
     g.tune = tune;
     g.max_nb = h.G.nb;
+    g.restart_k = pr->restart_k;
     g.S = reinterpret_cast<const Solve<T> *>(ws + layout(h.G, sizeof(T), pr->max_iter).desc);
     for (int k = 0; k < kKinds; ++k) g.nblk[k] = count_of(h, k);
     g.any_trB = h.trB_chunks > 0;
@@ -423,11 +458,11 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     HIP_TRY(hipStreamSynchronize(st0));
     prof_drain(plan, std::max(fs.steps, 0));
     plan->prof_iter = 0;
-    const bool is_cg = pr->variant == SCG_CG;
+    const bool plain_k = pr->variant == SCG_CG || pr->variant == SCG_S_CG_K;
     if (rep != nullptr) {
         std::memset(rep, 0, sizeof(*rep));
         rep->status = fs.done ? fs.status : SCG_ENOCONV;
-        rep->k = is_cg ? fs.k : std::max(fs.k, 1);
+        rep->k = plain_k ? fs.k : std::max(fs.k, 1);
         rep->steps = std::max(fs.steps, 0);
         rep->trials_total = fs.trials_total;
         rep->ell = fs.ell;
@@ -584,6 +619,7 @@ GroupImage<T> pack_group(Packer &pk, std::vector<Slot> &slots, const std::vector
                          int variant, scg_tuning tune, bool with_maps)
 {
     GroupImage<T> gi;
+    gi.g.restart_k = slots[members.front()].params.restart_k;
     std::vector<Solve<T>> descs;
     for (int i : members) descs.push_back(desc_of<T>(slots[i]));
     gi.g.ns = (int)descs.size();
@@ -652,8 +688,8 @@ int rebuild(scg_batch *b)
         const Slot &s = b->active[i];
         const int pi = s.params.prec == SCG_F64 ? 1 : 0;
         const scg_tuning t = s.tune;
-        keys[std::make_tuple(pi, (int)s.params.variant, t.project_groups * 100 +
-                                                           t.backproject_split * 10 + t.swizzle,
+        keys[std::make_tuple(pi, (int)s.params.variant * 100 + s.params.restart_k,
+                             t.project_groups * 100 + t.backproject_split * 10 + t.swizzle,
                              t.project_angles)]
             .push_back(i);
     }
@@ -661,8 +697,10 @@ int rebuild(scg_batch *b)
     std::vector<GroupImage<float>> imf;
     std::vector<GroupImage<double>> imd;
     for (auto &kv : keys) {
-        const int pi = std::get<0>(kv.first), variant = std::get<1>(kv.first);
-        const scg_tuning t = b->active[kv.second.front()].tune;
+        const int pi = std::get<0>(kv.first);
+        const Slot &first = b->active[kv.second.front()];
+        const int variant = first.params.variant;
+        const scg_tuning t = first.tune;
         if (pi == 0) {
             imf.push_back(pack_group<float>(pk, b->active, kv.second, variant, t, true));
             b->members_f.push_back(kv.second);
@@ -711,9 +749,9 @@ void gather(const scg::Group<T> &g, DevState *dst, double *tv, hipStream_t s)
 void fill_report(const Slot &s, const DevState &fs, double tv, scg_report *rep)
 {
     std::memset(rep, 0, sizeof(*rep));
-    const bool is_cg = s.params.variant == SCG_CG;
+    const bool plain_k = s.params.variant == SCG_CG || s.params.variant == SCG_S_CG_K;
     rep->status = fs.done ? fs.status : SCG_ENOCONV;
-    rep->k = is_cg ? fs.k : std::max(fs.k, 1);
+    rep->k = plain_k ? fs.k : std::max(fs.k, 1);
     rep->steps = std::max(fs.steps, 0);
     rep->trials_total = fs.trials_total;
     rep->ell = fs.ell;

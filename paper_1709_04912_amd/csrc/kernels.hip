@@ -15,6 +15,20 @@ namespace scg {
 
 namespace {
 
+// Pointers read from a descriptor in memory are generic to the compiler,
+// whose flat loads also count as LDS operations and so make every LDS wait
+// wait for the global loads in flight. The kernel bodies access memory
+// through these global-qualified views instead.
+template <typename P> __device__ __forceinline__ auto gl(P *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    using G = __attribute__((address_space(1))) P;
+    return (G *)p;
+#else
+    return p;   // host pass of the single-source compile: never executed
+#endif
+}
+
 constexpr int kBlock = 256;
 constexpr int kMaxVecBlocks = 512;
 
@@ -37,16 +51,6 @@ __device__ __forceinline__ double frc(double v) { return v - floor(v); }
 // both sides of every TV comparison use it), IEEE sqrt for FP64.
 __device__ __forceinline__ float tsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ double tsqrt(double v) { return sqrt(v); }
-
-template <typename T> __device__ __forceinline__ T pK(const ProjAngle &a);
-template <> __device__ __forceinline__ float pK<float>(const ProjAngle &a) { return a.Kf; }
-template <> __device__ __forceinline__ double pK<double>(const ProjAngle &a) { return a.K; }
-template <typename T> __device__ __forceinline__ T pC(const ProjAngle &a);
-template <> __device__ __forceinline__ float pC<float>(const ProjAngle &a) { return a.Cf; }
-template <> __device__ __forceinline__ double pC<double>(const ProjAngle &a) { return a.C; }
-template <typename T> __device__ __forceinline__ T pM(const ProjAngle &a);
-template <> __device__ __forceinline__ float pM<float>(const ProjAngle &a) { return a.inv_mf; }
-template <> __device__ __forceinline__ double pM<double>(const ProjAngle &a) { return a.inv_m; }
 
 template <typename T> struct BpW { T K, C, CK, M, c, s; };
 template <typename T> __device__ __forceinline__ BpW<T> bpw(const BpAngle &a);
@@ -83,7 +87,7 @@ __device__ void block_store(const A (&v)[NV], double *dst)
     if (threadIdx.x < NV) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
-        dst[threadIdx.x] = s;
+        gl(dst)[threadIdx.x] = s;
     }
     __syncthreads();
 }
@@ -97,22 +101,29 @@ __device__ void final_sums(const double *partials, int nblk, int stride, int nv,
     const int nw = blockDim.x >> 6;
     for (int k = wid; k < nv; k += nw) {
         double acc = 0.0;
-        for (int b = lane; b < nblk; b += 64) acc += partials[(size_t)b * stride + k];
+        const auto *pg = gl(partials);
+        for (int b = lane; b < nblk; b += 64) acc += pg[(size_t)b * stride + k];
         acc = wave_sum(acc);
         if (lane == 0) tot[k] = acc;
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ bool stopped(const DevState *st) { return st != nullptr && st->done; }
-
-__device__ __forceinline__ scg_trace_entry *trace_at(DevState *st, scg_trace_entry *trace, int k)
+__device__ __forceinline__ bool stopped(const DevState *st)
 {
-    if (trace == nullptr || k < 1 || k > st->trace_cap) return nullptr;
-    return &trace[k - 1];
+    return st != nullptr && gl(st)->done;
 }
 
-__device__ __forceinline__ void set_done(DevState *st, int status)
+// Trace entry of the open step: k + kofs (entries count from 1).
+template <typename S> __device__ __forceinline__ auto trace_at(S *st, scg_trace_entry *trace)
+{
+    using R = decltype(gl(trace));
+    const int k = st->k + st->kofs;
+    if (trace == nullptr || k < 1 || k > st->trace_cap) return (R) nullptr;
+    return gl(trace) + (k - 1);
+}
+
+template <typename S> __device__ __forceinline__ void set_done(S *st, int status)
 {
     st->done = 1;
     st->status = status;
@@ -122,13 +133,14 @@ __device__ __forceinline__ void set_done(DevState *st, int status)
 // the step that starts with counter value l (rounded to the image precision,
 // the value the trials and the accepted perturbation use). All threads of
 // the block take part.
-__device__ __forceinline__ void fill_gtab(double *gtab, const DevState *st, int ell)
+template <typename S> __device__ __forceinline__ void fill_gtab(double *gtab, S *st, int ell)
 {
     const double g0 = st->gamma0, a = st->a;
     const int mt = st->max_trials, f32 = st->is_f32;
+    auto *gt = gl(gtab);
     for (int m = threadIdx.x; m < mt; m += blockDim.x) {
         const double g = g0 * pow(a, (double)(ell + m));
-        gtab[m] = f32 ? (double)(float)g : g;
+        gt[m] = f32 ? (double)(float)g : g;
     }
 }
 
@@ -169,6 +181,12 @@ __device__ __forceinline__ int launch_index(int swz)
     const int per = n / kXcds, rem = n % kXcds;
     const int xcd = b % kXcds, idx = b / kXcds;
     return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// A solve's descriptor (a copy: the bodies' stores cannot alias it).
+template <typename T> __device__ __forceinline__ Solve<T> load_solve(const Solve<T> *S, int i)
+{
+    return gl(S)[i];
 }
 
 // The solve and the local block index of a batched launch's block.
@@ -237,9 +255,9 @@ __global__ __launch_bounds__(256) void kb_copy_out(const Solve<T> *S, const BlkM
                                                     int from_xh)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
-    const T *src = from_xh ? d.xh : d.x;
-    T *dst = d.xout;
+    const Solve<T> d = load_solve(S, m.solve);
+    const auto *src = gl(from_xh ? d.xh : d.x);
+    auto *dst = gl(d.xout);
     const size_t J = (size_t)d.G.n * d.G.n;
     for (size_t i = m.local * (size_t)blockDim.x + threadIdx.x; i < J;
          i += (size_t)d.nb_vec * blockDim.x)
@@ -259,8 +277,10 @@ void launch_b_copy_out(const Solve<T> *S, const BlkMap *map, int nblocks, int fr
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void stage_body(const T *__restrict__ x, T *__restrict__ xt, const Geo &G, VBlk vb)
+__device__ void stage_body(const T *__restrict__ x_, T *__restrict__ xt_, const Geo &G, VBlk vb)
 {
+    const auto *x = gl(x_);
+    auto *xt = gl(xt_);
     __shared__ T tile[32][33];
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
@@ -292,7 +312,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_stage(const Solve<T> *S, const BlkMap *map, int phase)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     stage_body(phase == kStageX ? d.x : d.xh, d.xs, d.G, vblk_of(m.local, nt, nt));
@@ -336,14 +356,15 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     __shared__ T lds[kPjWin * LS];
     const int t = threadIdx.x;
     const int chunk = vb.x, gi = vb.y;
-    const PjGroup grp = P.groups[gi];
+    const PjGroup grp = gl(P.groups)[gi];
+    const auto *pang = gl(P.ang);
     const int quarter = __builtin_amdgcn_readfirstlane(t / kPjBins);
     const int b_raw = chunk * kPjBins + (t & (kPjBins - 1));
     const bool bin_ok = b_raw < G.nb;
     const int b = bin_ok ? b_raw : G.nb - 1;   // idle lanes trace the chunk's last ray
     const int n = G.n;
-    const T *img = grp.major ? xt : x;
-    const int *win = P.win + ((size_t)gi * P.n_chunks + chunk) * P.n_bands;
+    const auto *img = gl(grp.major ? xt : x);
+    const auto *win = gl(P.win) + ((size_t)gi * P.n_chunks + chunk) * P.n_bands;
     const int scol = t % kPjWin, srow = (t / kPjWin) * RPT;
 
     double u0[SLOTS];
@@ -355,7 +376,7 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         accr[m] = T(0);
         u0[m] = 0.0;
         if (slot < grp.count) {
-            const ProjAngle &A = P.ang[grp.a0 + slot];
+            const auto &A = pang[grp.a0 + slot];
             u0[m] = fma((double)b, A.u0_step, A.u0_base);
         }
     }
@@ -366,7 +387,7 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         const int i0 = band * kPjBand + srow;
         const int col = jw + scol;
         const bool cok = col >= 0 && col < n;
-        const T *src = img + (size_t)i0 * n + (cok ? col : 0);
+        const auto *src = img + (size_t)i0 * n + (cok ? col : 0);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             T v = T(0);
@@ -392,12 +413,14 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         for (int m = 0; m < SLOTS; ++m) {
             const int slot = quarter + NQ * m;
             if (slot < grp.count) {
-                const ProjAngle &A = P.ang[grp.a0 + slot];
+                const auto &A = pang[grp.a0 + slot];
                 const double us = fma((double)i0, A.slope, u0[m]);
                 const double fu = floor(us);
                 const T *col0 = lds + ((int)fu - jw) * LS;
                 const T F0 = (T)(us - fu);
-                const T slope = (T)A.slope, K = pK<T>(A), C = pC<T>(A);
+                const T slope = (T)A.slope;
+                const T K = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
+                const T C = sizeof(T) == 4 ? (T)A.Cf : (T)A.C;
                 T a_ = acc[m], ar = accr[m];
 #pragma unroll
                 for (int k = 0; k < kPjBand; ++k) {
@@ -422,9 +445,10 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         const int slot = quarter + NQ * m;
         if (slot < grp.count && bin_ok) {
             const int a = grp.a0 + slot;
-            T val = (acc[m] + accr[m]) * pM<T>(P.ang[a]);
-            if (y != nullptr) val -= y[(size_t)a * y_stride + b];
-            out[(size_t)a * out_stride + out_off + b] = val;
+            const T im = sizeof(T) == 4 ? (T)pang[a].inv_mf : (T)pang[a].inv_m;
+            T val = (acc[m] + accr[m]) * im;
+            if (y != nullptr) val -= gl(y)[(size_t)a * y_stride + b];
+            gl(out)[(size_t)a * out_stride + out_off + b] = val;
             sq += (double)val * (double)val;
         }
     }
@@ -470,23 +494,19 @@ __global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, co
                                                            int phase, int swz)
 {
     const BlkMap m = locate(map, swz);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     // descriptor fields into registers: the body's stores cannot alias them
     const Geo G = d.G;
     const ProjTables P = d.P;
     const VBlk vb = vblk_of(m.local, P.n_chunks, P.n_groups);
-    if (phase == kPjQ) {
-        const T *img = d.p, *imgt = d.pt;
-        T *out = d.q;
-        double *part = d.partials;
-        project_body<T, NQ, GA>(img, imgt, G, P, nullptr, 0, out, G.rs, kSinoPadL, part, vb);
-    } else {
-        const T *img = phase == kPjResX ? d.x : d.xh, *imgt = d.xs, *y = d.y;
-        T *out = d.r;
-        double *part = d.partials;
-        project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, part, vb);
-    }
+    // one body instance: pick the phase's vectors first
+    const bool q = phase == kPjQ;
+    const T *img = q ? d.p : (phase == kPjResX ? d.x : d.xh);
+    const T *imgt = q ? d.pt : d.xs;
+    const T *y = q ? nullptr : d.y;
+    T *out = q ? d.q : d.r;
+    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, d.partials, vb);
 }
 
 template <typename T>
@@ -579,14 +599,14 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             const int a = a0 + al;
             T v = T(0), v2 = T(0);
             if (a < G.na) {
-                const BpAngle &A = ang[a];
+                const auto &A = gl(ang)[a];
                 const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
                 const int bb = (int)floor(pc) - kBpHalf + k;
                 if (bb >= 0 && bb < G.nb) {
                     const T m = (T)A.inv_m;
                     const size_t off = (size_t)a * G.rs + kSinoPadL + bb;
-                    v = r[off] * m;
-                    if (DUAL) v2 = r2[off] * m;
+                    v = gl(r)[off] * m;
+                    if (DUAL) v2 = gl(r2)[off] * m;
                 }
             }
             pre[0][e] = v;
@@ -597,7 +617,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 #pragma unroll
             for (int k = 0; k < kBpPrm; ++k) ppr[k] = T(0);
             if (a < G.na) {
-                const BpAngle &A = ang[a];
+                const BpAngle A = gl(ang)[a];
                 const BpW<T> W = bpw<T>(A);
                 const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
                 ppr[0] = W.c;
@@ -685,16 +705,19 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     double dsum = 0.0;
     if (gs == 0 && i < G.n) {
         const size_t p = (size_t)i * G.n + j;
+        auto *og = gl(out);
+        auto *og2 = gl(out2);
+        const auto *dg = gl(dotv);
         if (j < G.n) {
-            out[p] = acc0;
-            if (DUAL) out2[p] = bcc0;
-            if (dot == 1) dsum += (double)(DUAL ? bcc0 : acc0) * (double)dotv[p];
+            og[p] = acc0;
+            if (DUAL) og2[p] = bcc0;
+            if (dot == 1) dsum += (double)(DUAL ? bcc0 : acc0) * (double)dg[p];
             else if (dot == 2) dsum += (double)acc0 * (double)acc0;
         }
         if (j + 1 < G.n) {
-            out[p + 1] = acc1;
-            if (DUAL) out2[p + 1] = bcc1;
-            if (dot == 1) dsum += (double)(DUAL ? bcc1 : acc1) * (double)dotv[p + 1];
+            og[p + 1] = acc1;
+            if (DUAL) og2[p + 1] = bcc1;
+            if (dot == 1) dsum += (double)(DUAL ? bcc1 : acc1) * (double)dg[p + 1];
             else if (dot == 2) dsum += (double)acc1 * (double)acc1;
         }
     }
@@ -736,24 +759,20 @@ __global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T>
                                                                    int dot, int swz)
 {
     const BlkMap m = locate(map, swz);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     // descriptor fields into registers: the body's stores cannot alias them
     const Geo G = d.G;
     const BpAngle *ang = d.bang;
     const int nt = (G.n + kBpTile - 1) / kBpTile;
     const VBlk vb = vblk_of(m.local, nt, nt);
-    if (phase == kBpH) {
-        const T *src = d.q;
-        T *dst = d.h;
-        backproject_body<T, false, NS>(src, nullptr, G, ang, dst, nullptr, nullptr, 0, nullptr,
-                                       vb);
-    } else {   // kBpG, kBpGZ: g' = A^T r (and z' = A^T rt); dot against h or g'
-        const T *src = d.r, *src2 = d.rt, *dotv = d.h;
-        T *dst = d.g, *dst2 = d.z;
-        double *part = d.partials;
-        backproject_body<T, DUAL, NS>(src, src2, G, ang, dst, dst2, dotv, dot, part, vb);
-    }
+    // one body instance: kBpH is h = A^T q (no second sinogram, no dot);
+    // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g'
+    const bool hq = phase == kBpH;
+    const T *src = hq ? d.q : d.r;
+    T *dst = hq ? d.h : d.g;
+    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, d.h, hq ? 0 : dot,
+                                  hq ? nullptr : d.partials, vb);
 }
 
 template <typename T, bool DUAL>
@@ -825,9 +844,11 @@ __device__ __forceinline__ T tv_pixel(const T (&X)[3][3], int i, int j, int n, T
 // TV(x) block partials and optionally the subgradient (grid-stride over the
 // image with the body's block count).
 template <typename T>
-__device__ void tv_body(const T *__restrict__ x, T *__restrict__ s_out, const Geo &G, T k2,
+__device__ void tv_body(const T *__restrict__ x_, T *__restrict__ s_out_, const Geo &G, T k2,
                         double *partials, VBlk vb)
 {
+    const auto *x = gl(x_);
+    auto *s_out = gl(s_out_);
     const int n = G.n;
     double tv = 0.0;
     const size_t J = (size_t)n * n;
@@ -880,8 +901,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_tv(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
-    const T k2 = (T)(d.st->kappa * d.st->kappa);
+    const Solve<T> d = load_solve(S, m.solve);
+    const T k2 = (T)(gl(d.st)->kappa * gl(d.st)->kappa);
     tv_body<T>(d.xout, nullptr, d.G, k2, d.partials, vblk_of(m.local, d.nb_vec, 1));
 }
 
@@ -900,22 +921,29 @@ void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t 
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void xtv_body(const T *__restrict__ xh, const T *__restrict__ p, T *__restrict__ x,
-                         T *__restrict__ s_out, const Geo &G, double *partials,
-                         const DevState *st, VBlk vb)
+__device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T *__restrict__ x_,
+                         T *__restrict__ s_out_, const Geo &G, double *partials,
+                         const DevState *st_, VBlk vb)
 {
+    const auto *xh = gl(xh_);
+    const auto *p = gl(p_);
+    auto *x = gl(x_);
+    auto *s_out = gl(s_out_);
+    const auto *st = gl(st_);
     constexpr int TW = 32, TH = 8;
     __shared__ T tile[TH + 2][TW + 2];
     const int n = G.n;
     const int i0 = vb.y * TH, j0 = vb.x * TW;
     const T al = (T)st->alpha;
     const T k2 = (T)(st->kappa * st->kappa);
+    // S-CG-K: x_{k+1} is CG-K's output, already in x
+    const bool given = st->variant == SCG_S_CG_K;
     for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
         const int ii = i0 - 1 + e / (TW + 2), jj = j0 - 1 + e % (TW + 2);
         T v = T(0);
         if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
             const size_t q = (size_t)ii * n + jj;
-            v = fma(al, p[q], xh[q]);
+            v = given ? x[q] : fma(al, p[q], xh[q]);
         }
         tile[e / (TW + 2)][e % (TW + 2)] = v;
     }
@@ -932,7 +960,7 @@ __device__ void xtv_body(const T *__restrict__ xh, const T *__restrict__ p, T *_
         T own;
         const T sg = tv_pixel(X, i, j, n, k2, own);
         const size_t q = (size_t)i * n + j;
-        x[q] = X[1][1];
+        if (!given) x[q] = X[1][1];
         s_out[q] = sg;
         tv = (double)own;
         ss = (double)sg * (double)sg;
@@ -945,7 +973,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials, d.st,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
@@ -969,10 +997,14 @@ void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void trials_body(const T *__restrict__ x, const T *__restrict__ s, const Geo &G,
-                            const double *__restrict__ gtab, double *partials,
-                            const DevState *st, int first_m, int nchunks, VBlk vb)
+__device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, const Geo &G,
+                            const double *__restrict__ gtab_, double *partials,
+                            const DevState *st_, int first_m, int nchunks, VBlk vb)
 {
+    const auto *x = gl(x_);
+    const auto *s = gl(s_);
+    const auto *gtab = gl(gtab_);
+    const auto *st = gl(st_);
     constexpr int M = kTrialsPerPass;
     const int max_trials = st->max_trials;
     const int stride = 1 + M * nchunks;
@@ -1021,8 +1053,8 @@ __global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap
                                                   int first_m)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
-    if (d.st->done || d.st->search_done) return;
+    const Solve<T> d = load_solve(S, m.solve);
+    if (gl(d.st)->done || gl(d.st)->search_done) return;
     const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
     const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
     trials_body(d.x, d.s, d.G, d.gtab, d.partials, d.st, first_m, nchunks,
@@ -1049,12 +1081,18 @@ void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int firs
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void perturb_body(const T *__restrict__ x, const T *__restrict__ s,
-                             T *__restrict__ xh, T *__restrict__ xht, const Geo &G,
-                             const DevState *st, VBlk vb)
+__device__ void perturb_body(T *__restrict__ x_, const T *__restrict__ s_,
+                             T *__restrict__ xh_, T *__restrict__ xht_, const Geo &G,
+                             const DevState *st_, VBlk vb)
 {
+    auto *x = gl(x_);
+    const auto *s = gl(s_);
+    auto *xh = gl(xh_);
+    auto *xht = gl(xht_);
+    const auto *st = gl(st_);
     __shared__ T tile[32][33];
     const bool move = st->accepted >= 0 && st->gamma != 0.0;
+    const bool restart = st->variant == SCG_S_CG_K;   // CG-K starts from x_{k+1/2}
     const T g = (T)st->gamma, inv = (T)st->inv_snorm;
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
@@ -1067,6 +1105,7 @@ __device__ void perturb_body(const T *__restrict__ x, const T *__restrict__ s,
             const T xc = x[q];
             v = move ? fma(g, -s[q] * inv, xc) : xc;
             xh[q] = v;
+            if (restart) x[q] = v;
         }
         tile[r][tx] = v;
     }
@@ -1081,7 +1120,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_perturb(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     perturb_body(d.x, d.s, d.xh, d.xs, d.G, d.st, vblk_of(m.local, nt, nt));
@@ -1093,22 +1132,30 @@ void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStre
     hipLaunchKernelGGL(kb_perturb<T>, dim3(nblocks), dim3(256), 0, s, S, map);
 }
 
-__device__ __forceinline__ double beta_of(const DevState *st, int rule, int init)
+template <typename S> __device__ __forceinline__ double beta_of(S *st, int rule, int init)
 {
     if (init) return 0.0;
     if (rule == 0 || rule == 2) return st->gh / st->qq_prev;
     if (rule == 1) return -st->gg / st->gp_prev;
+    // CG-STEP inside a CG-K pass: a zero gradient (an exact minimiser) ends
+    // the pass's progress instead of a 0/0
+    if (st->variant == SCG_S_CG_K && st->delta == 0.0) return 0.0;
     return st->gg / st->delta;
 }
 
 template <typename T>
-__device__ void p_update_body(const T *__restrict__ g, const T *__restrict__ z,
-                              T *__restrict__ p, T *__restrict__ pt, const Geo &G,
-                              double *partials, const DevState *st, int rule, int init, VBlk vb)
+__device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_,
+                              T *__restrict__ p_, T *__restrict__ pt_, const Geo &G,
+                              double *partials, const DevState *st_, int rule, int init, VBlk vb)
 {
+    const auto *g = gl(g_);
+    const auto *z = gl(z_);
+    auto *p = gl(p_);
+    auto *pt = gl(pt_);
+    const auto *st = gl(st_);
     __shared__ T tile[32][33];
     const T bt = (T)beta_of(st, rule, init);
-    const T *src = (rule == 2) ? z : g;
+    const auto *src = (rule == 2) ? z : g;
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -1138,7 +1185,7 @@ __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkM
                                                     int rule, int init)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials, d.st, rule, init,
@@ -1158,16 +1205,18 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_x_update_cg(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
-    const T al = (T)d.st->alpha;
+    const T al = (T)gl(d.st)->alpha;
     const size_t J = (size_t)d.G.n * d.G.n;
+    auto *x = gl(d.x), *g = gl(d.g);
+    const auto *p = gl(d.p), *h = gl(d.h);
     double acc = 0.0;
     for (size_t q = m.local * (size_t)blockDim.x + threadIdx.x; q < J;
          q += (size_t)d.nb_vec * blockDim.x) {
-        d.x[q] = fma(al, d.p[q], d.x[q]);
-        const T gn = fma(al, d.h[q], d.g[q]);
-        d.g[q] = gn;
+        x[q] = fma(al, p[q], x[q]);
+        const T gn = fma(al, h[q], g[q]);
+        g[q] = gn;
         acc += (double)gn * (double)gn;
     }
     double v[1] = {acc};
@@ -1189,14 +1238,17 @@ void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hip
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void filter_body(const T *__restrict__ r, T *__restrict__ out,
-                            const T *__restrict__ kern, const Geo &G, int out_padded, int a)
+__device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
+                            const T *__restrict__ kern_, const Geo &G, int out_padded, int a)
 {
+    const auto *r = gl(r_);
+    auto *out = gl(out_);
+    const auto *kern = gl(kern_);
     extern __shared__ unsigned char smem[];
     T *row = reinterpret_cast<T *>(smem);
     T *kk = row + G.nb;                  // kk[d + nb - 1] = k[|d|], d in (-nb, nb)
     const int nb = G.nb;
-    const T *ra = r + (size_t)a * G.rs + kSinoPadL;
+    const auto *ra = r + (size_t)a * G.rs + kSinoPadL;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) row[b] = ra[b];
     for (int d = threadIdx.x; d < 2 * nb - 1; d += blockDim.x) {
         const int dd = d - (nb - 1);
@@ -1214,7 +1266,7 @@ __device__ void filter_body(const T *__restrict__ r, T *__restrict__ out,
             if (b0 + 2 < nb) acc2 = fma(kk[base + 2], rv, acc2);
             if (b0 + 3 < nb) acc3 = fma(kk[base + 3], rv, acc3);
         }
-        T *oa = out + (size_t)a * (out_padded ? G.rs : nb) + (out_padded ? kSinoPadL : 0);
+        auto *oa = out + (size_t)a * (out_padded ? G.rs : nb) + (out_padded ? kSinoPadL : 0);
         oa[b0] = acc0;
         if (b0 + 1 < nb) oa[b0 + 1] = acc1;
         if (b0 + 2 < nb) oa[b0 + 2] = acc2;
@@ -1243,7 +1295,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_filter(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
-    const Solve<T> &d = S[m.solve];
+    const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     filter_body(d.r, d.rt, d.kern, d.G, 1, m.local);
 }
@@ -1266,14 +1318,14 @@ void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_
 template <typename T>
 __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
 {
-    const Solve<T> &d = S[blockIdx.x];
-    DevState *st = d.st;
+    const Solve<T> d = load_solve(S, blockIdx.x);
+    auto *st = gl(d.st);
     __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
     __shared__ int s_go, s_ell;
 
     if (fin == kFinTV) {
         final_sums(d.partials, d.nb_vec, 1, 1, tot);
-        if (threadIdx.x == 0) *d.tvd = tot[0];
+        if (threadIdx.x == 0) *gl(d.tvd) = tot[0];
         return;
     }
     if (st->done) return;
@@ -1290,7 +1342,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         const double f = 0.5 * tot[0];
         st->f_half = f;
         if (fin == kFinResidualStep)
-            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->f_half = f;
+            if (auto *tr = trace_at(st, d.trace)) tr->f_half = f;
         if (!isfinite(f)) {
             set_done(st, SCG_ENAN);
         } else if (f <= st->eps) {
@@ -1307,17 +1359,21 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     }
     case kFinNormQ:
     case kFinNormQCG: {
+        // arg0 = 1: a CG-STEP inside a CG-K pass, where a zero ||A p||^2 or
+        // a zero gradient (an exact minimiser) leaves x where it is
         final_sums(d.partials, d.nb_pj, 1, 1, tot);
         if (threadIdx.x != 0) return;
         const double s = tot[0];
         st->qq = s;
         if (!isfinite(s)) {
             set_done(st, SCG_ENAN);
+        } else if (arg0 == 1 && (s == 0.0 || st->delta == 0.0)) {
+            st->alpha = 0.0;
         } else if (s == 0.0) {
             set_done(st, SCG_EBREAKDOWN);
         } else {
             st->alpha = (fin == kFinNormQCG) ? st->delta / s : -st->gp / s;
-            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->alpha = st->alpha;
+            if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
         }
         return;
     }
@@ -1339,13 +1395,15 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         if (arg0 == 3) st->delta = st->gg;
         if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
         if (!arg1)
-            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) tr->beta = beta;
+            if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
         return;
     }
     case kFinXUpdateCG: {
+        // arg0 = 1: a CG-STEP inside a CG-K pass (the pass counts as one step)
         final_sums(d.partials, d.nb_vec, 1, 1, tot);
         if (threadIdx.x != 0) return;
         st->gg = tot[0];
+        if (arg0 == 1) return;
         st->qq_prev = st->qq;
         st->k += 1;
         st->steps += 1;
@@ -1379,7 +1437,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         st->trials_total += used;
         if (hit >= 0) {
             st->accepted = first_m + hit;
-            st->gamma = d.gtab[first_m + hit];
+            st->gamma = gl(d.gtab)[first_m + hit];
             st->search_done = 1;
         } else if (st->trials_step >= st->max_trials) {
             st->accepted = -1;
@@ -1387,7 +1445,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
             st->search_done = 1;
         }
         if (st->search_done) {
-            if (scg_trace_entry *tr = trace_at(st, d.trace, st->k)) {
+            if (auto *tr = trace_at(st, d.trace)) {
                 tr->accepted = st->accepted;
                 tr->trials = st->trials_step;
                 tr->ell = st->ell;
@@ -1403,15 +1461,18 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         // -s/||s||, replayed decisions, trace) and fills the trials' table.
         final_sums(d.partials, d.nb_xtv, 2, 2, tot);
         if (threadIdx.x == 0) {
-            st->qq_prev = st->qq;
-            st->gp_prev = st->gp;
-            st->k += 1;
-            st->steps += 1;
+            if (st->open) {
+                st->qq_prev = st->qq;
+                st->gp_prev = st->gp;
+                st->k += 1;
+                st->steps += 1;
+            }
+            st->open = 1;
             s_go = 0;
             if (st->steps >= st->max_iter) {
                 set_done(st, SCG_ENOCONV);
             } else {
-                const int k = st->k;
+                const int k = st->k + st->kofs;   // the step opened here
                 st->trials_step = 0;
                 st->accepted = -1;
                 st->gamma = 0.0;
@@ -1420,7 +1481,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
                 st->s_norm2 = tot[1];
                 const bool dir = tot[1] > 0.0 && isfinite(tot[1]);
                 st->inv_snorm = dir ? 1.0 / sqrt(tot[1]) : 0.0;
-                if (scg_trace_entry *tr = trace_at(st, d.trace, k)) {
+                if (auto *tr = trace_at(st, d.trace)) {
                     tr->k = k;
                     tr->accepted = -1;
                     tr->trials = 0;
@@ -1431,8 +1492,9 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
                     tr->tv_x = tot[0];
                     tr->f_half = 0.0;
                 }
-                if (!st->search_done && d.forced != nullptr && k - 1 < st->forced_len) {
-                    const int nt = d.forced[2 * (k - 1)], am = d.forced[2 * (k - 1) + 1];
+                if (!st->search_done && d.forced != nullptr && k >= 1 && k - 1 < st->forced_len) {
+                    const auto *fc = gl(d.forced);
+                    const int nt = fc[2 * (k - 1)], am = fc[2 * (k - 1) + 1];
                     const int l0 = st->ell;
                     double g = 0.0;
                     if (am >= 0 && dir) {
@@ -1445,7 +1507,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
                     st->accepted = dir ? am : -1;
                     st->gamma = g;
                     st->search_done = 1;
-                    if (scg_trace_entry *tr = trace_at(st, d.trace, k)) {
+                    if (auto *tr = trace_at(st, d.trace)) {
                         tr->accepted = st->accepted;
                         tr->trials = nt;
                         tr->ell = st->ell;
@@ -1482,8 +1544,9 @@ __global__ void kb_gather(const Solve<T> *S, int ns, DevState *out, double *tv)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns) return;
-    out[i] = *S[i].st;
-    tv[i] = *S[i].tvd;
+    const Solve<T> d = load_solve(S, i);
+    gl(out)[i] = *gl(d.st);
+    gl(tv)[i] = *gl(d.tvd);
 }
 
 template <typename T>

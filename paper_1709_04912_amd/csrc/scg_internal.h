@@ -101,7 +101,10 @@ struct DevState {
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
     double tv_out;
-    int is_f32, pad1;
+    int is_f32;
+    int restart_k;   // CG-STEPs per pass (S-CG-K)
+    int open;        // a step (pass) is open and is closed by the next loop launch
+    int kofs;        // trace entry of the open step: k + kofs
 };
 
 // Device descriptor of one solve: its geometry tables, the workspace

@@ -20,7 +20,7 @@ SCG_OK, SCG_EINVAL, SCG_ENOMEM, SCG_EDEVICE = 0, -1, -2, -3
 SCG_ENOCONV, SCG_ENAN, SCG_EBREAKDOWN = -4, -5, -6
 SCG_EAGAIN, SCG_EINPROGRESS, SCG_ENOTFOUND = -7, -8, -9
 SCG_F32, SCG_F64 = 0, 1
-VARIANTS = {"CG": 0, "S_CG": 1, "S_CG_CD": 2, "S_PCG": 3}
+VARIANTS = {"CG": 0, "S_CG": 1, "S_CG_CD": 2, "S_PCG": 3, "S_CG_K": 4}
 SCG_FLAG_NO_PERTURB = 1
 
 
@@ -32,7 +32,7 @@ class scg_params(C.Structure):
     _fields_ = [("variant", C.c_int32), ("prec", C.c_int32), ("eps", C.c_double),
                 ("gamma0", C.c_double), ("a", C.c_double), ("max_iter", C.c_int32),
                 ("max_trials", C.c_int32), ("tv_kappa", C.c_double),
-                ("precond_mu", C.c_double), ("flags", C.c_uint32)]
+                ("precond_mu", C.c_double), ("flags", C.c_uint32), ("restart_k", C.c_int32)]
 
 
 class scg_report(C.Structure):
@@ -255,7 +255,8 @@ class Plan:
     # -- solver ------------------------------------------------------------
     def params(self, eps: float, gamma0: float, variant: str = "S_CG", prec: int = SCG_F32,
                a: float = 0.975, max_iter: int = 1000, max_trials: int = 100,
-               kappa: float = 0.0, mu: float = 0.0, flags: int = 0) -> scg_params:
+               kappa: float = 0.0, mu: float = 0.0, flags: int = 0,
+               restart_k: int = 2) -> scg_params:
         p = scg_params()
         lib.scg_default_params(C.byref(p))
         p.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -263,6 +264,7 @@ class Plan:
         p.eps, p.gamma0, p.a = float(eps), float(gamma0), float(a)
         p.max_iter, p.max_trials = int(max_iter), int(max_trials)
         p.tv_kappa, p.precond_mu, p.flags = float(kappa), float(mu), int(flags)
+        p.restart_k = int(restart_k)
         return p
 
     def workspace_bytes(self, params: scg_params) -> int:

@@ -93,3 +93,69 @@ def test_pcg_k_and_cg_k_steps(oracle_lib):
         ref = alg.cg(prob, x0, eps=0.0, max_iter=K).x
         assert np.allclose(xk, ref, rtol=0, atol=1e-12 * np.linalg.norm(ref))
         assert f0 == pytest.approx(prob.f(x0))
+
+
+def test_scg_1_without_perturbation_is_steepest_descent(oracle_lib):
+    """S-CG-K with K = 1 and gamma0 = 0 restarts CG after every step: each
+    pass is one exact line search along -g, x' = x - (g^T g / ||A g||^2) g
+    (written here with the dense matrix). The loop tests f of the pass's
+    input, so the output after m passes is the (m-1)-th iterate."""
+    g, A, y = _small_problem(oracle_lib, n=6, na=12, nb=9, seed=6)
+    prob = alg.Problem(g, y)
+    x = np.zeros(g.J)
+    sd = [x.copy()]
+    for _ in range(8):
+        gr = A.T @ (A @ x - y)
+        Ag = A @ gr
+        x = x - (gr @ gr) / (Ag @ Ag) * gr
+        sd.append(x.copy())
+    f = [0.5 * float(np.sum((A @ v - y) ** 2)) for v in sd]
+    for m in range(1, 7):
+        # eps between f of the (m-1)-th and the (m-2)-th iterate: m passes
+        eps = 0.5 * (f[m - 1] + f[m - 2]) if m >= 2 else 1.5 * f[0]
+        res = alg.scg_k(prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(0.0), K=1)
+        want_k = m if m >= 2 else 0
+        assert res.k == want_k, (m, res.k)
+        ref = sd[max(want_k - 1, 0)]
+        assert np.linalg.norm(res.x - ref) <= 1e-10 * max(np.linalg.norm(ref), 1e-30)
+        assert res.f_out <= eps
+
+
+def test_scg_k_passes_are_krylov_minimisers(oracle_lib):
+    """With gamma0 = 0, every S-CG-2 pass minimises f over x + span{g, H g}
+    (H = A^T A) from the pass's input x: a dense QR of that Krylov space."""
+    g, A, y = _small_problem(oracle_lib, n=6, na=14, nb=9, seed=7)
+    prob = alg.Problem(g, y)
+    H = A.T @ A
+    x = np.zeros(g.J)
+    xs = [x.copy()]
+    for _ in range(5):
+        gr = A.T @ (A @ x - y)
+        Kb = np.stack([gr, H @ gr], axis=1)
+        Q, _ = np.linalg.qr(Kb)
+        c, *_ = np.linalg.lstsq(A @ Q, y - A @ x, rcond=None)
+        x = x + Q @ c
+        xs.append(x.copy())
+    f = [0.5 * float(np.sum((A @ v - y) ** 2)) for v in xs]
+    for m in (2, 3, 4, 5):
+        eps = 0.5 * (f[m - 1] + f[m - 2])
+        res = alg.scg_k(prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(0.0), K=2)
+        assert res.k == m
+        assert np.linalg.norm(res.x - xs[m - 1]) <= 1e-9 * np.linalg.norm(xs[m - 1])
+
+
+def test_scg_k_terminates_below_eps(oracle_lib):
+    """With perturbations (gamma0 > 0) S-CG-2 stops with f(output) <= eps for
+    eps above the least-squares floor, and f(x0) <= eps returns x0 at k = 0."""
+    g, A, y = _small_problem(oracle_lib, n=8, na=20, nb=13, seed=8)
+    prob = alg.Problem(g, y)
+    eps0, _ = alg.ls_floor_dense(g, y)
+    x1 = alg.cg(prob, np.zeros(g.J), eps=0.0, max_iter=1).x
+    pp = alg.PerturbParams(gamma0=0.05 * float(np.linalg.norm(x1)))
+    res = alg.scg_k(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, K=2, max_iter=2000)
+    assert res.status == "ok" and res.f_out <= 1.1 * eps0
+    assert prob.f(res.x) == pytest.approx(res.f_out, rel=1e-12)
+    x0 = np.full(g.J, 0.3)
+    big = 2 * prob.f(x0)
+    res0 = alg.scg_k(prob, x0, eps=big, pp=pp, K=2)
+    assert res0.k == 0 and np.array_equal(res0.x, x0)
