@@ -384,9 +384,12 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     HIP_TRY(hipMemcpyAsync(ws + L.desc, &h, sizeof(h), hipMemcpyHostToDevice, s));
 
     // x_{1/2} = x0 (S-CG, S-CG-CD, S-PCG) or x_0 (CG, S-CG-K).
+    // S-CG-K also starts x_{-1/2} = x0 in x_{k+1/2}'s buffer: the output when
+    // f(x0) <= eps ends the loop before the first pass.
     T *x_start = (is_cg || is_k) ? h.x : h.xh;
     if (x0_ != nullptr) launch_copy<T>(x_start, static_cast<const T *>(x0_), J, nullptr, s);
     else launch_fill<T>(x_start, J, T(0), s);
+    if (is_k) launch_copy<T>(h.xh, h.x, J, nullptr, s);
     return SCG_OK;
 }
 

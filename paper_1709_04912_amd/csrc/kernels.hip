@@ -415,13 +415,22 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
             if (slot < grp.count) {
                 const auto &A = pang[grp.a0 + slot];
                 const double us = fma((double)i0, A.slope, u0[m]);
+                // The band adds exactly zero for a ray whose crossings stay
+                // left of column -1 or right of column n over its 16 rows
+                // (both split columns are zero padding); skip it when that
+                // holds for the whole wavefront.
+                const double ue = fma((double)(kPjBand - 1), A.slope, us);
+                const bool miss = fmax(us, ue) < -1.0 || fmin(us, ue) > (double)n;
+                if (__all(miss)) continue;
                 const double fu = floor(us);
                 const T *col0 = lds + ((int)fu - jw) * LS;
                 const T F0 = (T)(us - fu);
                 const T slope = (T)A.slope;
                 const T K = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
                 const T C = sizeof(T) == 4 ? (T)A.Cf : (T)A.C;
-                T a_ = acc[m], ar = accr[m];
+                // the band's 16 terms are summed apart and then added to the
+                // ray's sum: rounding grows with 16 + bands, not with N
+                T a_ = T(0), ar = T(0);
 #pragma unroll
                 for (int k = 0; k < kPjBand; ++k) {
                     const T v = fma((T)k, slope, F0);
@@ -432,8 +441,8 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                     a_ = fma(wl, xl - xr, a_);
                     ar += xr;
                 }
-                acc[m] = a_;
-                accr[m] = ar;
+                acc[m] += a_;
+                accr[m] += ar;
             }
         }
         band = nxt;
@@ -649,6 +658,9 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         __syncthreads();
         if (ch + NS < nchunks) prefetch(ch + NS);
         const int na = live ? min(kBpChunk, G.na - ch * kBpChunk) : 0;
+        // the chunk's terms are summed apart and then added to the pixel's
+        // sum: rounding grows with the chunk size plus the chunk count
+        T s0 = T(0), s1 = T(0), e0 = T(0), e1 = T(0);
 #pragma unroll 2
         for (int al = 0; al < na; ++al) {
             const T *pr = &prm[gs][al * kBpPrm];
@@ -660,17 +672,23 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             const T f0 = frc(u0), f1 = frc(u1);
             const T w00 = sat(fma(f0, -K, C)), w01 = sat(fma(f0, K, CK));
             const T w10 = sat(fma(f1, -K, C)), w11 = sat(fma(f1, K, CK));
-            acc0 = fma(w00, row[b0], acc0);
-            acc0 = fma(w01, row[b0 + 1], acc0);
-            acc1 = fma(w10, row[b1], acc1);
-            acc1 = fma(w11, row[b1 + 1], acc1);
+            s0 = fma(w00, row[b0], s0);
+            s0 = fma(w01, row[b0 + 1], s0);
+            s1 = fma(w10, row[b1], s1);
+            s1 = fma(w11, row[b1 + 1], s1);
             if (DUAL) {
                 const T *row2 = &win[gs][NW - 1][al * kBpWin];
-                bcc0 = fma(w00, row2[b0], bcc0);
-                bcc0 = fma(w01, row2[b0 + 1], bcc0);
-                bcc1 = fma(w10, row2[b1], bcc1);
-                bcc1 = fma(w11, row2[b1 + 1], bcc1);
+                e0 = fma(w00, row2[b0], e0);
+                e0 = fma(w01, row2[b0 + 1], e0);
+                e1 = fma(w10, row2[b1], e1);
+                e1 = fma(w11, row2[b1 + 1], e1);
             }
+        }
+        acc0 += s0;
+        acc1 += s1;
+        if (DUAL) {
+            bcc0 += e0;
+            bcc1 += e1;
         }
     }
 
@@ -1315,30 +1333,17 @@ void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_
 // leaves the state alone.
 // ---------------------------------------------------------------------------
 
+// Scalar logic of the finishers on the LDS copy of the state; every thread
+// of the block calls it (the sums are shared), thread 0 applies the logic.
 template <typename T>
-__global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
+__device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0, int arg1,
+                             double *tot, int &s_go, int &s_ell)
 {
-    const Solve<T> d = load_solve(S, blockIdx.x);
-    auto *st = gl(d.st);
-    __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
-    __shared__ int s_go, s_ell;
-
-    if (fin == kFinTV) {
-        final_sums(d.partials, d.nb_vec, 1, 1, tot);
-        if (threadIdx.x == 0) *gl(d.tvd) = tot[0];
-        return;
-    }
-    if (st->done) return;
-    if (fin == kFinCGCap) {
-        if (threadIdx.x == 0 && st->steps >= st->max_iter) set_done(st, SCG_ENOCONV);
-        return;
-    }
-
     switch (fin) {
     case kFinResidual:
     case kFinResidualStep: {
         final_sums(d.partials, d.nb_pj, 1, 1, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         const double f = 0.5 * tot[0];
         st->f_half = f;
         if (fin == kFinResidualStep)
@@ -1362,7 +1367,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         // arg0 = 1: a CG-STEP inside a CG-K pass, where a zero ||A p||^2 or
         // a zero gradient (an exact minimiser) leaves x where it is
         final_sums(d.partials, d.nb_pj, 1, 1, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         const double s = tot[0];
         st->qq = s;
         if (!isfinite(s)) {
@@ -1380,7 +1385,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     case kFinDotGH:
     case kFinDotGG: {
         final_sums(d.partials, d.nb_bp, 1, 1, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         if (fin == kFinDotGH) st->gh = tot[0];
         else st->gg = tot[0];
         return;
@@ -1388,7 +1393,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     case kFinPUpdate: {
         // arg0 = rule, arg1 = init
         final_sums(d.partials, d.nb_t32, 1, 1, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         const double beta = beta_of(st, arg0, arg1);
         st->beta = beta;
         st->gp = tot[0];
@@ -1401,7 +1406,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     case kFinXUpdateCG: {
         // arg0 = 1: a CG-STEP inside a CG-K pass (the pass counts as one step)
         final_sums(d.partials, d.nb_vec, 1, 1, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         st->gg = tot[0];
         if (arg0 == 1) return;
         st->qq_prev = st->qq;
@@ -1418,7 +1423,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
         const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
         const int stride = 1 + kTrialsPerPass * nchunks;
         final_sums(d.partials, nblk, stride, stride, tot);
-        if (threadIdx.x != 0) return;
+        if (threadIdx.x != 0) return;   // the block's other threads are done
         const bool with_tvx = first_m == 0;
         const double tvx = with_tvx ? tot[0] : st->tv_x;
         if (with_tvx) st->tv_x = tvx;
@@ -1529,6 +1534,39 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     default:
         return;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
+{
+    const Solve<T> d = load_solve(S, blockIdx.x);
+    __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
+    __shared__ int s_go, s_ell;
+    __shared__ DevState sst;
+
+    if (fin == kFinTV) {
+        final_sums(d.partials, d.nb_vec, 1, 1, tot);
+        if (threadIdx.x == 0) *gl(d.tvd) = tot[0];
+        return;
+    }
+    // The state comes into LDS in one round trip of all its words; thread 0
+    // works on that copy and the block writes it back at the end.
+    constexpr int kWords = sizeof(DevState) / 4;
+    static_assert(sizeof(DevState) % 4 == 0, "state copied in 32-bit words");
+    const auto *gw = reinterpret_cast<const unsigned *>(d.st);
+    unsigned *sw = reinterpret_cast<unsigned *>(&sst);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) sw[i] = gl(gw)[i];
+    __syncthreads();
+    if (sst.done) return;
+    DevState *st = &sst;
+    if (fin == kFinCGCap) {
+        if (threadIdx.x == 0 && st->steps >= st->max_iter) set_done(st, SCG_ENOCONV);
+    } else {
+        finish_logic(d, st, fin, arg0, arg1, tot, s_go, s_ell);
+    }
+    __syncthreads();
+    auto *gwo = reinterpret_cast<unsigned *>(d.st);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) gl(gwo)[i] = sw[i];
 }
 
 template <typename T>

@@ -40,12 +40,19 @@ def torch_mod():
     return torch
 
 
-def _case(oracle_lib, seed):
+# eps / eps0 per variant. S-CG-K (restarted CG-2 passes) needs hundreds of
+# passes to reach 1.1 eps0 on these workloads, and over that many passes a
+# 1e-15 change of y moves the FP64 oracle's own output by 5e-6; at 2 eps0 it
+# stops after 15-41 passes and the same change moves it by < 1e-9.
+EPS_FACTOR = {"S_CG_K": 2.0}
+
+
+def _case(oracle_lib, seed, variant="S_CG"):
     gd = _golden()[f"cfg1_s{seed}"]
     w = make_workload(1, seed, supersample=2)
     g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
     prob = alg.Problem(g, w.y)
-    eps = 1.1 * gd["eps0"]
+    eps = EPS_FACTOR.get(variant, 1.1) * gd["eps0"]
     gamma0 = 0.05 * gd["x1_norm"]
     return w, g, prob, eps, gamma0
 
@@ -58,15 +65,17 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg}
+ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg,
+             "S_CG_K": lambda prob, x0, eps, pp, max_iter: alg.scg_k(prob, x0, eps, pp, K=2,
+                                                                     max_iter=max_iter)}
 
 
-@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG"])
+@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_K"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
     print(f"[solver fp64] variant={variant} seed={seed}", flush=True)
-    w, g, prob, eps, gamma0 = _case(oracle_lib, seed)
+    w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
     ref = ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0),
                              max_iter=1000)
     assert ref.status == "ok"
@@ -87,7 +96,7 @@ def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
 def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
     print(f"[solver fp32] variant={variant} seed={seed}", flush=True)
-    w, g, prob, eps, gamma0 = _case(oracle_lib, seed)
+    w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
     ref = ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0),
                              max_iter=1000)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
@@ -105,6 +114,43 @@ def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     assert prob.f(xg) <= eps * (1 + 1e-5)
     assert rep.k == ref.k
     assert _rel(xg, ref.x) <= 1e-4
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fp32_parity_scg_k(scg, torch_mod, oracle_lib, seed):
+    """S-CG-K in FP32. CG-K's recursive gradient amplifies rounding across
+    passes, so the image bound is the oracle's own amplification of a
+    relative change of y (measured in FP64) applied to FP32's unit roundoff,
+    times 10, and it is checked after a fixed number of passes with the
+    oracle's decisions replayed (the stop test then cannot differ). Run to
+    the stop, the FP32 solve meets eps within one pass of the oracle's k."""
+    torch = torch_mod
+    print(f"[solver fp32] variant=S_CG_K seed={seed}", flush=True)
+    w, g, prob, eps, gamma0 = _case(oracle_lib, seed, "S_CG_K")
+    pp = alg.PerturbParams(gamma0)
+    ref = alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=1000)
+    passes = max(ref.k - 2, 1)
+    ref_n = alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=passes)
+    alt_n = alg.scg_k(alg.Problem(g, w.y * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
+                      max_iter=passes)
+    amp = _rel(alt_n.x, ref_n.x) / 1e-12
+    tol = max(1e-4, 10 * amp * 2.0 ** -24)
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        p_n = plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K", prec=scg.SCG_F32,
+                          max_iter=passes)
+        x_n, rep_n, _ = plan.solve(y, p_n, forced=[(t["trials"], t["accepted"])
+                                                   for t in ref_n.trace])
+        x, rep, _ = plan.solve(y, plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
+                                              prec=scg.SCG_F32, max_iter=1000), trace=False)
+    rel_n = _rel(x_n.cpu().numpy().astype(np.float64), ref_n.x)
+    print(f"  {passes} passes: rel={rel_n:.2e} (amplification {amp:.3g}, tolerance {tol:.2e}); "
+          f"full: k={rep.k} ref_k={ref.k}")
+    assert rep_n.status == scg.SCG_ENOCONV and rep_n.k == passes == ref_n.k
+    assert rel_n <= tol
+    xg = x.cpu().numpy().astype(np.float64)
+    assert rep.status == scg.SCG_OK and rep.f_out <= eps and prob.f(xg) <= eps * (1 + 1e-5)
+    assert abs(rep.k - ref.k) <= 1
 
 
 def test_cg_parity(scg, torch_mod, oracle_lib):
@@ -191,3 +237,30 @@ def test_solver_deterministic(scg, torch_mod, oracle_lib):
         x1, r1, t1 = plan.solve(y, p)
         x2, r2, t2 = plan.solve(y, p)
     assert torch.equal(x1, x2) and r1.k == r2.k and t1 == t2
+
+
+def test_scg_k_edges(scg, torch_mod, oracle_lib):
+    """S-CG-K's counter: f(x0) <= eps returns x0 with k = 0; max_iter = 0
+    ends before the first pass; K = 1 and K = 3 against the oracle."""
+    torch = torch_mod
+    w, g, prob, eps, gamma0 = _case(oracle_lib, 1, "S_CG_K")
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        f0 = 0.5 * float(np.sum(w.y ** 2))
+        x, rep, _ = plan.solve(y, plan.params(eps=2 * f0, gamma0=gamma0, variant="S_CG_K",
+                                              prec=scg.SCG_F64))
+        assert rep.status == scg.SCG_OK and rep.k == 0 and float(x.abs().max()) == 0.0
+        x, rep, _ = plan.solve(y, plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
+                                              prec=scg.SCG_F64, max_iter=0))
+        assert rep.status == scg.SCG_ENOCONV and rep.k == 0
+        for K in (1, 3):
+            ref = alg.scg_k(prob, np.zeros(g.J), eps, alg.PerturbParams(gamma0), K=K,
+                            max_iter=1000)
+            x, rep, trace = plan.solve(y, plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
+                                                      prec=scg.SCG_F64, restart_k=K))
+            assert rep.status == scg.SCG_OK and rep.k == ref.k, (K, rep.k, ref.k)
+            assert _decisions(trace) == [(t["trials"], t["accepted"]) for t in ref.trace]
+            assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
+        with pytest.raises(scg.ScgError):
+            plan.workspace_bytes(plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
+                                             restart_k=0))
