@@ -129,13 +129,17 @@ def mixed_runs(n_serve):
     reqs = build([make_batch_item(i) for i in range(64)])
     warm(reqs)
     b = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, keep_outputs=True)
+    be = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, graph=False,
+                             keep_outputs=True)
     p = serve.serve_plain(reqs, keep_outputs=True)
     batched = {
         "workload": "64 S-CG solves, N in {128,256,384,512}, angles in {180,360,540,720}, "
                     "bins ceil(sqrt(2)N)+1, sigma U[0.5%,3%], eps = f(x_true)",
         "batched_recons_per_s": b.recons_per_s, "plain_recons_per_s": p.recons_per_s,
         "speedup": b.recons_per_s / p.recons_per_s,
-        "bitwise_equal_outputs": same(p, b), "solves": len(reqs),
+        "batched_without_graph_recons_per_s": be.recons_per_s,
+        "bitwise_equal_outputs": same(p, b), "bitwise_equal_without_graph": same(p, be),
+        "solves": len(reqs),
         "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports))}
     log(f"batched: {batched}")
     pool = 120

@@ -331,9 +331,9 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // has one angle per slot). The block walks bands of kPjBand steps along the
 // group's major axis (rows of x, or rows of x^T for angles stepping over
 // columns), staging kPjWin columns of each band in LDS, column-major with a
-// stride of kPjBand + 1 elements so neighbouring columns fall in different
-// banks; the next band is prefetched into registers while the current one
-// is consumed. Within a band a ray's crossing coordinate is an integer anchor
+// stride of kPjBand + 1 elements (the two split columns of a step are one
+// paired read); the next band is prefetched into registers while the
+// current one is consumed. Within a band a ray's crossing coordinate is an integer anchor
 // plus an FP32 fraction (the anchor from FP64), so the split weights stay
 // accurate near the axes where the chord ramp is steep. Per step: the
 // crossing, its floor and fraction, one clamped FMA for the split weight, two
@@ -416,9 +416,9 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 const auto &A = pang[grp.a0 + slot];
                 const double us = fma((double)i0, A.slope, u0[m]);
                 // The band adds exactly zero for a ray whose crossings stay
-                // left of column -1 or right of column n over its 16 rows
-                // (both split columns are zero padding); skip it when that
-                // holds for the whole wavefront.
+                // left of column -1 or right of column n over its rows (both
+                // split columns are zero padding); skip it when that holds
+                // for the whole wavefront.
                 const double ue = fma((double)(kPjBand - 1), A.slope, us);
                 const bool miss = fmax(us, ue) < -1.0 || fmin(us, ue) > (double)n;
                 if (__all(miss)) continue;
@@ -428,8 +428,9 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 const T slope = (T)A.slope;
                 const T K = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
                 const T C = sizeof(T) == 4 ? (T)A.Cf : (T)A.C;
-                // the band's 16 terms are summed apart and then added to the
-                // ray's sum: rounding grows with 16 + bands, not with N
+                // the band's terms are summed apart and then added to the
+                // ray's sum: rounding grows with the band plus the band count,
+                // not with N
                 T a_ = T(0), ar = T(0);
 #pragma unroll
                 for (int k = 0; k < kPjBand; ++k) {

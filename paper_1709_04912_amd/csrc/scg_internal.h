@@ -17,7 +17,7 @@ namespace scg {
 // (group, bin chunk, band) is precomputed on the host (kWinSkip: the band
 // holds no pixel any of the block's rays crosses).
 constexpr int kPjBins = 128;
-constexpr int kPjBand = 16;
+constexpr int kPjBand = 32;
 constexpr int kPjWin = 256;
 constexpr int kPjGroup = 8;
 constexpr int kWinSkip = -0x40000000;
