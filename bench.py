@@ -51,6 +51,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_kb_project_kb_backproject_512x512_720x729.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1709_04912_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE
+    / WRITE_SIZE summary, or None when the kernels have changed since the
+    counters were taken (the summary records the source's sha256)."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernels\.hip sha256: ([0-9a-f]{64})", text)
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if m is None or m.group(1) != digest:
+        return None
+    m = re.search(rf"^traffic_bytes_per_launch {kernel}: (\d+)$", text, flags=re.M)
+    return int(m.group(1)) if m else None
+
+
 def count_nnz(n, n_angles, n_bins):
     """Exact number of nonzero entries of A: for every angle and pixel, the
     bins b whose line crosses the pixel square with positive length, i.e.
@@ -272,7 +293,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": measured_traffic("kb_" + dominant),
             "per_launch": {"nnz": nnz, "ops_per_nnz": OPS_PER_NNZ, "avg_us": avg_s * 1e6,
                            "launches": int(launches), "tail_launches": int(tail_launches),
                            "compulsory_hbm_GBs": compulsory / avg_s / 1e9,

@@ -365,6 +365,59 @@ def scg(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000,
                   records=records, ell=ell)
 
 
+def scg_qrec(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
+    """Alg. S-CG with CG-PR-STEP rewritten with q = A p carried by linearity.
+
+    With h = A^T A p: p^T h = ||A p||^2 and g'^T h = (A g')^T (A p), so beta =
+    (A g')^T q / ||q||^2; and A p' = A(-g' + beta p) = -A g' + beta q. A step
+    then needs A x_{k+1/2}, A^T r and A g' (two projections and one
+    backprojection) instead of two of each. The same iteration in exact
+    arithmetic; q accumulates rounding like a recursive residual."""
+    x0 = np.array(x0, dtype=np.float64).reshape(-1)
+    x_half = x0.copy()
+    r = prob.residual(x0)
+    f_half = 0.5 * float(r @ r)
+    g = prob.AT(r)
+    p = -g
+    q = prob.A(p)                               # q0 = A p0
+    qq = float(q @ q)
+    if qq == 0.0:
+        return Result(x=x_half, k=1, steps=0, status="breakdown", f_out=f_half)
+    alpha = -float(g @ p) / qq
+    x = x0 + alpha * p
+    k, ell = 1, 0
+    trace = []
+    status = "ok"
+    while f_half > eps:
+        if k - 1 >= max_iter:
+            status = "noconv"
+            break
+        xh, ell, info = perturbed(prob.g, x, ell, pp)
+        r = prob.residual(xh)
+        f_half = 0.5 * float(r @ r)
+        g_new = prob.AT(r)
+        u = prob.A(g_new)                       # A g'
+        beta = float(u @ q) / qq                # (A g')^T q / ||q||^2
+        p_new = -g_new + beta * p
+        q_new = -u + beta * q                   # A p' by linearity
+        qq_new = float(q_new @ q_new)
+        if qq_new == 0.0:
+            status = "breakdown"
+            x_half = xh
+            k += 1
+            break
+        gp = float(g_new @ p_new)
+        alpha = -gp / qq_new
+        x_new = xh + alpha * p_new
+        trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
+                      "trials": info.trials, "ell": ell, "gamma": info.gamma,
+                      "beta": beta, "alpha": alpha, "gp": gp, "qq": qq_new})
+        x_half, x, p, q, qq = xh, x_new, p_new, q_new, qq_new
+        k += 1
+    return Result(x=x_half, k=k, steps=len(trace), status=status, f_out=f_half, trace=trace,
+                  ell=ell)
+
+
 def scg_cd(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
     """Alg. S-CG-CD with CG-CD-STEP (beta = -||g'||^2 / g^T p, the
     conjugate-descent rule); the step carries g instead of h."""

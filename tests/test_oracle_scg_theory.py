@@ -139,3 +139,28 @@ def test_tv_not_above_unsuperiorized_cg(oracle_lib):
         if g.tv(s.x) <= g.tv(cg.x):
             wins += 1
     assert wins == len(seeds)
+
+
+def test_scg_q_recurrence_equals_scg(oracle_lib):
+    """S-CG with q = A p carried by linearity (beta from (A g')^T q) is the
+    same iteration as the literal CG-PR-STEP: identical decisions and k, and
+    iterates equal to rounding in FP64 (two seeds, with perturbations)."""
+    import numpy as np
+    from oracle import algorithms as alg
+    for seed in (11, 12):
+        g = oracle_lib.Geometry(16, 24, 25)
+        rng = np.random.default_rng(seed)
+        A = g.dense()
+        y = A @ rng.uniform(0, 1, g.J) + 0.05 * rng.standard_normal(g.L)
+        prob = alg.Problem(g, y)
+        eps0, _ = alg.ls_floor_dense(g, y)
+        x1 = alg.cg(prob, np.zeros(g.J), eps=0.0, max_iter=1).x
+        pp = alg.PerturbParams(gamma0=0.05 * float(np.linalg.norm(x1)))
+        a = alg.scg(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, max_iter=500)
+        b = alg.scg_qrec(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, max_iter=500)
+        assert a.status == b.status == "ok" and a.k == b.k
+        assert [(t["trials"], t["accepted"]) for t in a.trace] == \
+            [(t["trials"], t["accepted"]) for t in b.trace]
+        assert np.linalg.norm(a.x - b.x) <= 1e-8 * np.linalg.norm(a.x)
+        for ta, tb in zip(a.trace, b.trace):
+            assert abs(ta["beta"] - tb["beta"]) <= 1e-7 * max(abs(ta["beta"]), 1e-12)
