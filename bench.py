@@ -182,6 +182,33 @@ def mixed_runs(n_serve):
     return batched, served
 
 
+def three_operator_run(plan, y, params, out_scg, ws, stream, w, steps):
+    """The same solves with CG-PR-STEP evaluated by the q = A p recursion (two
+    projections and one backprojection per step): throughput, stopping step
+    and the image's distance from the literal S-CG output."""
+    import numpy as np
+    import torch
+    from paper_1709_04912_amd import scg
+    p3 = scg.scg_params.from_buffer_copy(params)
+    p3.variant = scg.VARIANTS["S_CG_3OP"]
+    out = torch.empty_like(out_scg)
+    _, rep, _ = plan.solve(y, p3, out=out, ws=ws, trace=False, stream=stream)
+    n = max(3, steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        _, rep, _ = plan.solve(y, p3, out=out, ws=ws, trace=False, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    a = out.double().cpu().numpy()
+    b = out_scg.double().cpu().numpy()
+    return {"variant": "S_CG_3OP", "value": n / elapsed, "unit": "recons/s", "solves": n,
+            "status": rep.status, "k": rep.k, "steps_per_solve": rep.steps, "f_out": rep.f_out,
+            "rel_diff_vs_s_cg": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "rel_err_vs_phantom": float(np.linalg.norm(a - w.x_true.reshape(-1))
+                                        / np.linalg.norm(w.x_true))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +327,7 @@ def main():
                            "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM},
         },
     }
+    result["three_operator"] = three_operator_run(plan, y, params, out, ws, stream, w, args.steps)
     if not args.no_mix:
         result["batched"], result["served"] = mixed_runs(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -64,8 +64,14 @@ typedef enum {
     SCG_S_CG = 1,    /* Alg. S-CG with CG-PR-STEP                              */
     SCG_S_CG_CD = 2, /* Alg. S-CG-CD with CG-CD-STEP (conjugate-descent beta)  */
     SCG_S_PCG = 3,   /* Alg. S-PCG with PCG-PR-STEP (filtered preconditioner)  */
-    SCG_S_CG_K = 4   /* Alg. S-CG-K: perturbed(x_k), then CG-K (K = restart_k  */
+    SCG_S_CG_K = 4,  /* Alg. S-CG-K: perturbed(x_k), then CG-K (K = restart_k  */
                      /* CG-STEPs) restarted from the perturbed point           */
+    SCG_S_CG_3OP = 5 /* Alg. S-CG with CG-PR-STEP evaluated with q = A p kept  */
+                     /* by linearity: beta = (A g')^T q / ||q||^2 and          */
+                     /* q' = -A g' + beta q, so a step applies A twice and A^T */
+                     /* once (h = A^T A p is never formed). The same iterates  */
+                     /* as SCG_S_CG in exact arithmetic; q accumulates the     */
+                     /* rounding of its recursion (Sec. 3 (CG-PR-STEP))        */
 } scg_variant;
 
 /* flags of scg_params.flags */

@@ -365,7 +365,7 @@ def scg(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000,
                   records=records, ell=ell)
 
 
-def scg_qrec(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
+def scg_3op(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
     """Alg. S-CG with CG-PR-STEP rewritten with q = A p carried by linearity.
 
     With h = A^T A p: p^T h = ||A p||^2 and g'^T h = (A g')^T (A p), so beta =

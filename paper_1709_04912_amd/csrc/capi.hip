@@ -247,7 +247,7 @@ void prof_drain(scg_plan *p, int last_iter)
 int check_params(const scg_params *pr)
 {
     if (pr == nullptr) return SCG_EINVAL;
-    if (pr->variant < SCG_CG || pr->variant > SCG_S_CG_K) return SCG_EINVAL;
+    if (pr->variant < SCG_CG || pr->variant > SCG_S_CG_3OP) return SCG_EINVAL;
     if (pr->variant == SCG_S_CG_K && (pr->restart_k < 1 || pr->restart_k > 64)) return SCG_EINVAL;
     if (pr->prec != SCG_F32 && pr->prec != SCG_F64) return SCG_EINVAL;
     if (!(pr->eps > 0.0) || !std::isfinite(pr->eps)) return SCG_EINVAL;
@@ -408,6 +408,7 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     // padded projection plus the filter taps must fit in LDS.
     if ((size_t)scg::blocks_bp(G) > (size_t)scg::kMaxPartials ||
         2 * (size_t)scg::blocks_xtv(G) > (size_t)scg::kMaxPartials ||
+        (size_t)scg::blocks_t32(G) + scg::blocks_sv(G) > (size_t)scg::kMaxPartials ||
         (size_t)3 * G.nb * sizeof(double) > 65536) {
         delete p;
         return SCG_EINVAL;

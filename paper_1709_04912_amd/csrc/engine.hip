@@ -70,7 +70,7 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
 }
 
 // Block kinds of the phase launches.
-enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKinds };
+enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKPQ, kKinds };
 
 template <typename T> int count_of(const Solve<T> &d, int kind)
 {
@@ -83,6 +83,7 @@ template <typename T> int count_of(const Solve<T> &d, int kind)
     case kKBp: return d.nb_bp;
     case kKVec: return d.nb_vec;
     case kKFilt: return d.G.na;
+    case kKPQ: return d.nb_t32 + d.nb_sv;
     default: return 0;
     }
 }
@@ -150,6 +151,14 @@ template <typename T> struct Enq {
         }
         finish(kFinPUpdate, rule, init);
     }
+    void pq_update() const
+    {
+        {
+            Prof t(g.prof, SCG_KC_VECTOR, s);
+            launch_b_pq_update<T>(g.S, m(kKPQ), n(kKPQ), s);
+        }
+        finish(kFinPQ);
+    }
     void filter() const
     {
         Prof t(g.prof, SCG_KC_FILTER, s);
@@ -193,7 +202,7 @@ template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
     }
     e.project(kPjQ);
     e.finish(kFinNormQ);
-    if (g.variant != SCG_S_CG_CD) e.backproject(kBpH, 0);
+    if (g.variant != SCG_S_CG_CD && g.variant != SCG_S_CG_3OP) e.backproject(kBpH, 0);
 }
 
 // One loop iteration. S- variants: close the previous step (x_{k+1} =
@@ -260,6 +269,15 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
             e.finish(kFinXUpdateCG, 1);
             if (j + 1 < g.restart_k) e.p_update(3, 0);
         }
+        return;
+    }
+    if (g.variant == SCG_S_CG_3OP) {
+        // CG-PR-STEP with q = A p carried by linearity: g' = A^T r (and its
+        // transpose), u = A g' with u^T q = g'^T h, then p' and q' = -u + beta q
+        e.backproject(kBpGT, 0);
+        e.project(kPjU);
+        e.finish(kFinDotUQ);
+        e.pq_update();
         return;
     }
     if (g.variant == SCG_S_PCG) {
@@ -339,6 +357,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.nb_vec = blocks_vec(J);
     h.nb_pj = h.P.n_chunks * h.P.n_groups;
     h.nb_bp = blocks_bp(G);
+    h.nb_sv = blocks_sv(G);
     h.trB_chunks = (std::max(pr->max_trials - kTrialsPerPass, 0) + kTrialsPerPass - 1) /
                    kTrialsPerPass;
     h.nb_trA = blocks_trials(G, 1);

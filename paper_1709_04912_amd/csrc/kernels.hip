@@ -202,6 +202,7 @@ __device__ __forceinline__ BlkMap locate(const BlkMap *map, int swz = 0)
 int blocks_xtv(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 7) / 8); }
 int blocks_t32(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 31) / 32); }
 int blocks_vec(size_t n) { return vec_blocks(n); }
+int blocks_sv(const Geo &G) { return G.na; }
 int blocks_bp(const Geo &G)
 {
     const int t = (G.n + kBpTile - 1) / kBpTile;
@@ -338,14 +339,15 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // accurate near the axes where the chord ramp is steep. Per step: the
 // crossing, its floor and fraction, one clamped FMA for the split weight, two
 // LDS reads and three FMAs/adds. With y given, out = A x - y. With partials
-// given, the block stores its sum of out^2.
+// given, the block stores its sum of out^2, or of out * dotv with dotv given
+// (same layout as out).
 // ---------------------------------------------------------------------------
 
 template <typename T, int NQ, int GA>
 __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, const Geo &G,
                              const ProjTables &P, const T *__restrict__ y, int y_stride,
-                             T *__restrict__ out, int out_stride, int out_off, double *partials,
-                             VBlk vb)
+                             T *__restrict__ out, int out_stride, int out_off,
+                             const T *__restrict__ dotv, double *partials, VBlk vb)
 {
     constexpr int NT = kPjBins * NQ;
     constexpr int LS = kPjBand + 1;               // LDS column stride (elements)
@@ -458,8 +460,10 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
             const T im = sizeof(T) == 4 ? (T)pang[a].inv_mf : (T)pang[a].inv_m;
             T val = (acc[m] + accr[m]) * im;
             if (y != nullptr) val -= gl(y)[(size_t)a * y_stride + b];
-            gl(out)[(size_t)a * out_stride + out_off + b] = val;
-            sq += (double)val * (double)val;
+            const size_t o = (size_t)a * out_stride + out_off + b;
+            gl(out)[o] = val;
+            const T w = dotv != nullptr ? gl(dotv)[o] : val;
+            sq += (double)val * (double)w;
         }
     }
     if (partials == nullptr) return;
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ 
                                                           ProjTables P, T *__restrict__ out,
                                                           int out_stride, int out_off, int swz)
 {
-    project_body<T, NQ, GA>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr,
+    project_body<T, NQ, GA>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr, nullptr,
                             vblk_of(launch_index(swz), P.n_chunks, P.n_groups));
 }
 
@@ -510,13 +514,15 @@ __global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, co
     const Geo G = d.G;
     const ProjTables P = d.P;
     const VBlk vb = vblk_of(m.local, P.n_chunks, P.n_groups);
-    // one body instance: pick the phase's vectors first
-    const bool q = phase == kPjQ;
-    const T *img = q ? d.p : (phase == kPjResX ? d.x : d.xh);
+    // one body instance: pick the phase's vectors first (kPjU: u = A g'
+    // into rt with the partials of u^T q)
+    const bool q = phase == kPjQ, u = phase == kPjU;
+    const T *img = q ? d.p : (u ? d.g : (phase == kPjResX ? d.x : d.xh));
     const T *imgt = q ? d.pt : d.xs;
-    const T *y = q ? nullptr : d.y;
-    T *out = q ? d.q : d.r;
-    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, d.partials, vb);
+    const T *y = (q || u) ? nullptr : d.y;
+    T *out = q ? d.q : (u ? d.rt : d.r);
+    const T *dv = u ? d.q : nullptr;
+    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, dv, d.partials, vb);
 }
 
 template <typename T>
@@ -580,8 +586,8 @@ constexpr int kBpPrm = 8;   // per-angle parameters staged in LDS
 template <typename T, bool DUAL, int NS>
 __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ r2, const Geo &G,
                                  const BpAngle *__restrict__ ang, T *__restrict__ out,
-                                 T *__restrict__ out2, const T *__restrict__ dotv, int dot,
-                                 double *partials, VBlk vb)
+                                 T *__restrict__ out2, T *__restrict__ outT,
+                                 const T *__restrict__ dotv, int dot, double *partials, VBlk vb)
 {
     constexpr int NW = DUAL ? 2 : 1;
     constexpr int NE = kBpChunk * kBpWin / kBpThreads;   // staged bins per thread and sinogram
@@ -726,16 +732,19 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         const size_t p = (size_t)i * G.n + j;
         auto *og = gl(out);
         auto *og2 = gl(out2);
+        auto *ogt = gl(outT);
         const auto *dg = gl(dotv);
         if (j < G.n) {
             og[p] = acc0;
             if (DUAL) og2[p] = bcc0;
+            if (outT != nullptr) ogt[(size_t)j * G.n + i] = acc0;
             if (dot == 1) dsum += (double)(DUAL ? bcc0 : acc0) * (double)dg[p];
             else if (dot == 2) dsum += (double)acc0 * (double)acc0;
         }
         if (j + 1 < G.n) {
             og[p + 1] = acc1;
             if (DUAL) og2[p + 1] = bcc1;
+            if (outT != nullptr) ogt[(size_t)(j + 1) * G.n + i] = acc1;
             if (dot == 1) dsum += (double)(DUAL ? bcc1 : acc1) * (double)dg[p + 1];
             else if (dot == 2) dsum += (double)acc1 * (double)acc1;
         }
@@ -751,8 +760,8 @@ __global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__rest
                                                                   T *__restrict__ out, int swz)
 {
     const int nt = (G.n + kBpTile - 1) / kBpTile;
-    backproject_body<T, false, NS>(r, nullptr, G, ang, out, nullptr, nullptr, 0, nullptr,
-                                   vblk_of(launch_index(swz), nt, nt));
+    backproject_body<T, false, NS>(r, nullptr, G, ang, out, nullptr, nullptr, nullptr, 0,
+                                   nullptr, vblk_of(launch_index(swz), nt, nt));
 }
 
 template <typename T>
@@ -786,11 +795,13 @@ __global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T>
     const int nt = (G.n + kBpTile - 1) / kBpTile;
     const VBlk vb = vblk_of(m.local, nt, nt);
     // one body instance: kBpH is h = A^T q (no second sinogram, no dot);
-    // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g'
+    // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g';
+    // kBpGT is g' with its transpose in xs
     const bool hq = phase == kBpH;
     const T *src = hq ? d.q : d.r;
     T *dst = hq ? d.h : d.g;
-    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, d.h, hq ? 0 : dot,
+    T *dstT = phase == kBpGT ? d.xs : nullptr;
+    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, dstT, d.h, hq ? 0 : dot,
                                   hq ? nullptr : d.partials, vb);
 }
 
@@ -1190,10 +1201,12 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
         }
         tile[r][tx] = pn;
     }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int j = bx + r, i = by + tx;
-        if (i < n && j < n) pt[(size_t)j * n + i] = tile[tx][r];
+    if (pt_ != nullptr) {   // uniform: the transposed copy for A p
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int j = bx + r, i = by + tx;
+            if (i < n && j < n) pt[(size_t)j * n + i] = tile[tx][r];
+        }
     }
     double v[1] = {acc};
     block_store(v, partials + vb.id());
@@ -1216,6 +1229,50 @@ void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int ru
                        hipStream_t s)
 {
     hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init);
+}
+
+// S-CG with three operators: q' = -u + beta q over sinogram row a (u = A g'
+// in rt), and the block's partial of ||q'||^2.
+template <typename T>
+__device__ void q_update_body(const T *__restrict__ u_, T *__restrict__ q_, const Geo &G,
+                              const DevState *st_, double *partial, int a)
+{
+    const auto *u = gl(u_);
+    auto *q = gl(q_);
+    const T bt = (T)beta_of(gl(st_), 0, 0);
+    const size_t row = (size_t)a * G.rs + kSinoPadL;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G.nb; b += blockDim.x) {
+        const T qn = fma(bt, q[row + b], -u[row + b]);
+        q[row + b] = qn;
+        acc += (double)qn * (double)qn;
+    }
+    double v[1] = {acc};
+    block_store(v, partial);
+}
+
+// Blocks [0, nb_t32): p' = -g' + beta p (no transposed copy: p' is not
+// projected); blocks [nb_t32, nb_t32 + nb_sv): q'. The partials land at the
+// block's own index.
+template <typename T>
+__global__ __launch_bounds__(256) void kb_pq_update(const Solve<T> *S, const BlkMap *map)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> d = load_solve(S, m.solve);
+    if (stopped(d.st)) return;
+    if (m.local < d.nb_t32) {
+        const int nt = (d.G.n + 31) / 32;
+        p_update_body(d.g, d.z, d.p, (T *)nullptr, d.G, d.partials, d.st, 0, 0,
+                      vblk_of(m.local, nt, nt));
+    } else {
+        q_update_body(d.rt, d.q, d.G, d.st, d.partials + m.local, m.local - d.nb_t32);
+    }
+}
+
+template <typename T>
+void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_pq_update<T>, dim3(nblocks), dim3(256), 0, s, S, map);
 }
 
 // Plain CG (Alg. CG, CG-STEP): x' = x + alpha p and the recursive gradient
@@ -1402,6 +1459,32 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
         if (!arg1)
             if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
+        return;
+    }
+    case kFinDotUQ: {
+        final_sums(d.partials, d.nb_pj, 1, 1, tot);
+        if (threadIdx.x != 0) return;   // the block's other threads are done
+        st->gh = tot[0];                // (A g')^T (A p) = g'^T h
+        return;
+    }
+    case kFinPQ: {
+        // the launch stored g'^T p' at [0, nb_t32) and ||q'||^2 after it
+        final_sums(d.partials, d.nb_t32, 1, 1, tot);
+        final_sums(d.partials + d.nb_t32, d.nb_sv, 1, 1, tot + 1);
+        if (threadIdx.x != 0) return;   // the block's other threads are done
+        const double beta = beta_of(st, 0, 0);
+        st->beta = beta;
+        st->gp = tot[0];
+        st->qq = tot[1];
+        if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
+        if (!isfinite(beta) || !isfinite(tot[0]) || !isfinite(tot[1])) {
+            set_done(st, SCG_ENAN);
+        } else if (tot[1] == 0.0) {
+            set_done(st, SCG_EBREAKDOWN);
+        } else {
+            st->alpha = -tot[0] / tot[1];
+            if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
+        }
         return;
     }
     case kFinXUpdateCG: {
@@ -1618,6 +1701,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int,        \
                                        hipStream_t);                                            \
     template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
+    template void launch_b_pq_update<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);   \
     template void launch_b_filter<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
     template void launch_b_copy_out<T>(const Solve<T> *, const BlkMap *, int, int,             \
                                        hipStream_t);                                            \

@@ -119,7 +119,7 @@ template <typename T> struct Solve {
     const T *y;                 // data, n_angles x n_bins
     T *x, *xh, *p, *g, *h, *s, *z;
     T *r, *q, *rt;              // padded sinograms (row stride G.rs)
-    T *xs, *pt;                 // transposes of x_{k+1/2} (or x) and of p
+    T *xs, *pt;                 // transposes of x_{k+1/2} (x, or g') and of p
     T *xout;                    // caller's output image
     double *partials;           // block partial sums of the last reduction
     double *gtab;               // gamma0 a^(l+m), m < max_trials
@@ -127,7 +127,7 @@ template <typename T> struct Solve {
     DevState *st;
     scg_trace_entry *trace;
     const int32_t *forced;      // replayed decisions or null
-    int nb_xtv, nb_trA, nb_trB, nb_t32, nb_pj, nb_bp, nb_vec;
+    int nb_xtv, nb_trA, nb_trB, nb_t32, nb_pj, nb_bp, nb_vec, nb_sv;
     int trB_chunks;             // trial chunks of the second trial launch
 };
 
@@ -146,6 +146,8 @@ enum Phase : int {
     kBpH = 5,         // h = A^T q
     kStageXh = 6,     // xs = x_{k+1/2}^T
     kStageX = 7,      // xs = x^T
+    kPjU = 8,         // u = A g' into rt, partials of u^T q (S-CG, three operators)
+    kBpGT = 9,        // g = A^T r and xs = g^T (S-CG, three operators)
 };
 
 // Finishers: one block per solve sums the partials of the previous launch
@@ -163,6 +165,8 @@ enum Fin : int {
     kFinXUpdateCG = 9,     // CG: ||g||^2 and the step count
     kFinCGCap = 10,        // CG: iteration cap at the loop top
     kFinTV = 11,           // TV of the output
+    kFinDotUQ = 12,        // (A g')^T q (S-CG, three operators)
+    kFinPQ = 13,           // beta, g^T p, ||q||^2 and alpha of the p and q updates
 };
 
 // Block counts of the solver kernels for one solve.
@@ -171,6 +175,7 @@ int blocks_t32(const Geo &G);
 int blocks_vec(size_t n);
 int blocks_trials(const Geo &G, int nchunks);
 int blocks_bp(const Geo &G);
+int blocks_sv(const Geo &G);   // sinogram vector kernels
 
 // ---- launchers (kernels.hip) -------------------------------------------
 template <typename T> void launch_fill(T *p, size_t n, T v, hipStream_t s);
@@ -215,6 +220,10 @@ void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int ru
                        hipStream_t s);
 template <typename T>
 void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+// p' = -g' + beta p (blocks [0, nb_t32)) and q' = -u + beta q (the next
+// nb_sv blocks) in one launch, with the partials of g'^T p' and ||q'||^2
+template <typename T>
+void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 template <typename T>
 void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
                      hipStream_t s);

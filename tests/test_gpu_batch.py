@@ -32,7 +32,7 @@ def torch_mod():
 # launch shapes per case (project_groups, backproject_split, project_angles,
 # swizzle): solves with different shapes run in different groups of a batch
 SHAPES = [(4, 4, 8, 0), (4, 2, 8, 0), (2, 1, 4, 1), (4, 4, 8, 0), (4, 4, 4, 1), (4, 4, 8, 1),
-          (2, 2, 8, 0), (4, 4, 4, 0)]
+          (2, 2, 8, 0), (4, 4, 4, 0), (4, 2, 8, 1)]
 
 # (n, n_angles, n_bins, variant, precision, seed)
 CASES = [
@@ -44,6 +44,7 @@ CASES = [
     (64, 90, 95, "S_CG", "f32", 6),
     (24, 30, 37, "S_PCG", "f64", 7),
     (40, 60, 61, "S_CG_K", "f32", 8),
+    (44, 60, 67, "S_CG_3OP", "f32", 9),
 ]
 
 

@@ -65,12 +65,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg,
+ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg, "S_CG_3OP": alg.scg_3op,
              "S_CG_K": lambda prob, x0, eps, pp, max_iter: alg.scg_k(prob, x0, eps, pp, K=2,
                                                                      max_iter=max_iter)}
 
 
-@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_K"])
+@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_K", "S_CG_3OP"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
@@ -91,7 +91,7 @@ def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
     assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
 
 
-@pytest.mark.parametrize("variant", ["S_CG", "S_PCG"])
+@pytest.mark.parametrize("variant", ["S_CG", "S_PCG", "S_CG_3OP"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod

@@ -157,7 +157,7 @@ def test_scg_q_recurrence_equals_scg(oracle_lib):
         x1 = alg.cg(prob, np.zeros(g.J), eps=0.0, max_iter=1).x
         pp = alg.PerturbParams(gamma0=0.05 * float(np.linalg.norm(x1)))
         a = alg.scg(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, max_iter=500)
-        b = alg.scg_qrec(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, max_iter=500)
+        b = alg.scg_3op(prob, np.zeros(g.J), eps=1.1 * eps0, pp=pp, max_iter=500)
         assert a.status == b.status == "ok" and a.k == b.k
         assert [(t["trials"], t["accepted"]) for t in a.trace] == \
             [(t["trials"], t["accepted"]) for t in b.trace]
