@@ -209,6 +209,36 @@ def three_operator_run(plan, y, params, out_scg, ws, stream, w, steps):
                                         / np.linalg.norm(w.x_true))}
 
 
+def counter_workload(shapes):
+    """Workload of the FETCH_SIZE / WRITE_SIZE counter runs: two 512x512
+    S-CG solves with fixed launch shapes, then three plain device copies of
+    64 MiB whose counter readings calibrate the counters' units."""
+    import torch
+    from paper_1709_04912_amd import scg
+    from synth import make_workload
+    w = make_workload(3, 0)
+    dev = torch.device("cuda:0")
+    plan = scg.Plan(N, N_ANGLES, N_BINS, device=0)
+    plan.set_tuning(scg.SCG_F32, *shapes)
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device=dev)
+    xt = torch.tensor(w.x_true.reshape(-1), dtype=torch.float32, device=dev)
+    res = plan.project(xt).double() - y.double()
+    eps = 0.5 * float((res * res).sum())
+    p1 = plan.params(eps=1e-30, gamma0=0.0, variant="CG", max_iter=1)
+    x1, _, _ = plan.solve(y, p1, trace=False)
+    gamma0 = RHO * float(torch.linalg.vector_norm(x1.double()))
+    p = plan.params(eps=eps, gamma0=gamma0, variant="S_CG", prec=scg.SCG_F32, max_iter=2000)
+    for _ in range(2):
+        _, rep, _ = plan.solve(y, p, trace=False)
+    a = torch.ones(16 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"counter workload done: shapes={shapes} k={rep.k} status={rep.status}")
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,11 +247,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--counter-workload", metavar="SHAPES",
+                    help="run only the hardware-counter workload with these launch shapes "
+                         "(project_groups,backproject_split,project_angles,swizzle)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
               "(one solve runs on one device)", file=sys.stderr)
         sys.exit(2)
+    if args.counter_workload:
+        counter_workload([int(v) for v in args.counter_workload.split(",")])
+        return
 
     import numpy as np
     import torch
