@@ -128,9 +128,24 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
             }
         }
         if (!ok) continue;
+        // Blocks differ in work by the bands they skip; dispatching the
+        // heaviest first lets the light ones fill the tail of the launch.
+        const int nblk = (int)groups.size() * n_chunks;
+        std::vector<int> bands(nblk, 0), order(nblk);
+        for (int id = 0; id < nblk; ++id) {
+            for (int band = 0; band < n_bands; ++band)
+                bands[id] += win[(size_t)id * n_bands + band] != scg::kWinSkip;
+            order[id] = id;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return bands[a] > bands[b]; });
         if (hipMalloc(&p->pgroups[ti], groups.size() * sizeof(PjGroup)) != hipSuccess ||
-            hipMalloc(&p->pwin[ti], win.size() * sizeof(int)) != hipSuccess)
+            hipMalloc(&p->pwin[ti], win.size() * sizeof(int)) != hipSuccess ||
+            hipMalloc(&p->porder[ti], order.size() * sizeof(int)) != hipSuccess)
             return SCG_ENOMEM;
+        if (hipMemcpy(p->porder[ti], order.data(), order.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return SCG_EDEVICE;
         if (hipMemcpy(p->pgroups[ti], groups.data(), groups.size() * sizeof(PjGroup),
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(p->pwin[ti], win.data(), win.size() * sizeof(int), hipMemcpyHostToDevice) !=
@@ -140,6 +155,7 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
         t.ang = p->pang;
         t.groups = p->pgroups[ti];
         t.win = p->pwin[ti];
+        t.order = p->porder[ti];
         t.n_groups = (int)groups.size();
         t.n_chunks = n_chunks;
         t.n_bands = n_bands;
@@ -467,6 +483,7 @@ void scg_plan_destroy(scg_plan *p)
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->pgroups[i]);
         (void)hipFree(p->pwin[i]);
+        (void)hipFree(p->porder[i]);
     }
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->xs[i]);

@@ -32,6 +32,53 @@ template <typename P> __device__ __forceinline__ auto gl(P *p)
 constexpr int kBlock = 256;
 constexpr int kMaxVecBlocks = 512;
 
+// Raw buffer views. A load through the buffer unit whose per-lane byte
+// offset is at or past the view's size returns zero without touching memory;
+// kernels use that for the zero padding around an image and pass kBufOob as
+// the offset of an element that lies outside it. The per-lane offset alone
+// is range-checked, so a uniform (scalar) offset is only added where every
+// element it reaches exists.
+#if defined(__HIP_DEVICE_COMPILE__)
+using Rsrc = __amdgpu_buffer_rsrc_t;
+#else
+struct Rsrc {
+    int w[4];
+};
+#endif
+constexpr uint32_t kBufOob = 0x80000000u;
+
+__device__ __forceinline__ Rsrc buf_rsrc(const void *p, uint32_t bytes)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    // word 3: raw (unswizzled) dword-addressed buffer on gfx9-family parts
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+#else
+    return Rsrc{};
+#endif
+}
+
+template <typename T> __device__ __forceinline__ T buf_load(Rsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float buf_load<float>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+#else
+    return 0.0f;
+#endif
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+#else
+    return 0.0;
+#endif
+}
+
 __device__ __forceinline__ float sat(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
 __device__ __forceinline__ double sat(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
@@ -343,6 +390,13 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // (same layout as out).
 // ---------------------------------------------------------------------------
 
+// Block id of the projector's local block index: heaviest first in launch
+// order (the XCD-contiguous order keeps neighbouring blocks together instead).
+__device__ __forceinline__ int pj_block(const ProjTables &P, int local, int swz)
+{
+    return (swz || P.order == nullptr) ? local : gl(P.order)[local];
+}
+
 template <typename T, int NQ, int GA>
 __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, const Geo &G,
                              const ProjTables &P, const T *__restrict__ y, int y_stride,
@@ -365,7 +419,8 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     const bool bin_ok = b_raw < G.nb;
     const int b = bin_ok ? b_raw : G.nb - 1;   // idle lanes trace the chunk's last ray
     const int n = G.n;
-    const auto *img = gl(grp.major ? xt : x);
+    const Rsrc img = buf_rsrc(grp.major ? xt : x, (uint32_t)((size_t)n * n * sizeof(T)));
+    const uint32_t rowb = (uint32_t)n * (uint32_t)sizeof(T);   // bytes per image row
     const auto *win = gl(P.win) + ((size_t)gi * P.n_chunks + chunk) * P.n_bands;
     const int scol = t % kPjWin, srow = (t / kPjWin) * RPT;
 
@@ -383,18 +438,22 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         }
     }
 
+    // staging loads: one per row, columns outside the image read as zero
     T pre[RPT];
     auto prefetch = [&](int band) {
         const int jw = win[band];
         const int i0 = band * kPjBand + srow;
         const int col = jw + scol;
         const bool cok = col >= 0 && col < n;
-        const auto *src = img + (size_t)i0 * n + (cok ? col : 0);
+        const uint32_t vo = cok ? (uint32_t)(i0 * n + col) * (uint32_t)sizeof(T) : kBufOob;
+        if ((band + 1) * kPjBand <= n) {
+            // every row of the band exists: the row step is a scalar offset
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            T v = T(0);
-            if (i0 + r < n) v = src[(size_t)r * n];
-            pre[r] = cok ? v : T(0);
+            for (int r = 0; r < RPT; ++r) pre[r] = buf_load<T>(img, vo, (uint32_t)r * rowb);
+        } else {
+            // last band of a ragged image: rows past the end read as zero
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) pre[r] = buf_load<T>(img, vo + (uint32_t)r * rowb, 0u);
         }
     };
 
@@ -425,7 +484,9 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 const bool miss = fmax(us, ue) < -1.0 || fmin(us, ue) > (double)n;
                 if (__all(miss)) continue;
                 const double fu = floor(us);
-                const T *col0 = lds + ((int)fu - jw) * LS;
+                // byte offset in LDS of the ray's first column; a step's
+                // column adds a 24-bit multiple of the column stride
+                const int cb = ((int)fu - jw) * (LS * (int)sizeof(T));
                 const T F0 = (T)(us - fu);
                 const T slope = (T)A.slope;
                 const T K = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
@@ -439,7 +500,9 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                     const T v = fma((T)k, slope, F0);
                     const int jl = flr(v);
                     const T wl = sat(fma(frc(v), -K, C));
-                    const T *col = col0 + jl * LS;
+                    const T *col = reinterpret_cast<const T *>(
+                        reinterpret_cast<const char *>(lds) +
+                        __mul24(jl, LS * (int)sizeof(T)) + cb);
                     const T xl = col[k], xr = col[LS + k];
                     a_ = fma(wl, xl - xr, a_);
                     ar += xr;
@@ -478,7 +541,7 @@ __global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ 
                                                           int out_stride, int out_off, int swz)
 {
     project_body<T, NQ, GA>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr, nullptr,
-                            vblk_of(launch_index(swz), P.n_chunks, P.n_groups));
+                            vblk_of(pj_block(P, launch_index(swz), swz), P.n_chunks, P.n_groups));
 }
 
 template <typename T>
@@ -513,7 +576,7 @@ __global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, co
     // descriptor fields into registers: the body's stores cannot alias them
     const Geo G = d.G;
     const ProjTables P = d.P;
-    const VBlk vb = vblk_of(m.local, P.n_chunks, P.n_groups);
+    const VBlk vb = vblk_of(pj_block(P, m.local, swz), P.n_chunks, P.n_groups);
     // one body instance: pick the phase's vectors first (kPjU: u = A g'
     // into rt with the partials of u^T q)
     const bool q = phase == kPjQ, u = phase == kPjU;
@@ -604,8 +667,46 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     T acc0 = T(0), acc1 = T(0), bcc0 = T(0), bcc1 = T(0);
     const int nchunks = (G.na + kBpChunk - 1) / kBpChunk;
 
+    // Window of each angle of a chunk: first bin and 1/m, from the FP64
+    // frame computed once per angle by the params step.
+    struct WinRef {
+        int base;
+        T m;
+    };
+    __shared__ WinRef wref[NS][kBpChunk];
+    const Rsrc sino = buf_rsrc(r, (uint32_t)((size_t)G.na * G.rs * sizeof(T)));
+    const Rsrc sino2 = buf_rsrc(DUAL ? r2 : r, (uint32_t)((size_t)G.na * G.rs * sizeof(T)));
+
     T pre[NW][NE];
     T ppr[kBpPrm];
+    // FP64 frame of the chunk's angles (threads t < kBpChunk, one angle
+    // each): the per-pixel parameters (kept in registers until the chunk is
+    // staged) and the window reference the staging loads read.
+    auto params = [&](int ch) {
+        if (t < kBpChunk) {
+            const int a = ch * kBpChunk + t;
+#pragma unroll
+            for (int k = 0; k < kBpPrm; ++k) ppr[k] = T(0);
+            WinRef w{0, T(0)};
+            if (a < G.na) {
+                const BpAngle A = gl(ang)[a];
+                const BpW<T> W = bpw<T>(A);
+                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
+                const double fb = floor(pc) - kBpHalf;
+                ppr[0] = W.c;
+                ppr[1] = W.s;
+                ppr[2] = W.K;
+                ppr[3] = W.C;
+                ppr[4] = W.CK;
+                ppr[5] = (T)(pc - fb);
+                w.base = (int)fb;
+                w.m = (T)A.inv_m;
+            }
+            wref[gs][t] = w;
+        }
+    };
+    // staging loads of a chunk (after a barrier that follows its params):
+    // bins outside the detector and angles past the last read as zero
     auto prefetch = [&](int ch) {
         const int a0 = ch * kBpChunk;
 #pragma unroll
@@ -613,39 +714,18 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             const int q = t + e * kBpThreads;
             const int al = q / kBpWin, k = q % kBpWin;
             const int a = a0 + al;
-            T v = T(0), v2 = T(0);
-            if (a < G.na) {
-                const auto &A = gl(ang)[a];
-                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
-                const int bb = (int)floor(pc) - kBpHalf + k;
-                if (bb >= 0 && bb < G.nb) {
-                    const T m = (T)A.inv_m;
-                    const size_t off = (size_t)a * G.rs + kSinoPadL + bb;
-                    v = gl(r)[off] * m;
-                    if (DUAL) v2 = gl(r2)[off] * m;
-                }
-            }
-            pre[0][e] = v;
-            if (DUAL) pre[NW - 1][e] = v2;
-        }
-        if (t < kBpChunk) {
-            const int a = a0 + t;
-#pragma unroll
-            for (int k = 0; k < kBpPrm; ++k) ppr[k] = T(0);
-            if (a < G.na) {
-                const BpAngle A = gl(ang)[a];
-                const BpW<T> W = bpw<T>(A);
-                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
-                ppr[0] = W.c;
-                ppr[1] = W.s;
-                ppr[2] = W.K;
-                ppr[3] = W.C;
-                ppr[4] = W.CK;
-                ppr[5] = (T)(pc - (floor(pc) - kBpHalf));
-            }
+            const WinRef w = wref[gs][al];
+            const int bb = w.base + k;
+            const bool ok = a < G.na && (unsigned)bb < (unsigned)G.nb;
+            const uint32_t vo =
+                ok ? (uint32_t)(a * G.rs + kSinoPadL + bb) * (uint32_t)sizeof(T) : kBufOob;
+            pre[0][e] = buf_load<T>(sino, vo, 0u) * w.m;
+            if (DUAL) pre[NW - 1][e] = buf_load<T>(sino2, vo, 0u) * w.m;
         }
     };
 
+    if (gs < nchunks) params(gs);
+    __syncthreads();
     if (gs < nchunks) prefetch(gs);
     for (int c0 = 0; c0 < nchunks; c0 += NS) {
         const int ch = c0 + gs;
@@ -662,6 +742,9 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
                 for (int k = 0; k < kBpPrm; ++k) prm[gs][t * kBpPrm + k] = ppr[k];
             }
         }
+        // the previous chunk's window references were read before the
+        // barrier above
+        if (ch + NS < nchunks) params(ch + NS);
         __syncthreads();
         if (ch + NS < nchunks) prefetch(ch + NS);
         const int na = live ? min(kBpChunk, G.na - ch * kBpChunk) : 0;

@@ -22,6 +22,7 @@ struct scg_plan {
     BpAngle *bang = nullptr;
     PjGroup *pgroups[2] = {nullptr, nullptr};
     int *pwin[2] = {nullptr, nullptr};
+    int *porder[2] = {nullptr, nullptr};
     ProjTables ptab[2] = {};              // projector tables, 8 and 4 angles per group
     void *xs[2] = {nullptr, nullptr};     // transposed-image scratch per precision
     void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision

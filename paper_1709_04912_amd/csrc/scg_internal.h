@@ -73,6 +73,8 @@ struct ProjTables {
     const ProjAngle *ang;
     const PjGroup *groups;
     const int *win;      // [group][chunk][band] window start column or kWinSkip
+    const int *order;    // dispatch order: block ids (group * n_chunks + chunk) by
+                         // decreasing count of bands to walk (heaviest first)
     int n_groups, n_chunks, n_bands, group_max;
 };
 
