@@ -146,10 +146,22 @@ __device__ void final_sums(const double *partials, int nblk, int stride, int nv,
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
+    constexpr int U = 8;   // loads in flight per lane
     for (int k = wid; k < nv; k += nw) {
         double acc = 0.0;
         const auto *pg = gl(partials);
-        for (int b = lane; b < nblk; b += 64) acc += pg[(size_t)b * stride + k];
+        for (int b0 = lane; b0 < nblk; b0 += 64 * U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = b0 + 64 * u;
+                v[u] = b < nblk ? pg[(size_t)b * stride + k] : 0.0;
+            }
+            // the lane's running sum in block order, as one load at a time
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b0 + 64 * u < nblk) acc += v[u];
+        }
         acc = wave_sum(acc);
         if (lane == 0) tot[k] = acc;
     }
