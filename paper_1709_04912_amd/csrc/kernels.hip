@@ -47,6 +47,9 @@ struct Rsrc {
 #endif
 constexpr uint32_t kBufOob = 0x80000000u;
 
+// Projector steps whose LDS reads are in flight together.
+constexpr int kPjGroupSteps = 8;
+
 __device__ __forceinline__ Rsrc buf_rsrc(const void *p, uint32_t bytes)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -81,15 +84,6 @@ __device__ __forceinline__ double buf_load<double>(Rsrc r, uint32_t voff, uint32
 
 __device__ __forceinline__ float sat(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
 __device__ __forceinline__ double sat(double v) { return fmin(fmax(v, 0.0), 1.0); }
-
-// floor() converted to int in one instruction (float); two for double.
-__device__ __forceinline__ int flr(float v)
-{
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-    return r;
-}
-__device__ __forceinline__ int flr(double v) { return (int)floor(v); }
 
 __device__ __forceinline__ float frc(float v) { return __builtin_amdgcn_fractf(v); }
 __device__ __forceinline__ double frc(double v) { return v - floor(v); }
@@ -396,7 +390,7 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // current one is consumed. Within a band a ray's crossing coordinate is an integer anchor
 // plus an FP32 fraction (the anchor from FP64), so the split weights stay
 // accurate near the axes where the chord ramp is steep. Per step: the
-// crossing, its floor and fraction, one clamped FMA for the split weight, two
+// crossing, its integer part and fraction, one clamped FMA for the split weight, two
 // LDS reads and three FMAs/adds. With y given, out = A x - y. With partials
 // given, the block stores its sum of out^2, or of out * dotv with dotv given
 // (same layout as out).
@@ -495,9 +489,12 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 const double ue = fma((double)(kPjBand - 1), A.slope, us);
                 const bool miss = fmax(us, ue) < -1.0 || fmin(us, ue) > (double)n;
                 if (__all(miss)) continue;
-                const double fu = floor(us);
-                // byte offset in LDS of the ray's first column; a step's
-                // column adds a 24-bit multiple of the column stride
+                // anchor one column left of the ray's leftmost crossing in the
+                // band: every step's offset from it is at least 1, so the
+                // column is the truncation of the offset
+                const double fu = floor(fmin(us, ue)) - 1.0;
+                // byte offset in LDS of the anchor column; a step's column
+                // adds a 24-bit multiple of the column stride
                 const int cb = ((int)fu - jw) * (LS * (int)sizeof(T));
                 const T F0 = (T)(us - fu);
                 const T slope = (T)A.slope;
@@ -507,17 +504,28 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 // ray's sum: rounding grows with the band plus the band count,
                 // not with N
                 T a_ = T(0), ar = T(0);
+                // steps in groups of kPjGroupSteps: the group's LDS reads are
+                // issued before its terms are summed (in step order)
 #pragma unroll
-                for (int k = 0; k < kPjBand; ++k) {
-                    const T v = fma((T)k, slope, F0);
-                    const int jl = flr(v);
-                    const T wl = sat(fma(frc(v), -K, C));
-                    const T *col = reinterpret_cast<const T *>(
-                        reinterpret_cast<const char *>(lds) +
-                        __mul24(jl, LS * (int)sizeof(T)) + cb);
-                    const T xl = col[k], xr = col[LS + k];
-                    a_ = fma(wl, xl - xr, a_);
-                    ar += xr;
+                for (int k0 = 0; k0 < kPjBand; k0 += kPjGroupSteps) {
+                    T xl[kPjGroupSteps], xr[kPjGroupSteps], wl[kPjGroupSteps];
+#pragma unroll
+                    for (int j = 0; j < kPjGroupSteps; ++j) {
+                        const int k = k0 + j;
+                        const T v = fma((T)k, slope, F0);
+                        const int jl = (int)v;
+                        wl[j] = sat(fma(frc(v), -K, C));
+                        const T *col = reinterpret_cast<const T *>(
+                            reinterpret_cast<const char *>(lds) +
+                            __mul24(jl, LS * (int)sizeof(T)) + cb);
+                        xl[j] = col[k];
+                        xr[j] = col[LS + k];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kPjGroupSteps; ++j) {
+                        a_ = fma(wl[j], xl[j] - xr[j], a_);
+                        ar += xr[j];
+                    }
                 }
                 acc[m] += a_;
                 accr[m] += ar;
