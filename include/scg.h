@@ -66,12 +66,18 @@ typedef enum {
     SCG_S_PCG = 3,   /* Alg. S-PCG with PCG-PR-STEP (filtered preconditioner)  */
     SCG_S_CG_K = 4,  /* Alg. S-CG-K: perturbed(x_k), then CG-K (K = restart_k  */
                      /* CG-STEPs) restarted from the perturbed point           */
-    SCG_S_CG_3OP = 5 /* Alg. S-CG with CG-PR-STEP evaluated with q = A p kept  */
+    SCG_S_CG_3OP = 5,/* Alg. S-CG with CG-PR-STEP evaluated with q = A p kept  */
                      /* by linearity: beta = (A g')^T q / ||q||^2 and          */
                      /* q' = -A g' + beta q, so a step applies A twice and A^T */
                      /* once (h = A^T A p is never formed). The same iterates  */
                      /* as SCG_S_CG in exact arithmetic; q accumulates the     */
                      /* rounding of its recursion (Sec. 3 (CG-PR-STEP))        */
+    SCG_PCG = 6,     /* Alg. PCG with PCG-STEP (unsuperiorized): z = M g is   */
+                     /* the filtered backprojection of the residual, which is */
+                     /* carried recursively with g; f is evaluated at every x  */
+    SCG_S_PCG_K = 7  /* Alg. S-PCG-K: perturbed(x_k), then PCG-K (K =         */
+                     /* restart_k PCG-STEPs) restarted from the perturbed      */
+                     /* point                                                  */
 } scg_variant;
 
 /* flags of scg_params.flags */
@@ -95,7 +101,8 @@ typedef struct {
     double  tv_kappa;    /* 0: exact isotropic TV; > 0: sqrt(a^2+b^2+kappa^2)     */
     double  precond_mu;  /* mu of the filter c(w) (S-PCG); <= 0 selects 2 pi / P  */
     uint32_t flags;      /* SCG_FLAG_*                                            */
-    int32_t restart_k;   /* K of SCG_S_CG_K: CG-STEPs per pass, 1..64 (default 2) */
+    int32_t restart_k;   /* K of SCG_S_CG_K / SCG_S_PCG_K: steps per pass, 1..64   */
+                         /* (default 2)                                        */
 } scg_params;
 
 typedef struct {

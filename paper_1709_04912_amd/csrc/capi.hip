@@ -263,8 +263,10 @@ void prof_drain(scg_plan *p, int last_iter)
 int check_params(const scg_params *pr)
 {
     if (pr == nullptr) return SCG_EINVAL;
-    if (pr->variant < SCG_CG || pr->variant > SCG_S_CG_3OP) return SCG_EINVAL;
-    if (pr->variant == SCG_S_CG_K && (pr->restart_k < 1 || pr->restart_k > 64)) return SCG_EINVAL;
+    if (pr->variant < SCG_CG || pr->variant > SCG_S_PCG_K) return SCG_EINVAL;
+    if ((pr->variant == SCG_S_CG_K || pr->variant == SCG_S_PCG_K) &&
+        (pr->restart_k < 1 || pr->restart_k > 64))
+        return SCG_EINVAL;
     if (pr->prec != SCG_F32 && pr->prec != SCG_F64) return SCG_EINVAL;
     if (!(pr->eps > 0.0) || !std::isfinite(pr->eps)) return SCG_EINVAL;
     if (!(pr->gamma0 >= 0.0) || !std::isfinite(pr->gamma0)) return SCG_EINVAL;

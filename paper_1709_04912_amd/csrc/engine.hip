@@ -70,7 +70,7 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
 }
 
 // Block kinds of the phase launches.
-enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKPQ, kKinds };
+enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKPQ, kKXR, kKinds };
 
 template <typename T> int count_of(const Solve<T> &d, int kind)
 {
@@ -84,6 +84,7 @@ template <typename T> int count_of(const Solve<T> &d, int kind)
     case kKVec: return d.nb_vec;
     case kKFilt: return d.G.na;
     case kKPQ: return d.nb_t32 + d.nb_sv;
+    case kKXR: return d.nb_vec + d.nb_sv;
     default: return 0;
     }
 }
@@ -164,7 +165,37 @@ template <typename T> struct Enq {
         Prof t(g.prof, SCG_KC_FILTER, s);
         launch_b_filter<T>(g.S, m(kKFilt), n(kKFilt), g.max_nb, s);
     }
+    // PCG-STEP after alpha: h = A^T q, x, g and r updated; then (unless the
+    // step ends a PCG-K pass) z' = A^T F r', delta' = g'^T z', p' = -z' + beta p
+    void pcg_step(int in_pass, bool last) const
+    {
+        backproject(kBpH, 0);
+        {
+            Prof t(g.prof, SCG_KC_VECTOR, s);
+            launch_b_x_update_pcg<T>(g.S, m(kKXR), n(kKXR), s);
+        }
+        if (last) return;
+        filter();
+        backproject(kBpZ, 1);
+        finish(kFinDeltaPCG, in_pass);
+        p_update(4, 0);
+    }
+    // z0 = M g0 with g0 (from r0 in r): delta0 = g0^T z0, p0 = -z0
+    void pcg_start() const
+    {
+        filter();
+        backproject(kBpGZ, 3);
+        finish(kFinDotGG);
+        p_update(4, 1);
+    }
 };
+
+inline bool restarted(int variant) { return variant == SCG_S_CG_K || variant == SCG_S_PCG_K; }
+inline bool unsuperiorized(int variant) { return variant == SCG_CG || variant == SCG_PCG; }
+inline bool filtered(int variant)
+{
+    return variant == SCG_S_PCG || variant == SCG_PCG || variant == SCG_S_PCG_K;
+}
 
 // Initial step. S- variants (steps 1-6 of the algorithms): x_{1/2} = x0, g0
 // (and z0), p0, h0 and alpha; x1 = x0 + alpha p0 and k = 1 are formed by the
@@ -173,8 +204,8 @@ template <typename T> struct Enq {
 template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
 {
     const Enq<T> e{g, s};
-    if (g.variant == SCG_S_CG_K) {
-        // S-CG-K: x_{-1/2} = x_0 = x0 and the loop test f(x0) > eps
+    if (restarted(g.variant)) {
+        // S-CG-K, S-PCG-K: x_{-1/2} = x_0 = x0 and the loop test f(x0) > eps
         e.stage(kStageX);
         e.project(kPjResX);
         e.finish(kFinResidual);
@@ -187,6 +218,14 @@ template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
         e.backproject(kBpG, 2);
         e.finish(kFinDotGG);
         e.p_update(3, 1);
+        return;
+    }
+    if (g.variant == SCG_PCG) {
+        // r0 = A x0 - y, g0 = A^T r0, z0 = A^T F r0, p0 = -z0
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        e.pcg_start();
         return;
     }
     e.stage(kStageXh);
@@ -223,6 +262,17 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
         }
         e.finish(kFinXUpdateCG);
         e.p_update(3, 0);
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        return;
+    }
+    if (g.variant == SCG_PCG) {
+        // cap test, PCG-STEP (recursive g and r), then f(x) explicitly
+        e.finish(kFinCGCap);
+        e.project(kPjQ);
+        e.finish(kFinNormQCG);
+        e.pcg_step(0, false);
         e.stage(kStageX);
         e.project(kPjResX);
         e.finish(kFinResidual);
@@ -271,6 +321,17 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
         }
         return;
     }
+    if (g.variant == SCG_S_PCG_K) {
+        // PCG-K from x_{k+1/2}: r0 (formed above), g0, z0, delta0, p0, then K
+        // PCG-STEPs; the direction update after the last one is not needed
+        e.pcg_start();
+        for (int j = 0; j < g.restart_k; ++j) {
+            e.project(kPjQ);
+            e.finish(kFinNormQCG, 1);
+            e.pcg_step(1, j + 1 == g.restart_k);
+        }
+        return;
+    }
     if (g.variant == SCG_S_CG_3OP) {
         // CG-PR-STEP with q = A p carried by linearity: g' = A^T r (and its
         // transpose), u = A g' with u^T q = g'^T h, then p' and q' = -u + beta q
@@ -302,7 +363,7 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
 // Output image (x_{k+1/2} of the S- variants, x of CG) and its TV.
 template <typename T> void enqueue_final(const Group<T> &g, hipStream_t s)
 {
-    launch_b_copy_out<T>(g.S, g.map[kKVec], g.nblk[kKVec], g.variant != SCG_CG, s);
+    launch_b_copy_out<T>(g.S, g.map[kKVec], g.nblk[kKVec], !unsuperiorized(g.variant), s);
     launch_b_tv<T>(g.S, g.map[kKVec], g.nblk[kKVec], s);
     launch_finish<T>(g.S, g.ns, kFinTV, 0, 0, s);
 }
@@ -369,7 +430,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     launch_fill<T>(h.rt, S, T(0), s);
     launch_fill<T>(h.xs, G.staged_elems(), T(0), s);
 
-    const bool is_cg = pr->variant == SCG_CG;
+    const bool is_cg = unsuperiorized(pr->variant);
     DevState &hs = stage->st;
     hs = DevState{};
     hs.eps = pr->eps;
@@ -380,7 +441,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     hs.max_trials = pr->max_trials;
     hs.variant = pr->variant;
     hs.flags = (int)pr->flags;
-    const bool is_k = pr->variant == SCG_S_CG_K;
+    const bool is_k = restarted(pr->variant);
     hs.k = 0;
     // the initial step of S-CG, S-CG-CD and S-PCG is open until the first
     // loop launch closes it (and is not counted); S-CG-K has none
@@ -402,9 +463,9 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
                                hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ws + L.desc, &h, sizeof(h), hipMemcpyHostToDevice, s));
 
-    // x_{1/2} = x0 (S-CG, S-CG-CD, S-PCG) or x_0 (CG, S-CG-K).
-    // S-CG-K also starts x_{-1/2} = x0 in x_{k+1/2}'s buffer: the output when
-    // f(x0) <= eps ends the loop before the first pass.
+    // x_{1/2} = x0 (S-CG, S-CG-CD, S-PCG) or x_0 (CG, PCG, S-CG-K, S-PCG-K).
+    // S-CG-K and S-PCG-K also start x_{-1/2} = x0 in x_{k+1/2}'s buffer: the
+    // output when f(x0) <= eps ends the loop before the first pass.
     T *x_start = (is_cg || is_k) ? h.x : h.xh;
     if (x0_ != nullptr) launch_copy<T>(x_start, static_cast<const T *>(x0_), J, nullptr, s);
     else launch_fill<T>(x_start, J, T(0), s);
@@ -432,7 +493,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
                char *ws, scg_report *rep, scg_trace_entry *trace_host, int32_t trace_cap,
                const int32_t *forced_host, int32_t forced_len, hipStream_t st0)
 {
-    if (pr->variant == SCG_S_PCG) {
+    if (filtered(pr->variant)) {
         int rc = ensure_filter(plan, pr->precond_mu);
         if (rc) return rc;
     }
@@ -480,7 +541,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     HIP_TRY(hipStreamSynchronize(st0));
     prof_drain(plan, std::max(fs.steps, 0));
     plan->prof_iter = 0;
-    const bool plain_k = pr->variant == SCG_CG || pr->variant == SCG_S_CG_K;
+    const bool plain_k = unsuperiorized(pr->variant) || restarted(pr->variant);
     if (rep != nullptr) {
         std::memset(rep, 0, sizeof(*rep));
         rep->status = fs.done ? fs.status : SCG_ENOCONV;
@@ -771,7 +832,7 @@ void gather(const scg::Group<T> &g, DevState *dst, double *tv, hipStream_t s)
 void fill_report(const Slot &s, const DevState &fs, double tv, scg_report *rep)
 {
     std::memset(rep, 0, sizeof(*rep));
-    const bool plain_k = s.params.variant == SCG_CG || s.params.variant == SCG_S_CG_K;
+    const bool plain_k = scg::unsuperiorized(s.params.variant) || scg::restarted(s.params.variant);
     rep->status = fs.done ? fs.status : SCG_ENOCONV;
     rep->k = plain_k ? fs.k : std::max(fs.k, 1);
     rep->steps = std::max(fs.steps, 0);
@@ -797,7 +858,7 @@ int retire(scg_batch *b, const std::vector<int> &idx)
             for (int i : idx) {
                 const Slot &s = b->active[i];
                 if ((s.params.prec == SCG_F64 ? 1 : 0) == pi &&
-                    (s.params.variant == SCG_CG ? 1 : 0) == cg)
+                    (scg::unsuperiorized(s.params.variant) ? 1 : 0) == cg)
                     sel.push_back(i);
             }
             if (sel.empty()) continue;
@@ -855,7 +916,7 @@ template <typename T>
 int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *y,
                 const void *x0, void *x_out, Slot &slot)
 {
-    if (pr->variant == SCG_S_PCG) {
+    if (scg::filtered(pr->variant)) {
         int rc = scg::ensure_filter(plan, pr->precond_mu);
         if (rc) return rc;
     }

@@ -661,7 +661,8 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 // bins are two LDS reads and its two weights two clamped FMAs. DUAL
 // backprojects a second sinogram with the same weights (S-PCG: g' and z').
 // With partials given, the block stores its part of a dot product: dot = 1,
-// out (or out2 when DUAL) against dotv; dot = 2, out against itself.
+// out (or out2 when DUAL) against dotv; dot = 2, out against itself; dot =
+// 3 (DUAL), out against out2.
 // ---------------------------------------------------------------------------
 
 constexpr int kBpPrm = 8;   // per-angle parameters staged in LDS
@@ -843,6 +844,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             if (outT != nullptr) ogt[(size_t)j * G.n + i] = acc0;
             if (dot == 1) dsum += (double)(DUAL ? bcc0 : acc0) * (double)dg[p];
             else if (dot == 2) dsum += (double)acc0 * (double)acc0;
+            else if (dot == 3) dsum += (double)acc0 * (double)bcc0;
         }
         if (j + 1 < G.n) {
             og[p + 1] = acc1;
@@ -850,6 +852,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             if (outT != nullptr) ogt[(size_t)(j + 1) * G.n + i] = acc1;
             if (dot == 1) dsum += (double)(DUAL ? bcc1 : acc1) * (double)dg[p + 1];
             else if (dot == 2) dsum += (double)acc1 * (double)acc1;
+            else if (dot == 3) dsum += (double)acc1 * (double)bcc1;
         }
     }
     if (partials == nullptr || dot == 0) return;
@@ -899,12 +902,14 @@ __global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T>
     const VBlk vb = vblk_of(m.local, nt, nt);
     // one body instance: kBpH is h = A^T q (no second sinogram, no dot);
     // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g';
-    // kBpGT is g' with its transpose in xs
-    const bool hq = phase == kBpH;
-    const T *src = hq ? d.q : d.r;
-    T *dst = hq ? d.h : d.g;
+    // kBpGT is g' with its transpose in xs; kBpZ is z = A^T rt with the dot
+    // against g
+    const bool hq = phase == kBpH, zq = phase == kBpZ;
+    const T *src = hq ? d.q : (zq ? d.rt : d.r);
+    T *dst = hq ? d.h : (zq ? d.z : d.g);
     T *dstT = phase == kBpGT ? d.xs : nullptr;
-    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, dstT, d.h, hq ? 0 : dot,
+    const T *dv = zq ? d.g : d.h;
+    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, dstT, dv, hq ? 0 : dot,
                                   hq ? nullptr : d.partials, vb);
 }
 
@@ -1069,8 +1074,8 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
     const int i0 = vb.y * TH, j0 = vb.x * TW;
     const T al = (T)st->alpha;
     const T k2 = (T)(st->kappa * st->kappa);
-    // S-CG-K: x_{k+1} is CG-K's output, already in x
-    const bool given = st->variant == SCG_S_CG_K;
+    // S-CG-K, S-PCG-K: x_{k+1} is the pass's output, already in x
+    const bool given = st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K;
     for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
         const int ii = i0 - 1 + e / (TW + 2), jj = j0 - 1 + e % (TW + 2);
         T v = T(0);
@@ -1225,7 +1230,8 @@ __device__ void perturb_body(T *__restrict__ x_, const T *__restrict__ s_,
     const auto *st = gl(st_);
     __shared__ T tile[32][33];
     const bool move = st->accepted >= 0 && st->gamma != 0.0;
-    const bool restart = st->variant == SCG_S_CG_K;   // CG-K starts from x_{k+1/2}
+    // CG-K and PCG-K start from x_{k+1/2}
+    const bool restart = st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K;
     const T g = (T)st->gamma, inv = (T)st->inv_snorm;
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
@@ -1272,8 +1278,8 @@ template <typename S> __device__ __forceinline__ double beta_of(S *st, int rule,
     if (rule == 1) return -st->gg / st->gp_prev;
     // CG-STEP inside a CG-K pass: a zero gradient (an exact minimiser) ends
     // the pass's progress instead of a 0/0
-    if (st->variant == SCG_S_CG_K && st->delta == 0.0) return 0.0;
-    return st->gg / st->delta;
+    if ((st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K) && st->delta == 0.0) return 0.0;
+    return st->gg / st->delta;   // rule 3 (CG-STEP), rule 4 (PCG-STEP: gg holds g^T z)
 }
 
 template <typename T>
@@ -1288,7 +1294,7 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
     const auto *st = gl(st_);
     __shared__ T tile[32][33];
     const T bt = (T)beta_of(st, rule, init);
-    const auto *src = (rule == 2) ? z : g;
+    const auto *src = (rule == 2 || rule == 4) ? z : g;   // PCG rules step along -z
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -1376,6 +1382,40 @@ template <typename T>
 void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
 {
     hipLaunchKernelGGL(kb_pq_update<T>, dim3(nblocks), dim3(256), 0, s, S, map);
+}
+
+// PCG-STEP: blocks [0, nb_vec) update x' = x + alpha p and g' = g + alpha h;
+// blocks [nb_vec, nb_vec + nb_sv) update sinogram row a of the recursive
+// residual, r' = r + alpha q (the filtered residual gives the next z).
+template <typename T>
+__global__ __launch_bounds__(256) void kb_x_update_pcg(const Solve<T> *S, const BlkMap *map)
+{
+    const BlkMap m = locate(map);
+    const Solve<T> d = load_solve(S, m.solve);
+    if (stopped(d.st)) return;
+    const T al = (T)gl(d.st)->alpha;
+    if (m.local < d.nb_vec) {
+        const size_t J = (size_t)d.G.n * d.G.n;
+        auto *x = gl(d.x), *g = gl(d.g);
+        const auto *p = gl(d.p), *h = gl(d.h);
+        for (size_t q = m.local * (size_t)blockDim.x + threadIdx.x; q < J;
+             q += (size_t)d.nb_vec * blockDim.x) {
+            x[q] = fma(al, p[q], x[q]);
+            g[q] = fma(al, h[q], g[q]);
+        }
+    } else {
+        const size_t row = (size_t)(m.local - d.nb_vec) * d.G.rs + kSinoPadL;
+        auto *r = gl(d.r);
+        const auto *q = gl(d.q);
+        for (int b = threadIdx.x; b < d.G.nb; b += blockDim.x)
+            r[row + b] = fma(al, q[row + b], r[row + b]);
+    }
+}
+
+template <typename T>
+void launch_b_x_update_pcg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_x_update_pcg<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map);
 }
 
 // Plain CG (Alg. CG, CG-STEP): x' = x + alpha p and the recursive gradient
@@ -1558,7 +1598,7 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         const double beta = beta_of(st, arg0, arg1);
         st->beta = beta;
         st->gp = tot[0];
-        if (arg0 == 3) st->delta = st->gg;
+        if (arg0 == 3 || arg0 == 4) st->delta = st->gg;
         if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
         if (!arg1)
             if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
@@ -1588,6 +1628,19 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
             st->alpha = -tot[0] / tot[1];
             if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
         }
+        return;
+    }
+    case kFinDeltaPCG: {
+        // delta' = g'^T z' of a PCG-STEP; arg0 = 1: inside a PCG-K pass (the
+        // pass counts as one step)
+        final_sums(d.partials, d.nb_bp, 1, 1, tot);
+        if (threadIdx.x != 0) return;   // the block's other threads are done
+        st->gg = tot[0];
+        if (!isfinite(tot[0])) set_done(st, SCG_ENAN);
+        if (arg0 == 1) return;
+        st->qq_prev = st->qq;
+        st->k += 1;
+        st->steps += 1;
         return;
     }
     case kFinXUpdateCG: {
@@ -1805,6 +1858,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
                                        hipStream_t);                                            \
     template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
     template void launch_b_pq_update<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);   \
+    template void launch_b_x_update_pcg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
     template void launch_b_filter<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
     template void launch_b_copy_out<T>(const Solve<T> *, const BlkMap *, int, int,             \
                                        hipStream_t);                                            \

@@ -150,6 +150,7 @@ enum Phase : int {
     kStageX = 7,      // xs = x^T
     kPjU = 8,         // u = A g' into rt, partials of u^T q (S-CG, three operators)
     kBpGT = 9,        // g = A^T r and xs = g^T (S-CG, three operators)
+    kBpZ = 10,        // z = A^T rt, partials of z^T g (PCG steps)
 };
 
 // Finishers: one block per solve sums the partials of the previous launch
@@ -169,6 +170,7 @@ enum Fin : int {
     kFinTV = 11,           // TV of the output
     kFinDotUQ = 12,        // (A g')^T q (S-CG, three operators)
     kFinPQ = 13,           // beta, g^T p, ||q||^2 and alpha of the p and q updates
+    kFinDeltaPCG = 14,     // PCG: delta' = g^T z and the step count
 };
 
 // Block counts of the solver kernels for one solve.
@@ -226,6 +228,10 @@ void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hip
 // nb_sv blocks) in one launch, with the partials of g'^T p' and ||q'||^2
 template <typename T>
 void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+// PCG-STEP: x' = x + alpha p, g' = g + alpha h (blocks [0, nb_vec)) and the
+// recursive residual r' = r + alpha q (the next nb_sv blocks)
+template <typename T>
+void launch_b_x_update_pcg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 template <typename T>
 void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
                      hipStream_t s);

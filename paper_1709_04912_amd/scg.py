@@ -20,7 +20,8 @@ SCG_OK, SCG_EINVAL, SCG_ENOMEM, SCG_EDEVICE = 0, -1, -2, -3
 SCG_ENOCONV, SCG_ENAN, SCG_EBREAKDOWN = -4, -5, -6
 SCG_EAGAIN, SCG_EINPROGRESS, SCG_ENOTFOUND = -7, -8, -9
 SCG_F32, SCG_F64 = 0, 1
-VARIANTS = {"CG": 0, "S_CG": 1, "S_CG_CD": 2, "S_PCG": 3, "S_CG_K": 4, "S_CG_3OP": 5}
+VARIANTS = {"CG": 0, "S_CG": 1, "S_CG_CD": 2, "S_PCG": 3, "S_CG_K": 4, "S_CG_3OP": 5,
+            "PCG": 6, "S_PCG_K": 7}
 SCG_FLAG_NO_PERTURB = 1
 
 

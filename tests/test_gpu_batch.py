@@ -32,7 +32,7 @@ def torch_mod():
 # launch shapes per case (project_groups, backproject_split, project_angles,
 # swizzle): solves with different shapes run in different groups of a batch
 SHAPES = [(4, 4, 8, 0), (4, 2, 8, 0), (2, 1, 4, 1), (4, 4, 8, 0), (4, 4, 4, 1), (4, 4, 8, 1),
-          (2, 2, 8, 0), (4, 4, 4, 0), (4, 2, 8, 1)]
+          (2, 2, 8, 0), (4, 4, 4, 0), (4, 2, 8, 1), (2, 4, 4, 0), (4, 1, 8, 1)]
 
 # (n, n_angles, n_bins, variant, precision, seed)
 CASES = [
@@ -45,6 +45,8 @@ CASES = [
     (24, 30, 37, "S_PCG", "f64", 7),
     (40, 60, 61, "S_CG_K", "f32", 8),
     (44, 60, 67, "S_CG_3OP", "f32", 9),
+    (36, 50, 55, "PCG", "f32", 10),
+    (40, 48, 61, "S_PCG_K", "f32", 11),
 ]
 
 

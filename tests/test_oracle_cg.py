@@ -159,3 +159,44 @@ def test_scg_k_terminates_below_eps(oracle_lib):
     big = 2 * prob.f(x0)
     res0 = alg.scg_k(prob, x0, eps=big, pp=pp, K=2)
     assert res0.k == 0 and np.array_equal(res0.x, x0)
+
+
+def test_spcg_1_without_perturbation_is_preconditioned_descent(oracle_lib):
+    """S-PCG-K with K = 1 and gamma0 = 0: each pass is one exact line search
+    along -z, z = A^T K (A x - y) the filtered-residual direction,
+    x' = x - (g^T z / ||A z||^2) z with g = A^T (A x - y) (written with the
+    dense A and the filter as a dense matrix). The loop tests f of the pass's
+    input, so the output after m passes is the (m-1)-th iterate."""
+    g, A, y = _small_problem(oracle_lib, n=6, na=12, nb=9, seed=8)
+    prob = alg.Problem(g, y)
+    Kd = np.stack([prob.K(e) for e in np.eye(g.L)], axis=1)
+    x = np.zeros(g.J)
+    it = [x.copy()]
+    for _ in range(8):
+        r = A @ x - y
+        gr = A.T @ r
+        z = A.T @ (Kd @ r)
+        Az = A @ z
+        x = x - (gr @ z) / (Az @ Az) * z
+        it.append(x.copy())
+    f = [0.5 * float(np.sum((A @ v - y) ** 2)) for v in it]
+    assert all(f[i + 1] < f[i] for i in range(len(f) - 1))
+    for m in range(2, 7):
+        eps = 0.5 * (f[m - 1] + f[m - 2])
+        res = alg.spcg_k(prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(0.0), K=1)
+        assert res.k == m, (m, res.k)
+        ref = it[m - 1]
+        assert np.linalg.norm(res.x - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert res.f_out <= eps
+
+
+def test_pcg_k_equals_pcg(oracle_lib):
+    """PCG-K from x0 with K steps is K iterations of PCG."""
+    g, A, y = _small_problem(oracle_lib, seed=9)
+    prob = alg.Problem(g, y)
+    x0 = np.zeros(g.J)
+    for K in (1, 2, 4):
+        xk, f0 = alg.pcg_k(prob, x0, K)
+        ref = alg.pcg(prob, x0, eps=0.0, max_iter=K).x
+        assert np.linalg.norm(xk - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert f0 == pytest.approx(prob.f(x0))
