@@ -32,8 +32,8 @@ namespace {
 
 // Workspace layout of one solve.
 struct Layout {
-    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, state, forced, trace, tv, gtab, desc,
-        total;
+    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, partials2, state, forced, trace, tv,
+        gtab, desc, total;
 };
 
 Layout layout(const Geo &G, size_t esz, int max_iter)
@@ -59,6 +59,7 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
     L.xs = take(G.staged_elems() * esz);
     L.pt = take(G.staged_elems() * esz);
     L.partials = take(kMaxPartials * sizeof(double));
+    L.partials2 = take(kMaxPartials * sizeof(double));
     L.state = take(sizeof(DevState));
     L.forced = take((size_t)2 * (max_iter + 1) * sizeof(int32_t));
     L.trace = take((size_t)(max_iter + 1) * sizeof(scg_trace_entry));
@@ -240,7 +241,8 @@ template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
         e.p_update(0, 1);
     }
     e.project(kPjQ);
-    e.finish(kFinNormQ);
+    // alpha: the first TV pass forms it (S-CG, S-CG-CD, S-PCG)
+    if (g.variant == SCG_S_CG_3OP) e.finish(kFinNormQ);
     if (g.variant != SCG_S_CG_CD && g.variant != SCG_S_CG_3OP) e.backproject(kBpH, 0);
 }
 
@@ -341,22 +343,21 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
         e.pq_update();
         return;
     }
+    // beta comes from the backprojection's dot inside the direction update,
+    // alpha from ||A p'||^2 inside the next TV pass; their finishers record
+    // them (no finisher launch of their own)
     if (g.variant == SCG_S_PCG) {
         e.filter();
         e.backproject(kBpGZ, 1);
-        e.finish(kFinDotGH);
         e.p_update(2, 0);
     } else if (g.variant == SCG_S_CG_CD) {
         e.backproject(kBpG, 2);
-        e.finish(kFinDotGG);
         e.p_update(1, 0);
     } else {
         e.backproject(kBpG, 1);
-        e.finish(kFinDotGH);
         e.p_update(0, 0);
     }
     e.project(kPjQ);
-    e.finish(kFinNormQ);
     if (g.variant != SCG_S_CG_CD) e.backproject(kBpH, 0);
 }
 
@@ -408,6 +409,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.pt = at(L.pt);
     h.xout = static_cast<T *>(xout_);
     h.partials = reinterpret_cast<double *>(ws + L.partials);
+    h.partials2 = reinterpret_cast<double *>(ws + L.partials2);
     h.gtab = reinterpret_cast<double *>(ws + L.gtab);
     h.tvd = reinterpret_cast<double *>(ws + L.tv);
     h.st = reinterpret_cast<DevState *>(ws + L.state);

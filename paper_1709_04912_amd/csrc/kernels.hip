@@ -162,6 +162,48 @@ __device__ void final_sums(const double *partials, int nblk, int stride, int nv,
     __syncthreads();
 }
 
+// Sum over b < nblk of partials[b], formed by every thread of a kBlock-thread
+// block (b strided by the block, four loads in flight, then fixed butterflies
+// and the waves' sums in order) and returned to all of them. Every block that
+// calls it on the same data gets the same bits: a kernel that needs a scalar
+// of the previous launch forms it itself, and the finisher that records it
+// forms the same value.
+__device__ double block_sum1(const double *partials, int nblk)
+{
+    __shared__ double wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int U = 4;
+    const auto *pg = gl(partials);
+    double acc = 0.0;
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += kBlock * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + kBlock * u;
+            v[u] = b < nblk ? pg[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + kBlock * u < nblk) acc += v[u];
+    }
+    acc = wave_sum(acc);
+    __syncthreads();   // a previous call's readers are done with wsum
+    if (lane == 0) wsum[wid] = acc;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
+    return t;
+}
+
+// Variants whose step size alpha = -g'^T p' / ||A p'||^2 is formed by the TV
+// pass that uses it (and recorded by that pass's finisher) instead of by a
+// finisher launch of its own.
+__device__ __forceinline__ bool local_alpha(int variant)
+{
+    return variant == SCG_S_CG || variant == SCG_S_CG_CD || variant == SCG_S_PCG;
+}
+
 __device__ __forceinline__ bool stopped(const DevState *st)
 {
     return st != nullptr && gl(st)->done;
@@ -1061,7 +1103,7 @@ void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t 
 template <typename T>
 __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T *__restrict__ x_,
                          T *__restrict__ s_out_, const Geo &G, double *partials,
-                         const DevState *st_, VBlk vb)
+                         const DevState *st_, double alpha, VBlk vb)
 {
     const auto *xh = gl(xh_);
     const auto *p = gl(p_);
@@ -1072,7 +1114,7 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
     __shared__ T tile[TH + 2][TW + 2];
     const int n = G.n;
     const int i0 = vb.y * TH, j0 = vb.x * TW;
-    const T al = (T)st->alpha;
+    const T al = (T)alpha;
     const T k2 = (T)(st->kappa * st->kappa);
     // S-CG-K, S-PCG-K: x_{k+1} is the pass's output, already in x
     const bool given = st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K;
@@ -1113,7 +1155,12 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
-    xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials, d.st,
+    const auto *st = gl(d.st);
+    // alpha of the open step: from the projection's partials (recorded by
+    // this pass's finisher) or from the state
+    double alpha = st->alpha;
+    if (local_alpha(st->variant) && st->open) alpha = -st->gp / block_sum1(d.partials, d.nb_pj);
+    xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
 }
 
@@ -1285,15 +1332,14 @@ template <typename S> __device__ __forceinline__ double beta_of(S *st, int rule,
 template <typename T>
 __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_,
                               T *__restrict__ p_, T *__restrict__ pt_, const Geo &G,
-                              double *partials, const DevState *st_, int rule, int init, VBlk vb)
+                              double *partials, int rule, int init, double beta, VBlk vb)
 {
     const auto *g = gl(g_);
     const auto *z = gl(z_);
     auto *p = gl(p_);
     auto *pt = gl(pt_);
-    const auto *st = gl(st_);
     __shared__ T tile[32][33];
-    const T bt = (T)beta_of(st, rule, init);
+    const T bt = (T)beta;
     const auto *src = (rule == 2 || rule == 4) ? z : g;   // PCG rules step along -z
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
@@ -1329,7 +1375,15 @@ __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkM
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
-    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials, d.st, rule, init,
+    const auto *st = gl(d.st);
+    // beta of rules 0-2 from the backprojection's dot partials (recorded by
+    // this update's finisher), of the others from the state
+    double beta = beta_of(st, rule, init);
+    if (!init && rule <= 2) {
+        const double dot = block_sum1(d.partials, d.nb_bp);
+        beta = rule == 1 ? -dot / st->gp_prev : dot / st->qq_prev;
+    }
+    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials2, rule, init, beta,
                   vblk_of(m.local, nt, nt));
 }
 
@@ -1371,7 +1425,7 @@ __global__ __launch_bounds__(256) void kb_pq_update(const Solve<T> *S, const Blk
     if (stopped(d.st)) return;
     if (m.local < d.nb_t32) {
         const int nt = (d.G.n + 31) / 32;
-        p_update_body(d.g, d.z, d.p, (T *)nullptr, d.G, d.partials, d.st, 0, 0,
+        p_update_body(d.g, d.z, d.p, (T *)nullptr, d.G, d.partials, 0, 0, beta_of(gl(d.st), 0, 0),
                       vblk_of(m.local, nt, nt));
     } else {
         q_update_body(d.rt, d.q, d.G, d.st, d.partials + m.local, m.local - d.nb_t32);
@@ -1592,14 +1646,22 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         return;
     }
     case kFinPUpdate: {
-        // arg0 = rule, arg1 = init
-        final_sums(d.partials, d.nb_t32, 1, 1, tot);
+        // arg0 = rule, arg1 = init. g'^T p' from the update's partials; for
+        // rules 0-2 after the initial step also the backprojection's dot
+        // (g'^T h or ||g'||^2), which the update formed its beta from
+        const double gp = block_sum1(d.partials2, d.nb_t32);
+        const bool fused = !arg1 && arg0 <= 2;
+        const double dot = fused ? block_sum1(d.partials, d.nb_bp) : 0.0;
         if (threadIdx.x != 0) return;   // the block's other threads are done
+        if (fused) {
+            if (arg0 == 1) st->gg = dot;
+            else st->gh = dot;
+        }
         const double beta = beta_of(st, arg0, arg1);
         st->beta = beta;
-        st->gp = tot[0];
+        st->gp = gp;
         if (arg0 == 3 || arg0 == 4) st->delta = st->gg;
-        if (!isfinite(beta) || !isfinite(tot[0])) set_done(st, SCG_ENAN);
+        if (!isfinite(beta) || !isfinite(gp)) set_done(st, SCG_ENAN);
         if (!arg1)
             if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
         return;
@@ -1704,8 +1766,24 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         // Closes the previous step (k, the carried ||A p||^2 and g^T p),
         // applies the iteration cap, opens the new step (TV(x_k), v =
         // -s/||s||, replayed decisions, trace) and fills the trials' table.
-        final_sums(d.partials, d.nb_xtv, 2, 2, tot);
-        if (threadIdx.x == 0) {
+        // For the variants whose TV pass formed alpha itself, first records
+        // ||A p||^2 and alpha of the step being closed (the same sums).
+        if (threadIdx.x == 0) s_go = 0;
+        final_sums(d.partials2, d.nb_xtv, 2, 2, tot);
+        const bool qa = local_alpha(st->variant) && st->open;
+        const double qq = qa ? block_sum1(d.partials, d.nb_pj) : 0.0;
+        if (threadIdx.x == 0 && qa) {
+            st->qq = qq;
+            if (!isfinite(qq)) {
+                set_done(st, SCG_ENAN);
+            } else if (qq == 0.0) {
+                set_done(st, SCG_EBREAKDOWN);
+            } else {
+                st->alpha = -st->gp / qq;
+                if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
+            }
+        }
+        if (threadIdx.x == 0 && !st->done) {
             if (st->open) {
                 st->qq_prev = st->qq;
                 st->gp_prev = st->gp;

@@ -124,6 +124,8 @@ template <typename T> struct Solve {
     T *xs, *pt;                 // transposes of x_{k+1/2} (x, or g') and of p
     T *xout;                    // caller's output image
     double *partials;           // block partial sums of the last reduction
+    double *partials2;          // partial sums of the TV pass and the direction
+                                // update (they read the other region's sums)
     double *gtab;               // gamma0 a^(l+m), m < max_trials
     double *tvd;                // TV of the output
     DevState *st;
