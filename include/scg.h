@@ -108,10 +108,11 @@ typedef struct {
 typedef struct {
     int32_t status;       /* SCG_OK, SCG_ENOCONV, SCG_ENAN or SCG_EBREAKDOWN      */
     int32_t k;            /* the paper's counter k when the loop ended; the       */
-                          /* output is x_{k-1/2} (SCG_S_CG_K: passes made, 0 when */
-                          /* f(x0) <= eps)                                        */
+                          /* output is x_{k-1/2} (SCG_S_CG_K, SCG_S_PCG_K: passes */
+                          /* made, 0 when f(x0) <= eps; SCG_CG, SCG_PCG: steps    */
+                          /* made, the output is x_k)                             */
     int32_t steps;        /* steps executed after the initial one (passes for    */
-                          /* SCG_S_CG_K)                                          */
+                          /* SCG_S_CG_K and SCG_S_PCG_K)                          */
     int32_t trials_total; /* TV trials made by perturbed()                        */
     int32_t ell;          /* final value of the gamma counter l                   */
     int32_t reserved;
@@ -139,7 +140,11 @@ typedef struct scg_plan scg_plan;
 /* Creates a plan for geometry *g on HIP device `device`: FP64 angle tables
  * (cos/sin evaluated in double and snapped to 0/+-1 within 1e-12) are built on
  * the host and uploaded, and the plan's scratch is allocated. *out is set to
- * NULL on failure. Errors: SCG_EINVAL (sizes), SCG_ENOMEM, SCG_EDEVICE. */
+ * NULL on failure. Errors: SCG_EINVAL (sizes: 2 <= N <= 2880, and the
+ * projector's (angle group, 128-bin chunk) blocks at most 65536, about
+ * n_angles / 4 * ceil(n_bins / 128)), SCG_ENOMEM, SCG_EDEVICE. The
+ * preconditioning filter (SCG_S_PCG, SCG_PCG, SCG_S_PCG_K, scg_filter)
+ * needs n_bins <= 2730 and returns SCG_EINVAL otherwise. */
 int scg_plan_create(const scg_geom *g, int device, scg_plan **out);
 
 /* Frees a plan and its device memory (NULL is accepted). The caller must

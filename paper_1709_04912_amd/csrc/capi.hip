@@ -180,6 +180,8 @@ namespace scg {
 int ensure_filter(scg_plan *p, double mu)
 {
     const int nb = p->G.nb, P = filter_pad(nb);
+    // a padded projection and the taps of one angle must fit in LDS
+    if ((size_t)3 * nb * sizeof(double) > 65536) return SCG_EINVAL;
     if (mu <= 0.0) mu = 2.0 * kPi / P;
     if (p->kern[0] != nullptr && p->kern_mu == mu) return SCG_OK;
     std::vector<double> k(nb);
@@ -422,12 +424,12 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     G.rs = G.nb + scg::kSinoPadL + scg::kSinoPadR;
     G.h = 0.5 * (G.n - 1);
     G.hb = 0.5 * (G.nb - 1);
-    // Every reduction's block partials must fit the partials buffer, and a
-    // padded projection plus the filter taps must fit in LDS.
+    // Every reduction's block partials must fit the partials buffer (the
+    // preconditioning filter's LDS bound is checked where the filter is set
+    // up).
     if ((size_t)scg::blocks_bp(G) > (size_t)scg::kMaxPartials ||
         2 * (size_t)scg::blocks_xtv(G) > (size_t)scg::kMaxPartials ||
-        (size_t)scg::blocks_t32(G) + scg::blocks_sv(G) > (size_t)scg::kMaxPartials ||
-        (size_t)3 * G.nb * sizeof(double) > 65536) {
+        (size_t)scg::blocks_t32(G) + scg::blocks_sv(G) > (size_t)scg::kMaxPartials) {
         delete p;
         return SCG_EINVAL;
     }

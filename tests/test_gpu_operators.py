@@ -215,3 +215,37 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
         for bad in ((3, 2, 8, 0), (4, 3, 8, 0), (0, 1, 8, 0), (4, 2, 6, 0), (4, 2, 8, 2)):
             with pytest.raises(scg.ScgError):
                 plan.set_tuning(scg.SCG_F32, *bad)
+
+
+def test_size_limits(scg, torch_mod, oracle_lib):
+    """The largest accepted image (N = 2880: the TV pass's block partials
+    fill the partials buffer) with a detector of 4076 bins, on sampled rays
+    and pixels against the oracle; one pixel more is rejected, and the
+    filter (only) rejects more than 2730 bins."""
+    torch = torch_mod
+    n, na, nb = 2880, 6, 4076
+    print(f"[limits] N={n} angles={na} bins={nb}", flush=True)
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(2880)
+    x = rng.uniform(0, 1, n * n)
+    y = rng.uniform(-1, 1, na * nb)
+    rays = np.concatenate([rng.choice(na * nb, 200, replace=False),
+                           np.arange(0, nb, 97), (na // 2) * nb + np.arange(0, nb, 89)])
+    pix = rng.choice(n * n, 200, replace=False)
+    with scg.Plan(n, na, nb) as plan:
+        ax = plan.project(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+        aty = plan.backproject(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
+        with pytest.raises(scg.ScgError):
+            plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda"))
+        with pytest.raises(scg.ScgError):
+            plan.solve(torch.tensor(y, dtype=torch.float32, device="cuda"),
+                       plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", max_iter=1),
+                       trace=False)
+    assert _rel(ax[rays], g.project_rays(x, rays)) <= 1e-5
+    assert _rel(aty[pix], g.backproject_pixels(y, pix)) <= 1e-5
+    assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
+    with pytest.raises(scg.ScgError):
+        scg.Plan(n + 1, na, 64)
+    with scg.Plan(64, 8, 2730) as plan:
+        r = torch.zeros(8 * 2730, dtype=torch.float32, device="cuda")
+        assert float(plan.filter(r).abs().max()) == 0.0
