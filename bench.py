@@ -121,8 +121,11 @@ def cpu_baseline(w, eps, gamma0, steps_gpu):
                        f"the GPU solve's {steps_gpu} steps")}
 
 
-def mixed_runs(n_serve):
-    """Batched and served runs against plain one-at-a-time solves."""
+def mixed_runs(n_serve, shape):
+    """Batched and served runs against plain one-at-a-time solves. Every plan
+    gets `shape` (the autotuner's pick at 512^2): one shape makes each phase
+    of the mix one launch, and one-at-a-time solves run as fast with it as
+    with per-geometry picks (which differ only in the block order)."""
     import torch
     from paper_1709_04912_amd import serve
     from synth.workloads import make_batch_item, make_serve_item, poisson_arrivals
@@ -145,7 +148,7 @@ def mixed_runs(n_serve):
     def same(a, b):
         return sum(int(torch.equal(a.outputs[i], b.outputs[i])) for i in a.outputs)
 
-    cache = serve.PlanCache()
+    cache = serve.PlanCache(shape=shape)
     log("batched run: generating 64 solves")
     reqs = build([make_batch_item(i) for i in range(64)])
     warm(reqs)
@@ -160,7 +163,7 @@ def mixed_runs(n_serve):
         "speedup": b.recons_per_s / p.recons_per_s,
         "batched_without_graph_recons_per_s": be.recons_per_s,
         "bitwise_equal_outputs": same(p, b), "bitwise_equal_without_graph": same(p, be),
-        "solves": len(reqs),
+        "solves": len(reqs), "launch_shape": list(shape),
         "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports))}
     log(f"batched: {batched}")
     pool = 120
@@ -176,7 +179,8 @@ def mixed_runs(n_serve):
     served = {
         "workload": f"{n_serve} requests, Poisson 200/s, (N, angles) in (128,180) (256,360) "
                     "(512,720) (1024,1440) weights 0.4/0.3/0.2/0.1, eps = f(x_true)",
-        "batched": b.summary(), "plain": p.summary(), "bitwise_equal_outputs": same(p, b)}
+        "batched": b.summary(), "plain": p.summary(), "bitwise_equal_outputs": same(p, b),
+        "launch_shape": list(shape)}
     log(f"served: {served}")
     cache.close()
     return batched, served
@@ -365,7 +369,9 @@ def main():
     }
     result["three_operator"] = three_operator_run(plan, y, params, out, ws, stream, w, args.steps)
     if not args.no_mix:
-        result["batched"], result["served"] = mixed_runs(args.serve_requests)
+        shape = (tuning["project_groups"], tuning["backproject_split"],
+                 tuning["project_angles"], tuning["swizzle"])
+        result["batched"], result["served"] = mixed_runs(args.serve_requests, shape)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(w, eps, gamma0, rep.steps)

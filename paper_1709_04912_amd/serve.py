@@ -38,19 +38,24 @@ class Request:
 
 
 class PlanCache:
-    """One plan per geometry (trig tables, projector windows, launch shapes
-    picked by the autotuner on first use)."""
+    """One plan per geometry (trig tables, projector windows). Launch shapes:
+    `shape` (project_groups, backproject_split, project_angles, swizzle) for
+    every plan when given - solves that share a shape run as one group, one
+    launch per phase in a batch - else the autotuner's pick per geometry."""
 
-    def __init__(self, device: int = 0, autotune: bool = True):
+    def __init__(self, device: int = 0, autotune: bool = True, shape=None):
         self.device = device
         self.autotune = autotune
+        self.shape = tuple(shape) if shape is not None else None
         self.plans = {}
 
     def get(self, n: int, n_angles: int, n_bins: int) -> "scg.Plan":
         key = (n, n_angles, n_bins)
         if key not in self.plans:
             p = scg.Plan(n, n_angles, n_bins, device=self.device)
-            if self.autotune:
+            if self.shape is not None:
+                p.set_tuning(scg.SCG_F32, *self.shape)
+            elif self.autotune:
                 p.autotune(scg.SCG_F32)
             self.plans[key] = p
         return self.plans[key]
