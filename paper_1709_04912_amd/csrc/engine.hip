@@ -382,7 +382,8 @@ template <typename T> struct Staging {
 template <typename T>
 int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, char *ws,
                   const void *y_, const void *x0_, void *xout_, int trace_cap,
-                  const int32_t *forced_host, int forced_len, Staging<T> *stage, hipStream_t s)
+                  const int32_t *forced_host, int forced_len, Staging<T> *stage, hipStream_t s,
+                  bool defer = false)
 {
     const Geo &G = plan->G;
     const size_t J = G.img_elems(), S = G.sino_elems();
@@ -426,11 +427,14 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.nb_trA = blocks_trials(G, 1);
     h.nb_trB = h.trB_chunks > 0 ? blocks_trials(G, h.trB_chunks) : 0;
 
-    // Pads of the staged image and of the sinograms must be zero.
-    launch_fill<T>(h.r, S, T(0), s);
-    launch_fill<T>(h.q, S, T(0), s);
-    launch_fill<T>(h.rt, S, T(0), s);
-    launch_fill<T>(h.xs, G.staged_elems(), T(0), s);
+    // Pads of the staged image and of the sinograms must be zero (a batch
+    // admission does this with the device set-up below: see Admit).
+    if (!defer) {
+        launch_fill<T>(h.r, S, T(0), s);
+        launch_fill<T>(h.q, S, T(0), s);
+        launch_fill<T>(h.rt, S, T(0), s);
+        launch_fill<T>(h.xs, G.staged_elems(), T(0), s);
+    }
 
     const bool is_cg = unsuperiorized(pr->variant);
     DevState &hs = stage->st;
@@ -459,6 +463,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
                                : 0;
     hs.forced_len = nf;
     h.forced = nf > 0 ? forced : nullptr;
+    if (defer) return SCG_OK;
     HIP_TRY(hipMemcpyAsync(h.st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
     if (nf > 0)
         HIP_TRY(hipMemcpyAsync(forced, forced_host, (size_t)2 * nf * sizeof(int32_t),
@@ -626,6 +631,9 @@ struct Slot {
     scg_tuning tune{};           // launch shapes fixed at admission
     size_t off = 0, bytes = 0;
     int staging = -1;            // index of the slot's pinned staging entry
+    bool fresh = false;          // admitted; its set-up and initial step run at the next
+                                 // rebuild, with the other new solves
+    const void *x0 = nullptr;    // start image (null: zero)
     Solve<float> df{};
     Solve<double> dd{};
 };
@@ -759,6 +767,60 @@ void drop_graph(scg_batch *b)
 
 // Groups the active solves, uploads their descriptors and block maps and
 // (unless disabled) captures one iteration of all groups as a graph.
+// Device set-up of the fresh solves of one precision: their state and
+// descriptor images and the Admit records go into the composition upload; the
+// records' device pointers are filled in once the buffer's address is known.
+template <typename T> struct AdmitPack {
+    std::vector<int> who;
+    size_t st_off = 0, desc_off = 0, rec_off = 0;
+};
+
+template <typename T> AdmitPack<T> pack_admits(Packer &pk, scg_batch *b)
+{
+    AdmitPack<T> ap;
+    std::vector<DevState> sts;
+    std::vector<Solve<T>> ds;
+    for (int i = 0; i < (int)b->active.size(); ++i) {
+        Slot &sl = b->active[i];
+        if (!sl.fresh || (sl.params.prec == SCG_F64) != (sizeof(T) == 8)) continue;
+        ap.who.push_back(i);
+        sts.push_back(staging_of<T>(b->staging[sl.staging]).st);
+        ds.push_back(desc_of<T>(sl));
+    }
+    if (ap.who.empty()) return ap;
+    ap.st_off = pk.put(sts);
+    ap.desc_off = pk.put(ds);
+    ap.rec_off = pk.put(std::vector<scg::Admit<T>>(ap.who.size()));
+    return ap;
+}
+
+template <typename T> void fill_admits(Packer &pk, scg_batch *b, const AdmitPack<T> &ap)
+{
+    auto *recs = reinterpret_cast<scg::Admit<T> *>(pk.bytes.data() + ap.rec_off);
+    for (size_t k = 0; k < ap.who.size(); ++k) {
+        Slot &sl = b->active[ap.who[k]];
+        const Solve<T> &h = desc_of<T>(sl);
+        const scg::Layout L = scg::layout(h.G, sizeof(T), sl.params.max_iter);
+        const bool from_x = scg::unsuperiorized(sl.params.variant) ||
+                            scg::restarted(sl.params.variant);
+        scg::Admit<T> a{};
+        a.st_src = reinterpret_cast<const DevState *>(b->comp + ap.st_off) + k;
+        a.st = h.st;
+        a.desc_src = reinterpret_cast<const Solve<T> *>(b->comp + ap.desc_off) + k;
+        a.desc = reinterpret_cast<Solve<T> *>(b->arena.base + sl.off + L.desc);
+        a.x0 = static_cast<const T *>(sl.x0);
+        a.x_start = from_x ? h.x : h.xh;
+        a.xh = scg::restarted(sl.params.variant) ? h.xh : nullptr;
+        a.r = h.r;
+        a.q = h.q;
+        a.rt = h.rt;
+        a.xs = h.xs;
+        a.J = (long long)h.G.img_elems();
+        a.S = (long long)h.G.sino_elems();
+        recs[k] = a;
+    }
+}
+
 int rebuild(scg_batch *b)
 {
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -779,25 +841,40 @@ int rebuild(scg_batch *b)
             .push_back(i);
     }
     Packer pk;
-    std::vector<GroupImage<float>> imf;
-    std::vector<GroupImage<double>> imd;
+    const AdmitPack<float> apf = pack_admits<float>(pk, b);
+    const AdmitPack<double> apd = pack_admits<double>(pk, b);
+    std::vector<GroupImage<float>> imf, inf;
+    std::vector<GroupImage<double>> imd, ind;
     for (auto &kv : keys) {
         const int pi = std::get<0>(kv.first);
         const Slot &first = b->active[kv.second.front()];
         const int variant = first.params.variant;
         const scg_tuning t = first.tune;
+        // the newly admitted solves of the group take their initial step
+        // together, one launch per phase
+        std::vector<int> fresh;
+        for (int i : kv.second)
+            if (b->active[i].fresh) fresh.push_back(i);
         if (pi == 0) {
             imf.push_back(pack_group<float>(pk, b->active, kv.second, variant, t, true));
             b->members_f.push_back(kv.second);
+            if (!fresh.empty()) inf.push_back(pack_group<float>(pk, b->active, fresh, variant, t, true));
         } else {
             imd.push_back(pack_group<double>(pk, b->active, kv.second, variant, t, true));
             b->members_d.push_back(kv.second);
+            if (!fresh.empty()) ind.push_back(pack_group<double>(pk, b->active, fresh, variant, t, true));
         }
     }
     int rc = ensure_buf(&b->comp, &b->comp_bytes, std::max<size_t>(pk.bytes.size(), 256));
     if (rc) return rc;
+    fill_admits<float>(pk, b, apf);
+    fill_admits<double>(pk, b, apd);
     if (!pk.bytes.empty())
         HIP_TRY(hipMemcpy(b->comp, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
+    scg::launch_admit<float>(reinterpret_cast<const scg::Admit<float> *>(b->comp + apf.rec_off),
+                             (int)apf.who.size(), b->stream);
+    scg::launch_admit<double>(reinterpret_cast<const scg::Admit<double> *>(b->comp + apd.rec_off),
+                              (int)apd.who.size(), b->stream);
     for (auto &gi : imf) {
         place(gi, b->comp);
         b->gf.push_back(gi.g);
@@ -806,6 +883,15 @@ int rebuild(scg_batch *b)
         place(gi, b->comp);
         b->gd.push_back(gi.g);
     }
+    for (auto &gi : inf) {
+        place(gi, b->comp);
+        scg::enqueue_init(gi.g, b->stream);
+    }
+    for (auto &gi : ind) {
+        place(gi, b->comp);
+        scg::enqueue_init(gi.g, b->stream);
+    }
+    for (auto &sl : b->active) sl.fresh = false;
     if (!(b->flags & SCG_BATCH_NO_GRAPH) && !b->active.empty()) {
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         for (auto &g : b->gf) scg::enqueue_iteration(g, b->stream);
@@ -926,12 +1012,11 @@ int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *
     scg::Staging<T> &stage = staging_of<T>(b->staging[slot.staging]);
     slot.tune = plan->tune[scg::prec_index<T>()];
     int rc = scg::prepare_solve<T>(plan, pr, slot.tune, ws, y, x0, x_out, 0, nullptr, 0, &stage,
-                                   b->stream);
+                                   b->stream, true);
     if (rc) return rc;
-    const Solve<T> &h = stage.desc;
-    desc_of<T>(slot) = h;
-    scg::Group<T> g = scg::single_group<T>(pr, slot.tune, h, ws);
-    scg::enqueue_init(g, b->stream);
+    desc_of<T>(slot) = stage.desc;
+    slot.x0 = x0;
+    slot.fresh = true;   // set-up and initial step run with the other new solves
     return SCG_OK;
 }
 

@@ -1438,6 +1438,44 @@ void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipSt
     hipLaunchKernelGGL(kb_pq_update<T>, dim3(nblocks), dim3(256), 0, s, S, map);
 }
 
+// Batch admission (see Admit): block row y serves record y.
+template <typename T> __global__ __launch_bounds__(256) void kb_admit(const Admit<T> *recs)
+{
+    const Admit<T> a = gl(recs)[blockIdx.y];
+    if (blockIdx.x == 0) {
+        constexpr int kSt = sizeof(DevState) / 4, kDs = sizeof(Solve<T>) / 4;
+        static_assert(sizeof(DevState) % 4 == 0 && sizeof(Solve<T>) % 4 == 0, "word copies");
+        const auto *ss = gl(reinterpret_cast<const unsigned *>(a.st_src));
+        auto *sd = gl(reinterpret_cast<unsigned *>(a.st));
+        const auto *ds = gl(reinterpret_cast<const unsigned *>(a.desc_src));
+        auto *dd = gl(reinterpret_cast<unsigned *>(a.desc));
+        for (int i = threadIdx.x; i < kSt; i += blockDim.x) sd[i] = ss[i];
+        for (int i = threadIdx.x; i < kDs; i += blockDim.x) dd[i] = ds[i];
+    }
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    auto *xs = gl(a.xs), *xst = gl(a.x_start), *xh = gl(a.xh);
+    const auto *x0 = gl(a.x0);
+    for (long long i = t0; i < a.J; i += stride) {
+        const T v = a.x0 != nullptr ? x0[i] : T(0);
+        xst[i] = v;
+        if (a.xh != nullptr) xh[i] = v;
+        xs[i] = T(0);
+    }
+    auto *r = gl(a.r), *q = gl(a.q), *rt = gl(a.rt);
+    for (long long i = t0; i < a.S; i += stride) {
+        r[i] = T(0);
+        q[i] = T(0);
+        rt[i] = T(0);
+    }
+}
+
+template <typename T> void launch_admit(const Admit<T> *recs, int n, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(kb_admit<T>, dim3(64, n), dim3(256), 0, s, recs);
+}
+
 // PCG-STEP: blocks [0, nb_vec) update x' = x + alpha p and g' = g + alpha h;
 // blocks [nb_vec, nb_vec + nb_sv) update sinogram row a of the recursive
 // residual, r' = r + alpha q (the filtered residual gives the next z).
@@ -1937,6 +1975,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
     template void launch_b_pq_update<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);   \
     template void launch_b_x_update_pcg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
+    template void launch_admit<T>(const Admit<T> *, int, hipStream_t);                        \
     template void launch_b_filter<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
     template void launch_b_copy_out<T>(const Solve<T> *, const BlkMap *, int, int,             \
                                        hipStream_t);                                            \

@@ -135,6 +135,22 @@ template <typename T> struct Solve {
     int trB_chunks;             // trial chunks of the second trial launch
 };
 
+// Set-up of one solve admitted to a batch, done on the device with the
+// other new solves in one launch: the state and the descriptor copied from
+// their packed images, the sinograms r, q, rt and the staged image xs
+// zeroed (their pads must be zero), and the start image x0 (or zero) written
+// to x_start and, for the restarted variants, also to x_{k+1/2}.
+template <typename T> struct Admit {
+    const DevState *st_src;
+    DevState *st;
+    const Solve<T> *desc_src;
+    Solve<T> *desc;
+    const T *x0;       // null: start from zero
+    T *x_start, *xh;   // xh null unless restarted
+    T *r, *q, *rt, *xs;
+    long long J, S;    // image and padded sinogram elements
+};
+
 // Block map entry of a batched launch: the solve and its local block index.
 struct BlkMap {
     int solve, local;
@@ -230,6 +246,8 @@ void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hip
 // nb_sv blocks) in one launch, with the partials of g'^T p' and ||q'||^2
 template <typename T>
 void launch_b_pq_update(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+template <typename T>
+void launch_admit(const Admit<T> *recs, int n, hipStream_t s);
 // PCG-STEP: x' = x + alpha p, g' = g + alpha h (blocks [0, nb_vec)) and the
 // recursive residual r' = r + alpha q (the next nb_sv blocks)
 template <typename T>
