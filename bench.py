@@ -24,7 +24,8 @@ gamma0 = RHO ||x_1|| per request, outputs compared bitwise):
   `served`:  a Poisson stream (mean 200 requests/s) of (N, angles) in
              {(128, 180), (256, 360), (512, 720), (1024, 1440)} with weights
              0.4/0.3/0.2/0.1; p50/p99 latency (completion - arrival) and
-             recons/s, continuous batching against a FIFO of plain solves.
+             recons/s, continuous batching against a FIFO of plain solves;
+             `overload_1000_per_s`: the same pool at five times the rate.
 """
 from __future__ import annotations
 
@@ -181,6 +182,14 @@ def mixed_runs(n_serve, shape):
                     "(512,720) (1024,1440) weights 0.4/0.3/0.2/0.1, eps = f(x_true)",
         "batched": b.summary(), "plain": p.summary(), "bitwise_equal_outputs": same(p, b),
         "launch_shape": list(shape)}
+    # the same pool offered at five times the rate: more than one solve at a
+    # time can finish, so the loops' own capacities show
+    arr = poisson_arrivals(5001, n_serve, 1000.0)
+    reqs = [serve.Request(i, base[i % pool].plan, base[i % pool].y, base[i % pool].params,
+                          float(arr[i])) for i in range(n_serve)]
+    b = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4)
+    p = serve.serve_plain(reqs)
+    served["overload_1000_per_s"] = {"batched": b.summary(), "plain": p.summary()}
     log(f"served: {served}")
     cache.close()
     return batched, served

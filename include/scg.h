@@ -298,9 +298,13 @@ int scg_batch_create(int device, size_t arena_bytes, int max_slots, uint32_t fla
 /* Waits for the batch's stream and frees everything it owns. */
 void scg_batch_destroy(scg_batch *batch);
 
-/* Admits a solve: allocates its workspace and enqueues its initial step
- * (scg_solve's arguments without trace and replay). *ticket identifies it.
- * SCG_EAGAIN: no slot or arena room now (retry after a step). */
+/* Admits a solve (scg_solve's arguments without trace and replay): takes a
+ * slot and arena room for its workspace and prepares its descriptor on the
+ * host. Its device set-up (state, zeroed sinogram pads, start image) and its
+ * initial step run at the start of the next scg_batch_step, together with
+ * those of the other solves submitted since the last step. *ticket
+ * identifies it. SCG_EAGAIN: no slot or arena room now (retry after a
+ * step). */
 int scg_batch_submit(scg_batch *batch, scg_plan *plan, const scg_params *params,
                      const void *y, const void *x0, void *x_out, uint64_t *ticket);
 

@@ -91,7 +91,7 @@ def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
     assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
 
 
-@pytest.mark.parametrize("variant", ["S_CG", "S_PCG", "S_CG_3OP"])
+@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_3OP"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
