@@ -130,15 +130,26 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
         if (!ok) continue;
         // Blocks differ in work by the bands they skip; dispatching the
         // heaviest first lets the light ones fill the tail of the launch.
+        // The hardware hands workgroup b to XCD b mod 8: launch positions on
+        // XCDs 0-3 take the groups that step over rows (they read x), those
+        // on XCDs 4-7 the groups that step over columns (they read x^T), so
+        // each XCD's L2 fetches one orientation of the image instead of both.
         const int nblk = (int)groups.size() * n_chunks;
-        std::vector<int> bands(nblk, 0), order(nblk);
+        std::vector<int> bands(nblk, 0), order;
+        std::vector<int> by_major[2];
         for (int id = 0; id < nblk; ++id) {
             for (int band = 0; band < n_bands; ++band)
                 bands[id] += win[(size_t)id * n_bands + band] != scg::kWinSkip;
-            order[id] = id;
+            by_major[groups[id / n_chunks].major].push_back(id);
         }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return bands[a] > bands[b]; });
+        for (auto &v : by_major)
+            std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return bands[a] > bands[b]; });
+        size_t next[2] = {0, 0};
+        for (int pos = 0; pos < nblk; ++pos) {
+            int mj = (pos % scg::kXcds) < scg::kXcds / 2 ? 0 : 1;
+            if (next[mj] == by_major[mj].size()) mj ^= 1;
+            order.push_back(by_major[mj][next[mj]++]);
+        }
         if (hipMalloc(&p->pgroups[ti], groups.size() * sizeof(PjGroup)) != hipSuccess ||
             hipMalloc(&p->pwin[ti], win.size() * sizeof(int)) != hipSuccess ||
             hipMalloc(&p->porder[ti], order.size() * sizeof(int)) != hipSuccess)
@@ -163,6 +174,31 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
         return SCG_OK;
     }
     return SCG_EINVAL;
+}
+
+// Backprojector tile of each launch position: the tile grid is cut into
+// kXcds regions (4 x 2, as square as the grid allows) and position b takes
+// the next tile of region b mod kXcds, the XCD the hardware hands workgroup b
+// to. Each XCD's L2 then holds the sinogram footprint of one region (about a
+// third of every projection at 512^2) instead of the whole sinogram. Tiles
+// are equal work, so the regions balance; a region that runs out lends the
+// position to the next one.
+std::vector<int> bp_tile_order(const Geo &G)
+{
+    const int nt = (G.n + scg::kBpTile - 1) / scg::kBpTile;
+    constexpr int kRx = 4, kRy = scg::kXcds / 4;
+    std::vector<std::vector<int>> region(scg::kXcds);
+    for (int ty = 0; ty < nt; ++ty)
+        for (int tx = 0; tx < nt; ++tx)
+            region[(ty * kRy / nt) * kRx + tx * kRx / nt].push_back(ty * nt + tx);
+    std::vector<int> order;
+    std::vector<size_t> next(scg::kXcds, 0);
+    for (int pos = 0; pos < nt * nt; ++pos) {
+        int r = pos % scg::kXcds;
+        while (next[r] == region[r].size()) r = (r + 1) % scg::kXcds;
+        order.push_back(region[r][next[r]++]);
+    }
+    return order;
 }
 
 int filter_pad(int nb)
@@ -443,8 +479,10 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     std::vector<ProjAngle> pa;
     std::vector<BpAngle> ba;
     build_angles(G, p->cosv, p->sinv, pa, ba);
+    const std::vector<int> bord = bp_tile_order(G);
     bool ok = hipMalloc(&p->pang, pa.size() * sizeof(ProjAngle)) == hipSuccess &&
               hipMalloc(&p->bang, ba.size() * sizeof(BpAngle)) == hipSuccess &&
+              hipMalloc(&p->border, bord.size() * sizeof(int)) == hipSuccess &&
               hipMalloc(&p->xs[0], G.staged_elems() * sizeof(float)) == hipSuccess &&
               hipMalloc(&p->xs[1], G.staged_elems() * sizeof(double)) == hipSuccess &&
               hipMalloc(&p->rpad[0], G.sino_elems() * sizeof(float)) == hipSuccess &&
@@ -458,6 +496,8 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     ok = hipMemcpy(p->pang, pa.data(), pa.size() * sizeof(ProjAngle), hipMemcpyHostToDevice) ==
              hipSuccess &&
          hipMemcpy(p->bang, ba.data(), ba.size() * sizeof(BpAngle), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(p->border, bord.data(), bord.size() * sizeof(int), hipMemcpyHostToDevice) ==
              hipSuccess &&
          hipMemset(p->xs[0], 0, G.staged_elems() * sizeof(float)) == hipSuccess &&
          hipMemset(p->xs[1], 0, G.staged_elems() * sizeof(double)) == hipSuccess &&
@@ -484,6 +524,7 @@ void scg_plan_destroy(scg_plan *p)
     scg::Device dg(p->device);
     (void)hipFree(p->pang);
     (void)hipFree(p->bang);
+    (void)hipFree(p->border);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->pgroups[i]);
         (void)hipFree(p->pwin[i]);

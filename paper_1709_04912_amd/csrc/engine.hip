@@ -394,6 +394,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.G = G;
     h.P = proj_tables(plan, tune);
     h.bang = plan->bang;
+    h.border = plan->border;
     h.kern = static_cast<const T *>(plan->kern[prec_index<T>()]);
     h.y = static_cast<const T *>(y_);
     h.x = at(L.x);

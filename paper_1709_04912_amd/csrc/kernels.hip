@@ -268,7 +268,6 @@ __device__ __forceinline__ VBlk grid_vblk()
 // XCD: the hardware hands workgroup b to XCD b mod 8, so the blocks the
 // hardware places on one XCD get one contiguous range of indices and share
 // that XCD's L2 for the data neighbouring blocks read.
-constexpr int kXcds = 8;
 __device__ __forceinline__ int launch_index(int swz)
 {
     const int b = blockIdx.x, n = gridDim.x;
@@ -941,7 +940,10 @@ __global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T>
     const Geo G = d.G;
     const BpAngle *ang = d.bang;
     const int nt = (G.n + kBpTile - 1) / kBpTile;
-    const VBlk vb = vblk_of(m.local, nt, nt);
+    // the tile of this launch position (partials are stored by tile, so the
+    // sums do not depend on the order)
+    const int tile = (swz || d.border == nullptr) ? m.local : gl(d.border)[m.local];
+    const VBlk vb = vblk_of(tile, nt, nt);
     // one body instance: kBpH is h = A^T q (no second sinogram, no dot);
     // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g';
     // kBpGT is g' with its transpose in xs; kBpZ is z = A^T rt with the dot

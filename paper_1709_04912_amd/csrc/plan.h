@@ -23,6 +23,7 @@ struct scg_plan {
     PjGroup *pgroups[2] = {nullptr, nullptr};
     int *pwin[2] = {nullptr, nullptr};
     int *porder[2] = {nullptr, nullptr};
+    int *border = nullptr;                // backprojector tile of each launch position
     ProjTables ptab[2] = {};              // projector tables, 8 and 4 angles per group
     void *xs[2] = {nullptr, nullptr};     // transposed-image scratch per precision
     void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision

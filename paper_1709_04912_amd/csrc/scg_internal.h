@@ -21,6 +21,9 @@ constexpr int kPjBand = 32;
 constexpr int kPjWin = 256;
 constexpr int kPjGroup = 8;
 constexpr int kWinSkip = -0x40000000;
+// XCDs (chiplets, each with its own L2); the hardware hands workgroup b of a
+// launch to XCD b mod kXcds.
+constexpr int kXcds = 8;
 // Backprojector tiling: 16 x 16 pixel tiles, groups of 128 threads (two
 // adjacent pixels each; 1, 2 or 4 groups per tile split the angles), angles
 // staged in LDS in chunks of kBpChunk with a window of kBpWin bins per angle
@@ -117,6 +120,7 @@ template <typename T> struct Solve {
     Geo G;
     ProjTables P;
     const BpAngle *bang;
+    const int *border;          // backprojector tile of each local block index
     const T *kern;              // filter taps (S-PCG)
     const T *y;                 // data, n_angles x n_bins
     T *x, *xh, *p, *g, *h, *s, *z;
