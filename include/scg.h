@@ -281,13 +281,15 @@ typedef struct {
     int32_t  active;        /* solves on the device                             */
     int32_t  slots;         /* max_slots                                        */
     int32_t  groups;        /* groups of the current set                       */
-    int32_t  reserved;
+    int32_t  graph_updates; /* changes of the set applied to the current graph */
+                            /* in place (same launches, new parameters)        */
     uint64_t arena_bytes;
     uint64_t arena_used;    /* workspace bytes of the active solves             */
     uint64_t submitted;
     uint64_t retired;
     uint64_t macro_steps;   /* iterations run (each over all active solves)     */
-    uint64_t graph_builds;  /* graphs captured (one per change of the set)      */
+    uint64_t graph_builds;  /* executable graphs instantiated (a change of the */
+                            /* set whose launches differ, or the first one)    */
 } scg_batch_stats;
 
 /* Creates a batch on `device` with an arena of arena_bytes and at most

@@ -825,7 +825,8 @@ template <typename T> void fill_admits(Packer &pk, scg_batch *b, const AdmitPack
 int rebuild(scg_batch *b)
 {
     HIP_TRY(hipStreamSynchronize(b->stream));
-    drop_graph(b);
+    // the executable graph is kept for an in-place update below; it is not
+    // launched before this rebuild has succeeded
     b->gf.clear();
     b->gd.clear();
     b->members_f.clear();
@@ -898,14 +899,38 @@ int rebuild(scg_batch *b)
         for (auto &g : b->gf) scg::enqueue_iteration(g, b->stream);
         for (auto &g : b->gd) scg::enqueue_iteration(g, b->stream);
         hipGraph_t graph = nullptr;
-        if (hipStreamEndCapture(b->stream, &graph) != hipSuccess || graph == nullptr)
-            return SCG_EDEVICE;
-        b->graph = graph;
-        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (hipStreamEndCapture(b->stream, &graph) != hipSuccess || graph == nullptr) {
             drop_graph(b);
             return SCG_EDEVICE;
         }
-        b->stats.graph_builds += 1;
+        // A composition with the same launches (the same groups and phases;
+        // only block counts, maps and descriptors differ, as when solves
+        // retire) updates the executable graph's kernel parameters in place,
+        // which costs far less than instantiating a new one.
+        bool updated = false;
+        if (b->exec != nullptr) {
+            hipGraphNode_t err_node = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            updated = hipGraphExecUpdate(b->exec, graph, &err_node, &res) == hipSuccess &&
+                      res == hipGraphExecUpdateSuccess;
+            if (updated) {
+                b->stats.graph_updates += 1;
+            } else {
+                (void)hipGetLastError();   // the refused update leaves no error behind
+                drop_graph(b);
+            }
+        }
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->graph = graph;
+        if (!updated) {
+            if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+                drop_graph(b);
+                return SCG_EDEVICE;
+            }
+            b->stats.graph_builds += 1;
+        }
+    } else {
+        drop_graph(b);
     }
     b->stats.groups = (int32_t)(b->gf.size() + b->gd.size());
     b->dirty = false;

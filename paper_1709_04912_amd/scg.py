@@ -324,7 +324,7 @@ class Plan:
 
 class scg_batch_stats(C.Structure):
     _fields_ = [("active", C.c_int32), ("slots", C.c_int32), ("groups", C.c_int32),
-                ("reserved", C.c_int32), ("arena_bytes", C.c_uint64),
+                ("graph_updates", C.c_int32), ("arena_bytes", C.c_uint64),
                 ("arena_used", C.c_uint64), ("submitted", C.c_uint64),
                 ("retired", C.c_uint64), ("macro_steps", C.c_uint64),
                 ("graph_builds", C.c_uint64)]

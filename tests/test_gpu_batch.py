@@ -145,7 +145,8 @@ def test_continuous_admission(scg, torch_mod, oracle_lib):
     items = _prepared(scg, torch, oracle_lib, CASES)
     alone = _alone(items)
     got, stats = _run_batch(scg, items, graph=True, max_slots=3, iters=2)
-    assert stats["submitted"] == len(items) and stats["graph_builds"] >= 3
+    assert stats["submitted"] == len(items)
+    assert stats["graph_builds"] >= 1 and stats["graph_builds"] + stats["graph_updates"] >= 3
     for i, (x, rep) in enumerate(alone):
         xb, rb = got[i]
         assert _same(rep, rb) and torch.equal(x, xb), CASES[i]
