@@ -217,11 +217,13 @@ int scg_plan_get_tuning(const scg_plan *plan, int prec, scg_tuning *out);
  * SCG_EINVAL for values other than the ones listed above. */
 int scg_plan_set_tuning(scg_plan *plan, int prec, const scg_tuning *in);
 
-/* Times A and A^T once per candidate shape on the plan's geometry (ones as
- * input, HIP events on `stream`, 5 launches each after one untimed launch),
- * keeps the fastest for precision prec and writes it to *chosen (may be
- * NULL). Allocates and frees one image and one sinogram of scratch;
- * synchronises the stream. */
+/* Times A and A^T for every candidate shape on the plan's geometry (ones as
+ * input, HIP events on `stream`): after a warm-up, each candidate is timed
+ * in two rounds of 10 launches and keeps its faster mean. The swizzle flag,
+ * shared by both operators, is the one whose best projector and best
+ * backprojector times sum lowest; the fastest shapes under it are kept for
+ * precision prec and written to *chosen (may be NULL). Allocates and frees
+ * one image and one sinogram of scratch; synchronises the stream. */
 int scg_plan_autotune(scg_plan *plan, int prec, void *stream, scg_tuning *chosen);
 
 /* ---- kernel timing ----------------------------------------------------- */

@@ -362,42 +362,60 @@ int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
     scg::launch_fill<T>(y, G.sino_elems(), T(1), s);
     T *xs = static_cast<T *>(plan->xs[pi]);
     scg::launch_stage<T>(x, xs, G, s);
-    constexpr int kReps = 5;
+    // Each candidate is timed twice, in two rounds over all candidates, and
+    // keeps its faster time; a warm-up before the first round brings the
+    // clocks up, so the candidates timed first are not penalised.
+    constexpr int kReps = 10;
+    constexpr int kRounds = 2;
     scg_tuning best = plan->tune[pi];
-    float best_pj = -1.0f, best_bp = -1.0f;
-    int best_pj_swz = 0, best_bp_swz = 0;
+    struct PjCand { int ga, nq, swz; float ms; };
+    struct BpCand { int sp, swz; float ms; };
+    std::vector<PjCand> pj;
+    std::vector<BpCand> bp;
     for (int ga : {8, 4})
         for (int nq : {2, 4})
-            for (int swz : {0, 1}) {
-                const ProjTables &P = plan->ptab[ga == 8 ? 0 : 1];
-                const float ms = time_launches(
-                    [&] {
-                        scg::launch_project<T>(x, xs, G, P, y, G.rs, scg::kSinoPadL, nq, swz, s);
-                    },
-                    s, kReps);
-                if (ms > 0.0f && (best_pj < 0.0f || ms < best_pj)) {
-                    best_pj = ms;
-                    best.project_groups = nq;
-                    best.project_angles = ga;
-                    best_pj_swz = swz;
-                }
-            }
+            for (int swz : {0, 1}) pj.push_back({ga, nq, swz, -1.0f});
     for (int sp : {1, 2, 4})
-        for (int swz : {0, 1}) {
-            const float ms = time_launches(
-                [&] { scg::launch_backproject<T>(y, G, plan->bang, x, sp, swz, s); }, s, kReps);
-            if (ms > 0.0f && (best_bp < 0.0f || ms < best_bp)) {
-                best_bp = ms;
-                best.backproject_split = sp;
-                best_bp_swz = swz;
-            }
+        for (int swz : {0, 1}) bp.push_back({sp, swz, -1.0f});
+    auto run_pj = [&](const PjCand &c) {
+        scg::launch_project<T>(x, xs, G, plan->ptab[c.ga == 8 ? 0 : 1], y, G.rs, scg::kSinoPadL,
+                               c.nq, c.swz, s);
+    };
+    auto run_bp = [&](const BpCand &c) {
+        scg::launch_backproject<T>(y, G, plan->bang, plan->border, x, c.sp, c.swz, s);
+    };
+    (void)time_launches([&] { run_pj(pj.front()); run_bp(bp.front()); }, s, 2 * kReps);
+    auto keep = [](float &acc, float ms) {
+        if (ms > 0.0f && (acc < 0.0f || ms < acc)) acc = ms;
+    };
+    for (int round = 0; round < kRounds; ++round) {
+        for (auto &c : pj) keep(c.ms, time_launches([&] { run_pj(c); }, s, kReps));
+        for (auto &c : bp) keep(c.ms, time_launches([&] { run_bp(c); }, s, kReps));
+    }
+    // one swizzle flag serves both operators, and a step applies each as
+    // often as the other: the flag with the smaller sum of the two best times
+    float best_sum = -1.0f;
+    for (int swz : {0, 1}) {
+        const PjCand *bpj = nullptr;
+        const BpCand *bbp = nullptr;
+        for (const auto &c : pj)
+            if (c.swz == swz && c.ms > 0.0f && (bpj == nullptr || c.ms < bpj->ms)) bpj = &c;
+        for (const auto &c : bp)
+            if (c.swz == swz && c.ms > 0.0f && (bbp == nullptr || c.ms < bbp->ms)) bbp = &c;
+        if (bpj == nullptr || bbp == nullptr) continue;
+        const float sum = bpj->ms + bbp->ms;
+        if (best_sum < 0.0f || sum < best_sum) {
+            best_sum = sum;
+            best.project_angles = bpj->ga;
+            best.project_groups = bpj->nq;
+            best.backproject_split = bbp->sp;
+            best.swizzle = swz;
         }
-    // one swizzle flag serves both operators: the one of the dearer operator
-    best.swizzle = best_pj >= best_bp ? best_pj_swz : best_bp_swz;
+    }
     const hipError_t e = hipStreamSynchronize(s);
     (void)hipFree(x);
     (void)hipFree(y);
-    if (e != hipSuccess || best_pj < 0.0f || best_bp < 0.0f) return SCG_EDEVICE;
+    if (e != hipSuccess || best_sum < 0.0f) return SCG_EDEVICE;
     plan->tune[pi] = best;
     if (chosen != nullptr) *chosen = best;
     return SCG_OK;
@@ -611,12 +629,12 @@ int scg_backproject(scg_plan *plan, int prec, const void *y, void *x, void *stre
     if (prec == SCG_F32) {
         float *rp = static_cast<float *>(plan->rpad[0]);
         scg::launch_pad_sino<float>(static_cast<const float *>(y), rp, G, s);
-        scg::launch_backproject<float>(rp, G, plan->bang, static_cast<float *>(x),
+        scg::launch_backproject<float>(rp, G, plan->bang, plan->border, static_cast<float *>(x),
                                        plan->tune[0].backproject_split, plan->tune[0].swizzle, s);
     } else {
         double *rp = static_cast<double *>(plan->rpad[1]);
         scg::launch_pad_sino<double>(static_cast<const double *>(y), rp, G, s);
-        scg::launch_backproject<double>(rp, G, plan->bang, static_cast<double *>(x),
+        scg::launch_backproject<double>(rp, G, plan->bang, plan->border, static_cast<double *>(x),
                                         plan->tune[1].backproject_split, plan->tune[1].swizzle,
                                         s);
     }

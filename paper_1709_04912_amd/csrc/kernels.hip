@@ -422,8 +422,9 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // ---------------------------------------------------------------------------
 // Forward projector A (ray-driven, banded). Block (bin chunk, angle group):
 // NQ groups of kPjBins threads; thread t owns bin b = chunk*kPjBins +
-// (t % kPjBins) for the group's angles (t / kPjBins) + NQ m (each wavefront
-// has one angle per slot). The block walks bands of kPjBand steps along the
+// (t mod 2 kPjBins) / 2 for the group's angles 2 (t / 2 kPjBins) + (t mod 2)
+// + NQ m (each wavefront traces 32 bins of two neighbouring angles, lanes
+// alternating between them). The block walks bands of kPjBand steps along the
 // group's major axis (rows of x, or rows of x^T for angles stepping over
 // columns), staging kPjWin columns of each band in LDS, column-major with a
 // stride of kPjBand + 1 elements (the two split columns of a step are one
@@ -461,8 +462,13 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     const int chunk = vb.x, gi = vb.y;
     const PjGroup grp = gl(P.groups)[gi];
     const auto *pang = gl(P.ang);
-    const int quarter = __builtin_amdgcn_readfirstlane(t / kPjBins);
-    const int b_raw = chunk * kPjBins + (t & (kPjBins - 1));
+    // Each wavefront traces 32 bins of two neighbouring angles, the angles
+    // alternating lane by lane: the rays of a half-wavefront then cross at
+    // most about 24 columns of a row (16 bins at up to sqrt(2) columns
+    // apart), so their paired LDS reads fall in distinct banks; 64 bins of
+    // one angle would span up to 90 columns and collide.
+    const int quarter = 2 * (t / (2 * kPjBins)) + (t & 1);
+    const int b_raw = chunk * kPjBins + ((t & (2 * kPjBins - 1)) >> 1);
     const bool bin_ok = b_raw < G.nb;
     const int b = bin_ok ? b_raw : G.nb - 1;   // idle lanes trace the chunk's last ray
     const int n = G.n;
@@ -483,6 +489,17 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
             const auto &A = pang[grp.a0 + slot];
             u0[m] = fma((double)b, A.u0_step, A.u0_base);
         }
+    }
+
+    // the group's angle parameters, read by every band from LDS (each lane's
+    // angle is its own, so a global load per band would stall the band)
+    __shared__ double s_slope[kPjGroup];
+    __shared__ T s_K[kPjGroup], s_C[kPjGroup];
+    if (t < grp.count) {
+        const auto &A = pang[grp.a0 + t];
+        s_slope[t] = A.slope;
+        s_K[t] = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
+        s_C[t] = sizeof(T) == 4 ? (T)A.Cf : (T)A.C;
     }
 
     // staging loads: one per row, columns outside the image read as zero
@@ -521,13 +538,13 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         for (int m = 0; m < SLOTS; ++m) {
             const int slot = quarter + NQ * m;
             if (slot < grp.count) {
-                const auto &A = pang[grp.a0 + slot];
-                const double us = fma((double)i0, A.slope, u0[m]);
+                const double slope64 = s_slope[slot];
+                const double us = fma((double)i0, slope64, u0[m]);
                 // The band adds exactly zero for a ray whose crossings stay
                 // left of column -1 or right of column n over its rows (both
                 // split columns are zero padding); skip it when that holds
                 // for the whole wavefront.
-                const double ue = fma((double)(kPjBand - 1), A.slope, us);
+                const double ue = fma((double)(kPjBand - 1), slope64, us);
                 const bool miss = fmax(us, ue) < -1.0 || fmin(us, ue) > (double)n;
                 if (__all(miss)) continue;
                 // anchor one column left of the ray's leftmost crossing in the
@@ -538,9 +555,9 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 // adds a 24-bit multiple of the column stride
                 const int cb = ((int)fu - jw) * (LS * (int)sizeof(T));
                 const T F0 = (T)(us - fu);
-                const T slope = (T)A.slope;
-                const T K = sizeof(T) == 4 ? (T)A.Kf : (T)A.K;
-                const T C = sizeof(T) == 4 ? (T)A.Cf : (T)A.C;
+                const T slope = (T)slope64;
+                const T K = s_K[slot];
+                const T C = s_C[slot];
                 // the band's terms are summed apart and then added to the
                 // ray's sum: rounding grows with the band plus the band count,
                 // not with N
@@ -904,28 +921,30 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 template <typename T, int NS>
 __global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__restrict__ r, Geo G,
                                                                   const BpAngle *__restrict__ ang,
+                                                                  const int *__restrict__ border,
                                                                   T *__restrict__ out, int swz)
 {
     const int nt = (G.n + kBpTile - 1) / kBpTile;
+    const int tile = (swz || border == nullptr) ? launch_index(swz) : border[blockIdx.x];
     backproject_body<T, false, NS>(r, nullptr, G, ang, out, nullptr, nullptr, nullptr, 0,
-                                   nullptr, vblk_of(launch_index(swz), nt, nt));
+                                   nullptr, vblk_of(tile, nt, nt));
 }
 
 template <typename T>
-void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, T *out, int split, int swz,
-                        hipStream_t s)
+void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, const int *border, T *out,
+                        int split, int swz, hipStream_t s)
 {
     const int nt = (G.n + kBpTile - 1) / kBpTile;
     dim3 grid(nt * nt);
     if (split >= 4)
-        hipLaunchKernelGGL((k_backproject<T, 4>), grid, dim3(kBpThreads * 4), 0, s, r, G, ang, out,
-                           swz);
+        hipLaunchKernelGGL((k_backproject<T, 4>), grid, dim3(kBpThreads * 4), 0, s, r, G, ang,
+                           border, out, swz);
     else if (split == 2)
-        hipLaunchKernelGGL((k_backproject<T, 2>), grid, dim3(kBpThreads * 2), 0, s, r, G, ang, out,
-                           swz);
+        hipLaunchKernelGGL((k_backproject<T, 2>), grid, dim3(kBpThreads * 2), 0, s, r, G, ang,
+                           border, out, swz);
     else
-        hipLaunchKernelGGL((k_backproject<T, 1>), grid, dim3(kBpThreads), 0, s, r, G, ang, out,
-                           swz);
+        hipLaunchKernelGGL((k_backproject<T, 1>), grid, dim3(kBpThreads), 0, s, r, G, ang, border,
+                           out, swz);
 }
 
 template <typename T, bool DUAL, int NS>
@@ -1959,8 +1978,8 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_project<T>(const T *, const T *, const Geo &, const ProjTables &, T *, \
                                     int, int, int, int, hipStream_t);                           \
     template void launch_pad_sino<T>(const T *, T *, const Geo &, hipStream_t);                \
-    template void launch_backproject<T>(const T *, const Geo &, const BpAngle *, T *, int, int, \
-                                        hipStream_t);                                           \
+    template void launch_backproject<T>(const T *, const Geo &, const BpAngle *, const int *,  \
+                                        T *, int, int, hipStream_t);                            \
     template void launch_tv<T>(const T *, T *, const Geo &, double, double *, double *,        \
                                hipStream_t);                                                    \
     template void launch_filter<T>(const T *, T *, const T *, const Geo &, int, hipStream_t);  \

@@ -215,8 +215,8 @@ void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, 
                     int out_stride, int out_off, int nq, int swz, hipStream_t s);
 template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
 template <typename T>
-void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, T *out, int split, int swz,
-                        hipStream_t s);
+void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, const int *border, T *out,
+                        int split, int swz, hipStream_t s);
 template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
                double *tv_dst, hipStream_t s);   // partials: vec_blocks(n^2) doubles
