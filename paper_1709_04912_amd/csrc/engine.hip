@@ -517,12 +517,12 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
 
     plan->prof_iter = 0;
     enqueue_init(g, st0);
-    // loop: chunks of iterations, the device decides when to stop
+    // loop: chunks of iterations (4, 8, 16, 16, ...) queued behind the
+    // initial step without waiting for it; the device decides when to stop,
+    // and launches queued after the stop return at once
     int done = 0;
     long issued = 0;
-    int chunk = 2;
-    HIP_TRY(hipMemcpyAsync(&done, &h.st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
-    HIP_TRY(hipStreamSynchronize(st0));
+    int chunk = 4;
     while (!done && issued <= (long)pr->max_iter) {
         for (int c = 0; c < chunk; ++c) {
             plan->prof_iter = (int)std::min<long>(issued + c + 1, INT_MAX - 1);
