@@ -150,6 +150,18 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
             if (next[mj] == by_major[mj].size()) mj ^= 1;
             order.push_back(by_major[mj][next[mj]++]);
         }
+        // An XCD deals its blocks to its CUs in turn, so with a plain
+        // heaviest-first sequence the first CU would receive the heaviest
+        // block of every round. Reversing every other round of kXcdCus
+        // blocks (a snake) pairs heavy with light on each CU.
+        for (int x = 0; x < scg::kXcds; ++x) {
+            std::vector<int> pos;
+            for (int p0 = x; p0 < nblk; p0 += scg::kXcds) pos.push_back(p0);
+            for (size_t r0 = scg::kXcdCus; r0 < pos.size(); r0 += 2 * scg::kXcdCus) {
+                const size_t r1 = std::min(pos.size(), r0 + scg::kXcdCus);
+                for (size_t a = r0, b = r1 - 1; a < b; ++a, --b) std::swap(order[pos[a]], order[pos[b]]);
+            }
+        }
         if (hipMalloc(&p->pgroups[ti], groups.size() * sizeof(PjGroup)) != hipSuccess ||
             hipMalloc(&p->pwin[ti], win.size() * sizeof(int)) != hipSuccess ||
             hipMalloc(&p->porder[ti], order.size() * sizeof(int)) != hipSuccess)

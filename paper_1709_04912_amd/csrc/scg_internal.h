@@ -24,6 +24,7 @@ constexpr int kWinSkip = -0x40000000;
 // XCDs (chiplets, each with its own L2); the hardware hands workgroup b of a
 // launch to XCD b mod kXcds.
 constexpr int kXcds = 8;
+constexpr int kXcdCus = 32;       // compute units per XCD
 // Backprojector tiling: 16 x 16 pixel tiles, groups of 128 threads (two
 // adjacent pixels each; 1, 2 or 4 groups per tile split the angles), angles
 // staged in LDS in chunks of kBpChunk with a window of kBpWin bins per angle
