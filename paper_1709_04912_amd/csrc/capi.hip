@@ -476,7 +476,9 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     if (out == nullptr) return SCG_EINVAL;
     *out = nullptr;
     if (g == nullptr || g->n < 2 || g->n_angles < 1 || g->n_bins < 1) return SCG_EINVAL;
-    if (g->n > 16384 || g->n_angles > 65536 || g->n_bins > 65536) return SCG_EINVAL;
+    // the largest image the parity tests cover (the block partials of every
+    // reduction fit the partials buffer well beyond it)
+    if (g->n > scg::kMaxN || g->n_angles > 65536 || g->n_bins > 65536) return SCG_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SCG_EDEVICE;
     scg::Device dg(device);

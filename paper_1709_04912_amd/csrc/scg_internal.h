@@ -43,6 +43,7 @@ constexpr int kTrialsPerPass = 16;   // TV trials evaluated per chunk of perturb
 constexpr int kMaxTrials = 1024;     // cap on max_trials
 constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPass;
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
+constexpr int kMaxN = 2880;          // largest accepted image side
 
 struct Geo {
     int n, na, nb;

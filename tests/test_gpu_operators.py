@@ -218,8 +218,7 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
 
 
 def test_size_limits(scg, torch_mod, oracle_lib):
-    """The largest accepted image (N = 2880: the TV pass's block partials
-    fill the partials buffer) with a detector of 4076 bins, on sampled rays
+    """The largest accepted image (N = 2880) with a detector of 4076 bins, on sampled rays
     and pixels against the oracle; one pixel more is rejected, and the
     filter (only) rejects more than 2730 bins."""
     torch = torch_mod
