@@ -158,15 +158,18 @@ def mixed_runs(n_serve, shape):
     log("batched run: generating 64 solves")
     reqs = build([make_batch_item(i) for i in range(64)])
     warm(reqs)
-    # each way twice, the faster run kept: the first run of a way can still
-    # pay one-time costs (graph capture of a new composition, allocator growth)
-    def best(runs):
-        return min(runs, key=lambda r: r.wall_s)
-    b = best([serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4,
-                                  keep_outputs=True) for _ in range(2)])
-    be = best([serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, graph=False,
-                                   keep_outputs=True) for _ in range(2)])
-    p = best([serve.serve_plain(reqs, keep_outputs=True) for _ in range(2)])
+    # each way twice, the ways alternating and the faster run of each kept:
+    # a first run can still pay one-time costs (graph capture of a new
+    # composition), and alternating keeps clock drift from favouring one way
+    runs = {"graph": [], "eager": [], "plain": []}
+    for _ in range(2):
+        runs["graph"].append(serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4,
+                                                 keep_outputs=True))
+        runs["eager"].append(serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4,
+                                                 graph=False, keep_outputs=True))
+        runs["plain"].append(serve.serve_plain(reqs, keep_outputs=True))
+    b, be, p = (min(runs[k], key=lambda r: r.wall_s) for k in ("graph", "eager", "plain"))
+    runs.clear()
     batched = {
         "workload": "64 S-CG solves, N in {128,256,384,512}, angles in {180,360,540,720}, "
                     "bins ceil(sqrt(2)N)+1, sigma U[0.5%,3%], eps = f(x_true)",
