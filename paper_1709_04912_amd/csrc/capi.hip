@@ -497,7 +497,8 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     // up).
     if ((size_t)scg::blocks_bp(G) > (size_t)scg::kMaxPartials ||
         2 * (size_t)scg::blocks_xtv(G) > (size_t)scg::kMaxPartials ||
-        (size_t)scg::blocks_t32(G) + scg::blocks_sv(G) > (size_t)scg::kMaxPartials) {
+        (size_t)scg::blocks_t32(G) + scg::blocks_sv(G) > (size_t)scg::kMaxPartials ||
+        scg::blocks_t32(G) > scg::kMaxT32Blocks) {
         delete p;
         return SCG_EINVAL;
     }

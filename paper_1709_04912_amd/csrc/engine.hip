@@ -32,7 +32,8 @@ namespace {
 
 // Workspace layout of one solve.
 struct Layout {
-    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, partials2, state, forced, trace, tv,
+    size_t x, xh, p, g, h, s, z, r, q, rt, xs, pt, partials, partials2, partials3, state, forced,
+        trace, tv,
         gtab, desc, total;
 };
 
@@ -60,6 +61,7 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
     L.pt = take(G.staged_elems() * esz);
     L.partials = take(kMaxPartials * sizeof(double));
     L.partials2 = take(kMaxPartials * sizeof(double));
+    L.partials3 = take(kMaxT32Blocks * sizeof(double));
     L.state = take(sizeof(DevState));
     L.forced = take((size_t)2 * (max_iter + 1) * sizeof(int32_t));
     L.trace = take((size_t)(max_iter + 1) * sizeof(scg_trace_entry));
@@ -147,11 +149,17 @@ template <typename T> struct Enq {
     }
     void p_update(int rule, int init) const
     {
+        // S-CG, S-CG-CD, S-PCG after the initial step: the update records beta
+        // itself and the next TV pass's finisher records g'^T p', so no
+        // finisher of its own follows
+        const bool rec = !init && rule <= 2 &&
+                         (g.variant == SCG_S_CG || g.variant == SCG_S_CG_CD ||
+                          g.variant == SCG_S_PCG);
         {
             Prof t(g.prof, SCG_KC_VECTOR, s);
-            launch_b_p_update<T>(g.S, m(kKT32), n(kKT32), rule, init, s);
+            launch_b_p_update<T>(g.S, m(kKT32), n(kKT32), rule, init, rec ? 1 : 0, s);
         }
-        finish(kFinPUpdate, rule, init);
+        if (!rec) finish(kFinPUpdate, rule, init);
     }
     void pq_update() const
     {
@@ -412,6 +420,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.xout = static_cast<T *>(xout_);
     h.partials = reinterpret_cast<double *>(ws + L.partials);
     h.partials2 = reinterpret_cast<double *>(ws + L.partials2);
+    h.partials3 = reinterpret_cast<double *>(ws + L.partials3);
     h.gtab = reinterpret_cast<double *>(ws + L.gtab);
     h.tvd = reinterpret_cast<double *>(ws + L.tv);
     h.st = reinterpret_cast<DevState *>(ws + L.state);

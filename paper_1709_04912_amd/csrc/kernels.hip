@@ -1177,10 +1177,14 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const auto *st = gl(d.st);
-    // alpha of the open step: from the projection's partials (recorded by
-    // this pass's finisher) or from the state
+    // alpha of the open step: from the direction update's and the
+    // projection's partials (recorded by this pass's finisher) or from the
+    // state
     double alpha = st->alpha;
-    if (local_alpha(st->variant) && st->open) alpha = -st->gp / block_sum1(d.partials, d.nb_pj);
+    if (local_alpha(st->variant) && st->open) {
+        const double gp = block_sum1(d.partials3, d.nb_t32);
+        alpha = -gp / block_sum1(d.partials, d.nb_pj);
+    }
     xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
 }
@@ -1390,29 +1394,39 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
 
 template <typename T>
 __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkMap *map,
-                                                    int rule, int init)
+                                                    int rule, int init, int rec)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
-    const auto *st = gl(d.st);
-    // beta of rules 0-2 from the backprojection's dot partials (recorded by
-    // this update's finisher), of the others from the state
+    auto *st = gl(d.st);
+    // beta of rules 0-2 from the backprojection's dot partials, of the
+    // others from the state
     double beta = beta_of(st, rule, init);
     if (!init && rule <= 2) {
         const double dot = block_sum1(d.partials, d.nb_bp);
         beta = rule == 1 ? -dot / st->gp_prev : dot / st->qq_prev;
+        // rec: no finisher follows; the solve's first block records the dot
+        // and beta (fields the other blocks do not read), and g'^T p' is
+        // recorded by the finisher of the TV pass that forms alpha from it
+        if (rec && m.local == 0 && threadIdx.x == 0) {
+            if (rule == 1) st->gg = dot;
+            else st->gh = dot;
+            st->beta = beta;
+            if (!isfinite(beta)) set_done(st, SCG_ENAN);
+            if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
+        }
     }
-    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials2, rule, init, beta,
+    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init, beta,
                   vblk_of(m.local, nt, nt));
 }
 
 template <typename T>
 void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
-                       hipStream_t s)
+                       int rec, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init);
+    hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init, rec);
 }
 
 // S-CG with three operators: q' = -u + beta q over sinogram row a (u = A g'
@@ -1708,7 +1722,7 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         // arg0 = rule, arg1 = init. g'^T p' from the update's partials; for
         // rules 0-2 after the initial step also the backprojection's dot
         // (g'^T h or ||g'||^2), which the update formed its beta from
-        const double gp = block_sum1(d.partials2, d.nb_t32);
+        const double gp = block_sum1(d.partials3, d.nb_t32);
         const bool fused = !arg1 && arg0 <= 2;
         const double dot = fused ? block_sum1(d.partials, d.nb_bp) : 0.0;
         if (threadIdx.x != 0) return;   // the block's other threads are done
@@ -1831,9 +1845,11 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         final_sums(d.partials2, d.nb_xtv, 2, 2, tot);
         const bool qa = local_alpha(st->variant) && st->open;
         const double qq = qa ? block_sum1(d.partials, d.nb_pj) : 0.0;
+        const double gp = qa ? block_sum1(d.partials3, d.nb_t32) : 0.0;
         if (threadIdx.x == 0 && qa) {
             st->qq = qq;
-            if (!isfinite(qq)) {
+            st->gp = gp;
+            if (!isfinite(qq) || !isfinite(gp)) {
                 set_done(st, SCG_ENAN);
             } else if (qq == 0.0) {
                 set_done(st, SCG_EBREAKDOWN);
@@ -1991,7 +2007,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);         \
     template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
     template void launch_b_perturb<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);     \
-    template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int,        \
+    template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int, int,   \
                                        hipStream_t);                                            \
     template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
     template void launch_b_pq_update<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);   \

@@ -44,6 +44,7 @@ constexpr int kMaxTrials = 1024;     // cap on max_trials
 constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPass;
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
 constexpr int kMaxN = 2880;          // largest accepted image side
+constexpr int kMaxT32Blocks = 8192;  // 32 x 32 image tiles (direction update blocks)
 
 struct Geo {
     int n, na, nb;
@@ -130,8 +131,10 @@ template <typename T> struct Solve {
     T *xs, *pt;                 // transposes of x_{k+1/2} (x, or g') and of p
     T *xout;                    // caller's output image
     double *partials;           // block partial sums of the last reduction
-    double *partials2;          // partial sums of the TV pass and the direction
-                                // update (they read the other region's sums)
+    double *partials2;          // partial sums of the TV pass (it reads the other
+                                // region's sums)
+    double *partials3;          // partials of g'^T p' of the direction update,
+                                // read by the TV pass that forms alpha
     double *gtab;               // gamma0 a^(l+m), m < max_trials
     double *tvd;                // TV of the output
     DevState *st;
@@ -245,7 +248,7 @@ template <typename T>
 void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 template <typename T>
 void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
-                       hipStream_t s);
+                       int rec, hipStream_t s);
 template <typename T>
 void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 // p' = -g' + beta p (blocks [0, nb_t32)) and q' = -u + beta q (the next
