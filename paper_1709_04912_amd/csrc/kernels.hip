@@ -133,6 +133,32 @@ __device__ void block_store(const A (&v)[NV], double *dst)
     __syncthreads();
 }
 
+// Block sums of NV values of a kBlock-thread block into dst[k] for
+// first <= k < NV, through LDS: one row per value, eight lanes per row, each
+// lane summing a fixed stride-8 subset in order and a three-step butterfly
+// joining the eight (many values cost a few LDS passes instead of a shuffle
+// tree each). Every thread of the block must call this.
+template <int NV, typename A>
+__device__ void block_store_rows(const A (&v)[NV], double *dst, int first)
+{
+    static_assert(NV * 8 <= kBlock, "eight lanes per value");
+    constexpr int S = kBlock + 8;   // row stride: the next row's lanes start 8 banks on
+    __shared__ A sh[NV * S];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * S + threadIdx.x] = v[k];
+    __syncthreads();
+    const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
+    double acc = 0.0;
+    if (k < NV) {
+        for (int i = 0; i < kBlock / 8; ++i) acc += (double)sh[k * S + p + 8 * i];
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    if (k < NV && k >= first && p == 0) gl(dst)[k] = acc;
+    __syncthreads();
+}
+
 // tot[k] = sum over blocks b of partials[b * stride + k], k < nv: lane-strided
 // runs, then a fixed butterfly; one wave per value so that all loads are in
 // flight together. tot is in shared memory and valid in every thread after.
@@ -1246,15 +1272,13 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
                 acc[m] += tv_term(zd - zc, zr - zc, k2);
             }
         }
-        double *dst = partials + (size_t)bid * stride;
-        if (c == 0) {
-            T tvx[1] = {acc[M]};
-            block_store(tvx, dst);
-        }
-        T tr[M];
+        // [TV(x) (first chunk only), the chunk's trials] at dst + M c
+        double *dst = partials + (size_t)bid * stride + M * c;
+        T vals[M + 1];
+        vals[0] = acc[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) tr[m] = acc[m];
-        block_store(tr, dst + 1 + M * c);
+        for (int m = 0; m < M; ++m) vals[1 + m] = acc[m];
+        block_store_rows(vals, dst, c == 0 ? 0 : 1);
     }
 }
 
