@@ -1954,7 +1954,7 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
+__device__ void finish_body(const Solve<T> *S, int fin, int arg0, int arg1)
 {
     const Solve<T> d = load_solve(S, blockIdx.x);
     __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
@@ -1987,9 +1987,29 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
+{
+    finish_body(S, fin, arg0, arg1);
+}
+
+// The trials' finisher sums 17 values (or more) per block of the trial
+// launch, one wavefront per value: 16 wavefronts take them in two rounds
+// instead of five. Only the trial case runs here (its sums are
+// width-generic; the single-value block sums of the other cases assume
+// kBlock threads).
+template <typename T>
+__global__ __launch_bounds__(1024) void kb_finish_wide(const Solve<T> *S, int arg0, int arg1)
+{
+    finish_body(S, kFinTrials, arg0, arg1);
+}
+
+template <typename T>
 void launch_finish(const Solve<T> *S, int ns, int fin, int arg0, int arg1, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_finish<T>, dim3(ns), dim3(kBlock), 0, s, S, fin, arg0, arg1);
+    if (fin == kFinTrials)
+        hipLaunchKernelGGL(kb_finish_wide<T>, dim3(ns), dim3(1024), 0, s, S, arg0, arg1);
+    else
+        hipLaunchKernelGGL(kb_finish<T>, dim3(ns), dim3(kBlock), 0, s, S, fin, arg0, arg1);
 }
 
 // Copies every solve's state and output TV into compact arrays for one
