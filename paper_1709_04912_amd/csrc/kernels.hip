@@ -198,7 +198,7 @@ __device__ double block_sum1(const double *partials, int nblk)
 {
     __shared__ double wsum[kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int U = 4;
+    constexpr int U = 8;
     const auto *pg = gl(partials);
     double acc = 0.0;
     for (int b0 = threadIdx.x; b0 < nblk; b0 += kBlock * U) {
@@ -220,6 +220,49 @@ __device__ double block_sum1(const double *partials, int nblk)
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
     return t;
+}
+
+// block_sum1 of two arrays with the loads of both in flight together; each
+// result has the bits block_sum1 gives for its array.
+__device__ void block_sum2(const double *pa, int na, const double *pb, int nb, double &sa,
+                           double &sb)
+{
+    __shared__ double wsum[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int U = 8;
+    const auto *ga = gl(pa);
+    const auto *gb = gl(pb);
+    const int n = na > nb ? na : nb;
+    double acc_a = 0.0, acc_b = 0.0;
+    for (int b0 = threadIdx.x; b0 < n; b0 += kBlock * U) {
+        double va[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + kBlock * u;
+            va[u] = b < na ? ga[b] : 0.0;
+            vb[u] = b < nb ? gb[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + kBlock * u < na) acc_a += va[u];
+            if (b0 + kBlock * u < nb) acc_b += vb[u];
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    __syncthreads();   // a previous call's readers are done with wsum
+    if (lane == 0) {
+        wsum[0][wid] = acc_a;
+        wsum[1][wid] = acc_b;
+    }
+    __syncthreads();
+    sa = 0.0;
+    sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        sa += wsum[0][w];
+        sb += wsum[1][w];
+    }
 }
 
 // Variants whose step size alpha = -g'^T p' / ||A p'||^2 is formed by the TV
@@ -1208,8 +1251,9 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     // state
     double alpha = st->alpha;
     if (local_alpha(st->variant) && st->open) {
-        const double gp = block_sum1(d.partials3, d.nb_t32);
-        alpha = -gp / block_sum1(d.partials, d.nb_pj);
+        double gp, qq;
+        block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
+        alpha = -gp / qq;
     }
     xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
@@ -1868,8 +1912,8 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         if (threadIdx.x == 0) s_go = 0;
         final_sums(d.partials2, d.nb_xtv, 2, 2, tot);
         const bool qa = local_alpha(st->variant) && st->open;
-        const double qq = qa ? block_sum1(d.partials, d.nb_pj) : 0.0;
-        const double gp = qa ? block_sum1(d.partials3, d.nb_t32) : 0.0;
+        double qq = 0.0, gp = 0.0;
+        if (qa) block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
         if (threadIdx.x == 0 && qa) {
             st->qq = qq;
             st->gp = gp;
