@@ -350,6 +350,7 @@ def main():
                      "tail_avg_us": (1e3 * v[3] / v[2]) if v[2] else 0.0}
                  for c, v in prof_all.items()}
     compulsory = 4 * (N * N + N_ANGLES * N_BINS)
+    traffic = measured_traffic("kb_" + dominant)
 
     result = {
         "metric": "S-CG recons/s at 512x512 (720 angles x 729 bins)",
@@ -382,11 +383,18 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": measured_traffic("kb_" + dominant),
+            "traffic": traffic,
+            # the three bandwidth readings of a matrix-free operator: its
+            # counted HBM bytes (null when the counters are stale), the
+            # compulsory bytes, and what an explicit sparse matrix (value and
+            # column index per nonzero) would have to stream in the same time
             "per_launch": {"nnz": nnz, "ops_per_nnz": OPS_PER_NNZ, "avg_us": avg_s * 1e6,
                            "launches": int(launches), "tail_launches": int(tail_launches),
+                           "measured_hbm_GBs": (traffic / avg_s / 1e9) if traffic else None,
+                           "measured_hbm_frac": (traffic / avg_s / PEAK_HBM) if traffic else None,
                            "compulsory_hbm_GBs": compulsory / avg_s / 1e9,
-                           "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM},
+                           "compulsory_hbm_frac": compulsory / avg_s / PEAK_HBM,
+                           "sparse_equivalent_GBs": (8 * nnz + compulsory) / avg_s / 1e9},
         },
     }
     result["three_operator"] = three_operator_run(plan, y, params, out, ws, stream, w, args.steps)
