@@ -299,11 +299,10 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
     }
     e.finish(kFinTrials, 0);
     if (g.any_trB) {
-        {
-            Prof t(g.prof, SCG_KC_TRIALS, s);
-            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
-        }
-        e.finish(kFinTrials, kTrialsPerPass);
+        // the second trial launch (it runs only where the first accepted no
+        // step) applies its own trial decision in its last block
+        Prof t(g.prof, SCG_KC_TRIALS, s);
+        launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
     }
     {
         Prof t(g.prof, SCG_KC_VECTOR, s);

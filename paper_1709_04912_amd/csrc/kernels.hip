@@ -1277,6 +1277,9 @@ void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t
 // ---------------------------------------------------------------------------
 
 template <typename T>
+__device__ void finish_body(const Solve<T> *S, int solve, int fin, int arg0, int arg1);
+
+template <typename T>
 __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, const Geo &G,
                             const double *__restrict__ gtab_, double *partials,
                             const DevState *st_, int first_m, int nchunks, VBlk vb)
@@ -1334,9 +1337,28 @@ __global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap
     const Solve<T> d = load_solve(S, m.solve);
     if (gl(d.st)->done || gl(d.st)->search_done) return;
     const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
+    if (nchunks <= 0) return;
     const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
     trials_body(d.x, d.s, d.G, d.gtab, d.partials, d.st, first_m, nchunks,
                 vblk_of(m.local, nblk, 1));
+    if (first_m == 0) return;
+    // The second launch, which runs only after the first one found no
+    // acceptable step, decides its own trials: the last of the solve's blocks
+    // to store its sums (an arrival count, with fences that publish every
+    // block's sums before its arrival and make them visible to the last
+    // block after it) applies the finisher's trial logic. A step whose first
+    // launch accepted returns above, so it pays neither a finisher launch
+    // nor any fence here.
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int arrived = atomicAdd(&d.st->trB_arrived, 1);
+        s_last = arrived == nblk - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    finish_body(S, m.solve, kFinTrials, first_m, 0);
 }
 
 template <typename T>
@@ -1868,6 +1890,7 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         final_sums(d.partials, nblk, stride, stride, tot);
         if (threadIdx.x != 0) return;   // the block's other threads are done
         const bool with_tvx = first_m == 0;
+        if (!with_tvx) st->trB_arrived = 0;   // ready for the next step's launch
         const double tvx = with_tvx ? tot[0] : st->tv_x;
         if (with_tvx) st->tv_x = tvx;
         const int left = st->max_trials - first_m;
@@ -1998,9 +2021,9 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
 }
 
 template <typename T>
-__device__ void finish_body(const Solve<T> *S, int fin, int arg0, int arg1)
+__device__ void finish_body(const Solve<T> *S, int solve, int fin, int arg0, int arg1)
 {
-    const Solve<T> d = load_solve(S, blockIdx.x);
+    const Solve<T> d = load_solve(S, solve);
     __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
     __shared__ int s_go, s_ell;
     __shared__ DevState sst;
@@ -2033,7 +2056,7 @@ __device__ void finish_body(const Solve<T> *S, int fin, int arg0, int arg1)
 template <typename T>
 __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int arg0, int arg1)
 {
-    finish_body(S, fin, arg0, arg1);
+    finish_body(S, (int)blockIdx.x, fin, arg0, arg1);
 }
 
 // The trials' finisher sums 17 values (or more) per block of the trial
@@ -2044,7 +2067,7 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
 template <typename T>
 __global__ __launch_bounds__(1024) void kb_finish_wide(const Solve<T> *S, int arg0, int arg1)
 {
-    finish_body(S, kFinTrials, arg0, arg1);
+    finish_body(S, (int)blockIdx.x, kFinTrials, arg0, arg1);
 }
 
 template <typename T>

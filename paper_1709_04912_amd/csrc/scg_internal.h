@@ -104,7 +104,8 @@ struct DevState {
     int k, steps, done, status;
     // perturbation
     int ell, trials_step, accepted, search_done;
-    int trials_total, forced_len, trace_cap, pad0;
+    int trials_total, forced_len, trace_cap;
+    int trB_arrived;   // blocks of the second trial launch that have stored their sums
     double tv_x, s_norm2, inv_snorm, gamma;
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
