@@ -521,7 +521,9 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
               hipMalloc(&p->rpad[0], G.sino_elems() * sizeof(float)) == hipSuccess &&
               hipMalloc(&p->rpad[1], G.sino_elems() * sizeof(double)) == hipSuccess &&
               hipMalloc(&p->partials, scg::kMaxPartials * sizeof(double)) == hipSuccess &&
-              hipMalloc(&p->tvbuf, sizeof(double)) == hipSuccess;
+              hipMalloc(&p->tvbuf, sizeof(double)) == hipSuccess &&
+              hipHostMalloc(&p->host_pinned, scg::kHostPinnedBytes, hipHostMallocDefault) ==
+                  hipSuccess;
     if (!ok) {
         scg_plan_destroy(p);
         return SCG_ENOMEM;
@@ -570,6 +572,7 @@ void scg_plan_destroy(scg_plan *p)
     }
     (void)hipFree(p->partials);
     (void)hipFree(p->tvbuf);
+    if (p->host_pinned) (void)hipHostFree(p->host_pinned);
     scg::prof_drain(p);
     for (hipEvent_t e : p->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->prof_open)

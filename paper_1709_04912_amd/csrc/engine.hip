@@ -527,34 +527,41 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     enqueue_init(g, st0);
     // loop: chunks of iterations (4, 8, 16, 16, ...) queued behind the
     // initial step without waiting for it; the device decides when to stop,
-    // and launches queued after the stop return at once
-    int done = 0;
+    // and launches queued after the stop return at once. The flag and the
+    // final state come back through the plan's pinned host words.
+    static_assert(sizeof(DevState) + 2 * sizeof(double) <= kHostPinnedBytes, "pinned words");
+    auto *done_h = static_cast<volatile int *>(plan->host_pinned);
+    auto *fs_h = reinterpret_cast<DevState *>(static_cast<char *>(plan->host_pinned) + 64);
+    auto *tv_h = reinterpret_cast<double *>(static_cast<char *>(plan->host_pinned) + 64 +
+                                            ((sizeof(DevState) + 7) / 8) * 8);
+    *done_h = 0;
     long issued = 0;
     int chunk = 4;
-    while (!done && issued <= (long)pr->max_iter) {
+    while (!*done_h && issued <= (long)pr->max_iter) {
         for (int c = 0; c < chunk; ++c) {
             plan->prof_iter = (int)std::min<long>(issued + c + 1, INT_MAX - 1);
             enqueue_iteration(g, st0);
         }
         issued += chunk;
         chunk = std::min(chunk * 2, 16);
-        HIP_TRY(hipMemcpyAsync(&done, &h.st->done, sizeof(int), hipMemcpyDeviceToHost, st0));
+        HIP_TRY(hipMemcpyAsync(const_cast<int *>(done_h), &h.st->done, sizeof(int),
+                               hipMemcpyDeviceToHost, st0));
         HIP_TRY(hipStreamSynchronize(st0));
     }
     plan->prof_iter = INT_MAX;
     g.prof = nullptr;
     enqueue_final(g, st0);
 
-    DevState fs{};
-    double tv_out = 0.0;
-    HIP_TRY(hipMemcpyAsync(&fs, h.st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
-    HIP_TRY(hipMemcpyAsync(&tv_out, h.tvd, sizeof(double), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipMemcpyAsync(fs_h, h.st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
+    HIP_TRY(hipMemcpyAsync(tv_h, h.tvd, sizeof(double), hipMemcpyDeviceToHost, st0));
     if (trace_host != nullptr && trace_cap > 0) {
         const int n = std::min<int>(trace_cap, pr->max_iter + 1);
         HIP_TRY(hipMemcpyAsync(trace_host, h.trace, (size_t)n * sizeof(scg_trace_entry),
                                hipMemcpyDeviceToHost, st0));
     }
     HIP_TRY(hipStreamSynchronize(st0));
+    const DevState fs = *fs_h;
+    const double tv_out = *tv_h;
     prof_drain(plan, std::max(fs.steps, 0));
     plan->prof_iter = 0;
     const bool plain_k = unsuperiorized(pr->variant) || restarted(pr->variant);

@@ -29,6 +29,9 @@ struct scg_plan {
     void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision
     double *partials = nullptr;           // standalone TV partials
     double *tvbuf = nullptr;
+    // pinned host words the solver reads its stop flag and final state into
+    // (a read into pinned memory is one DMA, not a staged pageable copy)
+    void *host_pinned = nullptr;
     void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
     scg_tuning tune[2] = {{4, 4, 8, 0}, {4, 2, 8, 0}};  // launch shapes (F32, F64)
     double kern_mu = -1.0;

@@ -45,6 +45,7 @@ constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPa
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
 constexpr int kMaxN = 2880;          // largest accepted image side
 constexpr int kMaxT32Blocks = 8192;  // 32 x 32 image tiles (direction update blocks)
+constexpr size_t kHostPinnedBytes = 4096;   // a plan's pinned host words
 
 struct Geo {
     int n, na, nb;
