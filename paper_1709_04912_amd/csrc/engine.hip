@@ -513,7 +513,12 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
         int rc = ensure_filter(plan, pr->precond_mu);
         if (rc) return rc;
     }
-    Staging<T> stage{};
+    // the state and descriptor images are uploaded from the plan's pinned
+    // host words (a DMA of pinned memory, no staged pageable copy)
+    static_assert(kPinnedStagingOffset + sizeof(Staging<double>) <= kHostPinnedBytes,
+                  "pinned staging");
+    Staging<T> &stage = *new (static_cast<char *>(plan->host_pinned) + kPinnedStagingOffset)
+        Staging<T>{};
     const int cap = trace_host != nullptr ? trace_cap : pr->max_iter + 1;
     const scg_tuning tune = plan->tune[prec_index<T>()];
     int rc = prepare_solve<T>(plan, pr, tune, ws, y, x0, xout, cap, forced_host, forced_len,

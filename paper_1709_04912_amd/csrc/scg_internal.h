@@ -46,6 +46,7 @@ constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks
 constexpr int kMaxN = 2880;          // largest accepted image side
 constexpr int kMaxT32Blocks = 8192;  // 32 x 32 image tiles (direction update blocks)
 constexpr size_t kHostPinnedBytes = 4096;   // a plan's pinned host words
+constexpr size_t kPinnedStagingOffset = 2048;   // where a solve's upload images sit in them
 
 struct Geo {
     int n, na, nb;
