@@ -781,18 +781,27 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 // gs, gs + NS, ... (the groups' sums are added in a fixed order at the end).
 // Angles are processed in chunks of kBpChunk: for each angle the kBpWin bins
 // around the tile centre's projection are staged in LDS, already scaled by
-// 1/m, next to the angle's parameters (cos, sin, the two weight constants and
-// the centre's fractional position); the next chunk is prefetched into
-// registers while the current one is consumed. A pixel's footprint centre is
-// an FP32 offset from the tile centre (it stays in (4, 27) bins), its two
-// bins are two LDS reads and its two weights two clamped FMAs. DUAL
+// 1/m, next to the angle's parameters (cos and the weight constants) and,
+// for each of the tile's 16 rows, the row's part of the footprint position
+// (the centre's fractional position plus the row offset times sin, shared
+// by the 8 threads of a row); the next chunk is prefetched into registers
+// while the current one is consumed. A pixel's footprint centre is an FP32
+// offset from the tile centre (it stays in (4, 27) bins) and takes one FMA
+// per angle, its two bins are two LDS reads and its two weights two clamped
+// FMAs. DUAL
 // backprojects a second sinogram with the same weights (S-PCG: g' and z').
 // With partials given, the block stores its part of a dot product: dot = 1,
 // out (or out2 when DUAL) against dotv; dot = 2, out against itself; dot =
 // 3 (DUAL), out against out2.
 // ---------------------------------------------------------------------------
 
-constexpr int kBpPrm = 8;   // per-angle parameters staged in LDS
+constexpr int kBpPrm = 4;   // per-angle parameters staged in LDS
+// Waves per SIMD the FP32 single-sinogram backprojector is held to (at most
+// 64 VGPRs); the others are left to the compiler.
+template <typename T, bool DUAL> constexpr int kBpWaves = sizeof(T) == 4 && !DUAL ? 8 : 1;
+constexpr int kBpRt = kBpTile / (kBpThreads / kBpChunk);   // row terms per thread
+static_assert(kBpThreads % kBpChunk == 0 && kBpRt * (kBpThreads / kBpChunk) == kBpTile,
+              "the threads of an angle cover the tile's rows");
 
 template <typename T, bool DUAL, int NS>
 __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ r2, const Geo &G,
@@ -803,7 +812,10 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     constexpr int NW = DUAL ? 2 : 1;
     constexpr int NE = kBpChunk * kBpWin / kBpThreads;   // staged bins per thread and sinogram
     __shared__ T win[NS][NW][kBpChunk * kBpWin];
-    __shared__ T prm[NS][kBpChunk * kBpPrm];
+    // angle parameters and row terms, two buffers: the next chunk's are
+    // written while the current chunk's are read
+    __shared__ T prm[2][NS][kBpChunk * kBpPrm];
+    __shared__ T rowt[2][NS][kBpChunk * kBpTile];
     static_assert(NS * NW * kBpChunk * kBpWin >= (NS - 1) * kBpThreads * 2 * NW,
                   "combine buffer fits in the windows");
     const int gs = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBpThreads);
@@ -811,7 +823,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     const int ty = t >> 3, tx = (t & 7) * 2;
     const int i0 = vb.y * kBpTile, j0 = vb.x * kBpTile;
     const double xc = ((double)j0 + 7.5) - G.h, yc = G.h - ((double)i0 + 7.5);
-    const T dx = (T)((double)tx - 7.5), dy = (T)(7.5 - (double)ty);
+    const T dx = (T)((double)tx - 7.5);
     T acc0 = T(0), acc1 = T(0), bcc0 = T(0), bcc1 = T(0);
     const int nchunks = (G.na + kBpChunk - 1) / kBpChunk;
 
@@ -826,31 +838,40 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     const Rsrc sino2 = buf_rsrc(DUAL ? r2 : r, (uint32_t)((size_t)G.na * G.rs * sizeof(T)));
 
     T pre[NW][NE];
-    T ppr[kBpPrm];
-    // FP64 frame of the chunk's angles (threads t < kBpChunk, one angle
-    // each): the per-pixel parameters (kept in registers until the chunk is
-    // staged) and the window reference the staging loads read.
-    auto params = [&](int ch) {
-        if (t < kBpChunk) {
-            const int a = ch * kBpChunk + t;
+    // FP64 frame of the chunk's angles (kBpThreads / kBpChunk threads per
+    // angle, each computing it): the per-pixel parameters and kBpRt of the
+    // row terms, written to LDS buffer `buf`, and the window reference the
+    // staging loads read.
+    auto params = [&](int ch, int buf) {
+        const int al = t * kBpRt / kBpTile, r0 = t * kBpRt % kBpTile;
+        const int a = ch * kBpChunk + al;
+        T pp[kBpPrm], rt[kBpRt];
 #pragma unroll
-            for (int k = 0; k < kBpPrm; ++k) ppr[k] = T(0);
-            WinRef w{0, T(0)};
-            if (a < G.na) {
-                const BpAngle A = gl(ang)[a];
-                const BpW<T> W = bpw<T>(A);
-                const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
-                const double fb = floor(pc) - kBpHalf;
-                ppr[0] = W.c;
-                ppr[1] = W.s;
-                ppr[2] = W.K;
-                ppr[3] = W.C;
-                ppr[4] = W.CK;
-                ppr[5] = (T)(pc - fb);
-                w.base = (int)fb;
-                w.m = (T)A.inv_m;
-            }
-            wref[gs][t] = w;
+        for (int k = 0; k < kBpPrm; ++k) pp[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < kBpRt; ++k) rt[k] = T(0);
+        WinRef w{0, T(0)};
+        if (a < G.na) {
+            const BpAngle A = gl(ang)[a];
+            const BpW<T> W = bpw<T>(A);
+            const double pc = fma(xc, A.c, fma(yc, A.s, G.hb));
+            const double fb = floor(pc) - kBpHalf;
+            const T fr = (T)(pc - fb);
+            pp[0] = W.c;
+            pp[1] = W.K;
+            pp[2] = W.C;
+            pp[3] = W.CK;
+#pragma unroll
+            for (int k = 0; k < kBpRt; ++k) rt[k] = fma((T)(7.5 - (double)(r0 + k)), W.s, fr);
+            w.base = (int)fb;
+            w.m = (T)A.inv_m;
+        }
+#pragma unroll
+        for (int k = 0; k < kBpRt; ++k) rowt[buf][gs][t * kBpRt + k] = rt[k];
+        if (r0 == 0) {
+#pragma unroll
+            for (int k = 0; k < kBpPrm; ++k) prm[buf][gs][al * kBpPrm + k] = pp[k];
+            wref[gs][al] = w;
         }
     };
     // staging loads of a chunk (after a barrier that follows its params):
@@ -872,11 +893,12 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         }
     };
 
-    if (gs < nchunks) params(gs);
+    if (gs < nchunks) params(gs, 0);
     __syncthreads();
     if (gs < nchunks) prefetch(gs);
     for (int c0 = 0; c0 < nchunks; c0 += NS) {
         const int ch = c0 + gs;
+        const int cb = (c0 / NS) & 1;
         const bool live = ch < nchunks;
         __syncthreads();
         if (live) {
@@ -885,14 +907,10 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
                 win[gs][0][t + e * kBpThreads] = pre[0][e];
                 if (DUAL) win[gs][NW - 1][t + e * kBpThreads] = pre[NW - 1][e];
             }
-            if (t < kBpChunk) {
-#pragma unroll
-                for (int k = 0; k < kBpPrm; ++k) prm[gs][t * kBpPrm + k] = ppr[k];
-            }
         }
-        // the previous chunk's window references were read before the
-        // barrier above
-        if (ch + NS < nchunks) params(ch + NS);
+        // the previous chunk's window references and the other buffer's
+        // parameters were read before the barrier above
+        if (ch + NS < nchunks) params(ch + NS, cb ^ 1);
         __syncthreads();
         if (ch + NS < nchunks) prefetch(ch + NS);
         const int na = live ? min(kBpChunk, G.na - ch * kBpChunk) : 0;
@@ -901,9 +919,9 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         T s0 = T(0), s1 = T(0), e0 = T(0), e1 = T(0);
 #pragma unroll 2
         for (int al = 0; al < na; ++al) {
-            const T *pr = &prm[gs][al * kBpPrm];
-            const T c = pr[0], s = pr[1], K = pr[2], C = pr[3], CK = pr[4];
-            const T u0 = fma(dx, c, fma(dy, s, pr[5]));
+            const T *pr = &prm[cb][gs][al * kBpPrm];
+            const T c = pr[0], K = pr[1], C = pr[2], CK = pr[3];
+            const T u0 = fma(dx, c, rowt[cb][gs][al * kBpTile + ty]);
             const T u1 = u0 + c;
             const T *row = &win[gs][0][al * kBpWin];
             const int b0 = (int)u0, b1 = (int)u1;   // u > 0: truncation is floor
@@ -988,7 +1006,8 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 }
 
 template <typename T, int NS>
-__global__ __launch_bounds__(kBpThreads * NS) void k_backproject(const T *__restrict__ r, Geo G,
+__global__ __launch_bounds__(kBpThreads * NS)
+__attribute__((amdgpu_waves_per_eu(kBpWaves<T, false>))) void k_backproject(const T *__restrict__ r, Geo G,
                                                                   const BpAngle *__restrict__ ang,
                                                                   const int *__restrict__ border,
                                                                   T *__restrict__ out, int swz)
@@ -1017,7 +1036,8 @@ void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, const int 
 }
 
 template <typename T, bool DUAL, int NS>
-__global__ __launch_bounds__(kBpThreads * NS) void kb_backproject(const Solve<T> *S,
+__global__ __launch_bounds__(kBpThreads * NS)
+__attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL>))) void kb_backproject(const Solve<T> *S,
                                                                    const BlkMap *map, int phase,
                                                                    int dot, int swz)
 {
