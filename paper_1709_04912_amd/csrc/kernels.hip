@@ -975,7 +975,11 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         }
     }
 
-    const int i = i0 + ty, j = j0 + tx;
+    // the pixel's row and column are formed again from an opaque copy of t:
+    // held across the angle loop they would take a register it lacks
+    int te = t;
+    asm volatile("" : "+v"(te));
+    const int i = i0 + (te >> 3), j = j0 + (te & 7) * 2;
     double dsum = 0.0;
     if (gs == 0 && i < G.n) {
         const size_t p = (size_t)i * G.n + j;
