@@ -105,6 +105,7 @@ class PerturbInfo:
     trials: int          # trials made in this call
     gamma: float         # step used (0 when the point is unperturbed)
     s_norm: float
+    margins: list = field(default_factory=list)   # TV(x + gamma v) - TV(x) per trial
 
 
 def perturbed(g: Geometry, x, ell: int, pp: PerturbParams):
@@ -117,13 +118,16 @@ def perturbed(g: Geometry, x, ell: int, pp: PerturbParams):
     if s_norm == 0.0:
         return x.copy(), ell, PerturbInfo(tv_x, -1, 0, 0.0, 0.0)
     v = -s / s_norm
+    margins = []
     for trial in range(pp.max_trials):
         gamma = pp.gamma0 * pp.a ** ell
         ell += 1
         z = x + gamma * v
-        if g.tv(z, pp.kappa) <= tv_x:
-            return z, ell, PerturbInfo(tv_x, trial, trial + 1, gamma, s_norm)
-    return x.copy(), ell, PerturbInfo(tv_x, -1, pp.max_trials, 0.0, s_norm)
+        tv_z = g.tv(z, pp.kappa)
+        margins.append(tv_z - tv_x)
+        if tv_z <= tv_x:
+            return z, ell, PerturbInfo(tv_x, trial, trial + 1, gamma, s_norm, margins)
+    return x.copy(), ell, PerturbInfo(tv_x, -1, pp.max_trials, 0.0, s_norm, margins)
 
 
 # ---------------------------------------------------------------------------
@@ -264,7 +268,8 @@ def pcg_k(prob: Problem, x0, K: int):
     return x, f0
 
 
-def _s_k(prob: Problem, x0, eps, pp: PerturbParams, K: int, inner, max_iter: int) -> Result:
+def _s_k(prob: Problem, x0, eps, pp: PerturbParams, K: int, inner, max_iter: int,
+         record: bool = False) -> Result:
     """Alg. S-CG-K / S-PCG-K: k = 0, x_{-1/2} = x0; while f(x_{k-1/2}) > eps:
     x_{k+1/2} = perturbed(x_k), x_{k+1} = inner-K(x_{k+1/2}), k = k + 1;
     output x_{k-1/2}."""
@@ -273,7 +278,7 @@ def _s_k(prob: Problem, x0, eps, pp: PerturbParams, K: int, inner, max_iter: int
     f_half = prob.f(x_half)
     k, ell = 0, 0
     status = "ok"
-    trace = []
+    trace, records = [], []
     while f_half > eps:
         if k >= max_iter:
             status = "noconv"
@@ -282,13 +287,17 @@ def _s_k(prob: Problem, x0, eps, pp: PerturbParams, K: int, inner, max_iter: int
         x, f_half = inner(prob, x_half, K)
         k += 1
         trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
-                      "trials": info.trials, "ell": ell, "gamma": info.gamma})
-    return Result(x=x_half, k=k, steps=k, status=status, f_out=f_half, trace=trace, ell=ell)
+                      "trials": info.trials, "ell": ell, "gamma": info.gamma,
+                      "margins": info.margins})
+        if record:
+            records.append({"k": k, "x_half": x_half})
+    return Result(x=x_half, k=k, steps=k, status=status, f_out=f_half, trace=trace,
+                  records=records, ell=ell)
 
 
 def scg_k(prob: Problem, x0, eps: float, pp: PerturbParams, K: int = 2,
-          max_iter: int = 1000) -> Result:
-    return _s_k(prob, x0, eps, pp, K, cg_k, max_iter)
+          max_iter: int = 1000, record: bool = False) -> Result:
+    return _s_k(prob, x0, eps, pp, K, cg_k, max_iter, record)
 
 
 def spcg_k(prob: Problem, x0, eps: float, pp: PerturbParams, K: int = 2,
@@ -354,7 +363,8 @@ def scg(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000,
         x_new = xh + alpha * p_new              # x' = x + alpha p'
         trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
                       "trials": info.trials, "ell": ell, "gamma": info.gamma,
-                      "beta": beta, "alpha": alpha, "gp": gp, "qq": pth_new})
+                      "margins": info.margins, "beta": beta, "alpha": alpha, "gp": gp,
+                      "qq": pth_new})
         if record:
             records.append({"k": k, "x_k": x, "x_half": xh, "g_half": g_new, "p_prev": p,
                             "q_prev": q, "p": p_new, "q": q_new, "x_next": x_new,
@@ -411,14 +421,16 @@ def scg_3op(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 10
         x_new = xh + alpha * p_new
         trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
                       "trials": info.trials, "ell": ell, "gamma": info.gamma,
-                      "beta": beta, "alpha": alpha, "gp": gp, "qq": qq_new})
+                      "margins": info.margins, "beta": beta, "alpha": alpha, "gp": gp,
+                      "qq": qq_new})
         x_half, x, p, q, qq = xh, x_new, p_new, q_new, qq_new
         k += 1
     return Result(x=x_half, k=k, steps=len(trace), status=status, f_out=f_half, trace=trace,
                   ell=ell)
 
 
-def scg_cd(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
+def scg_cd(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000,
+           record: bool = False) -> Result:
     """Alg. S-CG-CD with CG-CD-STEP (beta = -||g'||^2 / g^T p, the
     conjugate-descent rule); the step carries g instead of h."""
     x0 = np.array(x0, dtype=np.float64).reshape(-1)
@@ -434,7 +446,7 @@ def scg_cd(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 100
     alpha = -float(g @ p) / pth
     x = x0 + alpha * p
     k, ell = 1, 0
-    trace = []
+    trace, records = [], []
     status = "ok"
     while f_half > eps:
         if k - 1 >= max_iter:
@@ -459,11 +471,14 @@ def scg_cd(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 100
         x_new = xh + alpha * p_new
         trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
                       "trials": info.trials, "ell": ell, "gamma": info.gamma,
-                      "beta": beta, "alpha": alpha, "gp": gp, "qq": pth_new})
+                      "margins": info.margins, "beta": beta, "alpha": alpha, "gp": gp,
+                      "qq": pth_new})
+        if record:
+            records.append({"k": k, "x_k": x, "x_half": xh, "p": p_new, "x_next": x_new})
         x_half, x, p, g = xh, x_new, p_new, g_new
         k += 1
     return Result(x=x_half, k=k, steps=len(trace), status=status, f_out=f_half, trace=trace,
-                  ell=ell)
+                  records=records, ell=ell)
 
 
 def spcg(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000) -> Result:
@@ -509,7 +524,8 @@ def spcg(prob: Problem, x0, eps: float, pp: PerturbParams, max_iter: int = 1000)
         x_new = xh + alpha * p_new
         trace.append({"k": k, "f_half": f_half, "tv_x": info.tv_x, "accepted": info.accepted,
                       "trials": info.trials, "ell": ell, "gamma": info.gamma,
-                      "beta": beta, "alpha": alpha, "gp": gp, "qq": pth_new})
+                      "margins": info.margins, "beta": beta, "alpha": alpha, "gp": gp,
+                      "qq": pth_new})
         x_half, x, p, h, pth = xh, x_new, p_new, h_new, pth_new
         k += 1
     return Result(x=x_half, k=k, steps=len(trace), status=status, f_out=f_half, trace=trace,
