@@ -58,15 +58,18 @@ def variant_curve(plan, y, x_true, eps, gamma0, variant, prec, k_max, stream):
     for m in range(1, m_end + 1):
         p = plan.params(eps=1e-300, gamma0=gamma0, variant=variant, prec=prec, max_iter=m)
         r, t = _timed_solve(plan, y, p, ws, out, stream)
-        x = out.double()
-        res = plan.project(out).double() - y.double()
-        points.append({"steps": m, "k": r.k, "time_s": t, "f": 0.5 * float((res * res).sum()),
-                       "tv": r.tv_out, "error": _rel(x, x_true)})
+        # the report's f and TV are those of the output the solve returns
+        points.append({"steps": m, "k": r.k, "time_s": t, "f": r.f_out, "tv": r.tv_out,
+                       "error": _rel(out.double(), x_true)})
     return {"variant": variant, "gamma0": gamma0, "stop": stop, "points": points}
 
 
 def run(config: int = 2, seed: int = 0, variants=None, prec: int = scg.SCG_F32,
-        k_max: int = 200, rho_grid=RHO_GRID, device: int = 0) -> dict:
+        k_max: int = 200, rho_grid=RHO_GRID, device: int = 0, eps=None, x1_norm=None,
+        rho=None) -> dict:
+    """eps (default f(x_true)) and x1_norm (default ||x_1|| of the library's
+    first CG iterate) may be given; rho fixes gamma0 = rho ||x_1|| for every
+    superiorized variant instead of the per-variant search."""
     from synth import make_workload
 
     variants = variants or VARIANTS_ALL
@@ -79,11 +82,12 @@ def run(config: int = 2, seed: int = 0, variants=None, prec: int = scg.SCG_F32,
     plan = scg.Plan(w.n, w.n_angles, w.n_bins, device=device)
     if prec == scg.SCG_F32:
         plan.autotune(scg.SCG_F32)
-    res = plan.project(x_true.to(dt)).double() - y.double()
-    eps = 0.5 * float((res * res).sum())            # f(x_true): the stopping value
-    x1, _, _ = plan.solve(y, plan.params(eps=1e-300, gamma0=0.0, variant="CG", prec=prec,
-                                         max_iter=1), trace=False)
-    x1_norm = float(torch.linalg.vector_norm(x1.double()))
+    if eps is None:
+        eps = plan.f(y, x_true.to(dt))              # f(x_true): the stopping value
+    if x1_norm is None:
+        x1, _, _ = plan.solve(y, plan.params(eps=1e-300, gamma0=0.0, variant="CG", prec=prec,
+                                             max_iter=1), trace=False)
+        x1_norm = float(torch.linalg.vector_norm(x1.double()))
     out = {"config": config, "seed": seed, "n": w.n, "n_angles": w.n_angles,
            "n_bins": w.n_bins, "eps": eps, "tv_phantom": plan.tv(x_true.to(dt)),
            "precision": "f32" if prec == scg.SCG_F32 else "f64", "curves": []}
@@ -91,6 +95,8 @@ def run(config: int = 2, seed: int = 0, variants=None, prec: int = scg.SCG_F32,
     for v in variants:
         if v in ("CG", "PCG"):
             gamma0 = 0.0
+        elif rho is not None:
+            gamma0 = rho * x1_norm
         else:
             best = None
             for rho in rho_grid:

@@ -268,6 +268,14 @@ class Plan:
         p.restart_k = int(restart_k)
         return p
 
+    def f(self, y: torch.Tensor, x: torch.Tensor, stream=None) -> float:
+        """f(x) = 1/2 ||y - A x||^2 evaluated by the library: scg_solve of
+        plain CG from x0 = x with max_iter = 0 reports f at its start point
+        (FP64 accumulation)."""
+        p = self.params(eps=1e-300, gamma0=0.0, variant="CG", prec=_prec_of(y), max_iter=0)
+        _, rep, _ = self.solve(y, p, x0=x, trace=False, stream=stream)
+        return rep.f_out
+
     def workspace_bytes(self, params: scg_params) -> int:
         n = C.c_size_t()
         _check(lib.scg_workspace_bytes(self._h, C.byref(params), C.byref(n)),

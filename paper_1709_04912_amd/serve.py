@@ -77,8 +77,7 @@ def make_request(rid: int, cache: PlanCache, y_np: np.ndarray, x_true_np: np.nda
     y = torch.tensor(np.ascontiguousarray(y_np).reshape(-1), dtype=torch.float32, device=dev)
     xt = torch.tensor(np.ascontiguousarray(x_true_np).reshape(-1), dtype=torch.float32,
                       device=dev)
-    res = plan.project(xt).double() - y.double()
-    eps = 0.5 * float((res * res).sum())
+    eps = plan.f(y, xt)
     x1, _, _ = plan.solve(y, plan.params(eps=1e-30, gamma0=0.0, variant="CG", max_iter=1),
                           trace=False)
     gamma0 = rho * float(torch.linalg.vector_norm(x1.double()))

@@ -1,7 +1,9 @@
 """S-CG and S-PCG at 256 x 256 (360 angles, 367 bins, 20 ellipses, 2 %
-Gaussian noise): the FP32 path (FP32 operators, TV and vector updates, FP64
-CG scalars and eps test) against the all-FP64 GPU path, and the FP64 path
-against the FP64 oracle over the first steps.
+Gaussian noise) solved to the stop against the FP64 oracle: the FP64 GPU
+path with identical decisions, stop and image within 1e-8, and the FP32
+path (FP32 operators, TV and vector updates, FP64 CG scalars and eps test)
+within relative L2 1e-4 with the eps test met, its decisions checked
+against the oracle's FP64 margins (tests/parity_c10.py).
 
 eps = 1.05 eps0_hat, eps0_hat an upper bound of the least-squares floor from
 the oracle's CG run to ||g|| <= 1e-10 ||g_0|| (tests/golden/eps.json).
@@ -12,12 +14,15 @@ import os
 import numpy as np
 import pytest
 
+import parity_c10 as c10
 from oracle import algorithms as alg
 from synth import make_workload
 
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+ORACLE = {"S_CG": alg.scg, "S_PCG": alg.spcg}
+_REFS = {}
 
 
 @pytest.fixture(scope="module")
@@ -33,51 +38,58 @@ def case256(oracle_lib):
     gd = json.load(open(os.path.join(HERE, "golden", "eps.json")))["cfg2_s0"]
     w = make_workload(2, 0, supersample=2)
     g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
-    return w, g, 1.05 * gd["eps0"], 0.05 * gd["x1_norm"]
+    return w, g, alg.Problem(g, w.y), 1.05 * gd["eps0"], 0.05 * gd["x1_norm"]
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+def _oracle(case256, variant, max_iter=None):
+    w, g, prob, eps, gamma0 = case256
+    key = (variant, max_iter)
+    if key not in _REFS:
+        print(f"  oracle {variant} 256x256 max_iter={max_iter}", flush=True)
+        _REFS[key] = ORACLE[variant](prob, np.zeros(g.J), eps=eps,
+                                     pp=alg.PerturbParams(gamma0),
+                                     max_iter=400 if max_iter is None else max_iter)
+    return _REFS[key]
 
 
 @pytest.mark.parametrize("variant", ["S_CG", "S_PCG"])
-def test_fp32_against_fp64_gpu(scg, case256, variant):
+def test_fp64_to_the_stop(scg, case256, variant):
     import torch
-    w, g, eps, gamma0 = case256
-    print(f"[256] variant={variant} eps={eps:.6g}", flush=True)
-    y64 = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
-    y32 = y64.float()
-    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        p64 = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
-                          max_iter=400)
-        x64, r64, t64 = plan.solve(y64, p64)
-        forced = [(t["trials"], t["accepted"]) for t in t64]
-        p32 = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
-                          max_iter=400)
-        x32, r32, t32 = plan.solve(y32, p32)
-        if [(t["trials"], t["accepted"]) for t in t32] != forced or r32.k != r64.k:
-            x32, r32, t32 = plan.solve(y32, p32, forced=forced)
-    rel = _rel(x32.double().cpu().numpy(), x64.cpu().numpy())
-    print(f"  fp64: status={r64.status} k={r64.k} f={r64.f_out:.6g}; "
-          f"fp32: status={r32.status} k={r32.k} f={r32.f_out:.6g}; rel={rel:.2e}")
-    assert r64.status in (scg.SCG_OK, scg.SCG_ENOCONV)
-    assert r32.status == r64.status and r32.k == r64.k
-    if r64.status == scg.SCG_OK:
-        assert r64.f_out <= eps and r32.f_out <= eps
-    assert rel <= 1e-4
-
-
-def test_fp64_gpu_against_oracle_first_steps(scg, case256, oracle_lib):
-    """Five S-CG steps at 256 x 256: GPU FP64 against the FP64 oracle."""
-    import torch
-    w, g, eps, gamma0 = case256
-    prob = alg.Problem(g, w.y)
-    ref = alg.scg(prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0), max_iter=5)
+    w, g, prob, eps, gamma0 = case256
+    print(f"[256 fp64] variant={variant} eps={eps:.6g}", flush=True)
+    ref = _oracle(case256, variant)
+    assert ref.status == "ok"
     y64 = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        x, rep, trace = plan.solve(y64, plan.params(eps=eps, gamma0=gamma0, prec=scg.SCG_F64,
-                                                    max_iter=5))
-    assert rep.status == scg.SCG_ENOCONV and ref.status == "noconv"
-    assert [(t["trials"], t["accepted"]) for t in trace] == \
-        [(t["trials"], t["accepted"]) for t in ref.trace]
-    assert _rel(x.cpu().numpy(), ref.x) <= 1e-9
+        x, rep, trace = plan.solve(y64, plan.params(eps=eps, gamma0=gamma0, variant=variant,
+                                                    prec=scg.SCG_F64, max_iter=400))
+    rel = c10.rel_l2(x.cpu().numpy(), ref.x)
+    print(f"  k={rep.k} ref_k={ref.k} rel={rel:.2e}")
+    assert rep.status == scg.SCG_OK and rep.k == ref.k
+    assert c10.decisions(trace) == c10.decisions(ref.trace)
+    assert rep.f_out <= eps and abs(rep.f_out - ref.f_out) <= 1e-9 * ref.f_out
+    assert rel <= 1e-8
+
+
+@pytest.mark.parametrize("variant", ["S_CG", "S_PCG"])
+def test_fp32_to_the_stop(scg, case256, variant):
+    import torch
+    w, g, prob, eps, gamma0 = case256
+    print(f"[256 fp32] variant={variant} eps={eps:.6g}", flush=True)
+    y32 = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        def run_gpu(forced, max_iter):
+            p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
+                            max_iter=400 if max_iter is None else max_iter)
+            x, rep, trace = plan.solve(y32, p, forced=forced)
+            return x.cpu().numpy().astype(np.float64), rep, trace
+
+        xg, rep, ref, kinds = c10.compare(f"256x256 {variant}", run_gpu,
+                                          lambda m: _oracle(case256, variant, m), eps,
+                                          ref=_oracle(case256, variant))
+    rel = c10.rel_l2(xg, ref.x)
+    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e} f={rep.f_out:.8g}")
+    assert rep.k == ref.k and rel <= 1e-4
+    if "stop" not in kinds:
+        assert rep.status == scg.SCG_OK and rep.f_out <= eps
+    assert prob.f(xg) <= eps * (1 + c10.MARGIN)

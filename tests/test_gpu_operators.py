@@ -104,7 +104,8 @@ def test_tv_and_subgradient(scg, torch_mod, oracle_lib, n):
             assert abs(plan.tv(xd, kappa=kappa) - g.tv(x, kappa)) <= 1e-12 * g.tv(x, kappa)
 
 
-@pytest.mark.parametrize("geom", [(16, 5, 7), (64, 90, 95), (32, 3, 129)])
+@pytest.mark.parametrize("geom", [(16, 5, 7), (64, 90, 95), (32, 3, 129), (16, 7, 367),
+                                  (16, 5, 729), (16, 3, 1450)])
 def test_filter(scg, torch_mod, oracle_lib, geom):
     torch = torch_mod
     n, na, nb = geom

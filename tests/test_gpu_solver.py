@@ -4,9 +4,10 @@ FP64 GPU path: same decisions (accepted trial and trial count per step), same
 stopping k, final image within relative L2 1e-8 of the oracle's.
 FP32 operators with FP64 scalars: final image within relative L2 1e-4 with the
 eps test met. The accept test TV(x + gamma v) <= TV(x) and the stop test are
-discontinuous, so FP32 rounding may flip a decision whose FP64 margin is tiny;
-then the GPU replays the oracle's decisions (forced mode) and the comparison is
-made on that run, whose eps test must still hold.
+discontinuous, so FP32 rounding may flip a decision whose FP64 margin is
+within FP32 rounding of its threshold; only then is the GPU replayed with the
+oracle's decisions (forced mode) or taken to the oracle's step count, and the
+case is counted (tests/parity_c10.py). A flip at a larger margin fails.
 """
 import json
 import os
@@ -14,6 +15,7 @@ import os
 import numpy as np
 import pytest
 
+import parity_c10 as c10
 from oracle import algorithms as alg
 from synth import make_workload
 
@@ -97,60 +99,67 @@ def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
     print(f"[solver fp32] variant={variant} seed={seed}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
-    ref = ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0),
-                             max_iter=1000)
+    pp = alg.PerturbParams(gamma0)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32, max_iter=1000)
-        x, rep, trace = plan.solve(y, p)
-        forced = None
-        if _decisions(trace) != [(t["trials"], t["accepted"]) for t in ref.trace] or rep.k != ref.k:
-            forced = [(t["trials"], t["accepted"]) for t in ref.trace]
+        def run_gpu(forced, max_iter):
+            p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
+                            max_iter=1000 if max_iter is None else max_iter)
             x, rep, trace = plan.solve(y, p, forced=forced)
-    xg = x.cpu().numpy().astype(np.float64)
-    print(f"  k={rep.k} ref_k={ref.k} forced={forced is not None} rel={_rel(xg, ref.x):.2e}")
-    assert rep.status == scg.SCG_OK
-    assert rep.f_out <= eps
-    assert prob.f(xg) <= eps * (1 + 1e-5)
-    assert rep.k == ref.k
-    assert _rel(xg, ref.x) <= 1e-4
+            return x.cpu().numpy().astype(np.float64), rep, trace
+
+        def run_oracle(max_iter):
+            return ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=pp,
+                                      max_iter=1000 if max_iter is None else max_iter)
+
+        xg, rep, ref, kinds = c10.compare(f"64x64 {variant} seed {seed}", run_gpu, run_oracle,
+                                          eps)
+    rel = _rel(xg, ref.x)
+    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e}")
+    assert rep.k == ref.k and rel <= 1e-4
+    if "stop" not in kinds:
+        assert rep.status == scg.SCG_OK and ref.status == "ok" and rep.f_out <= eps
+    assert prob.f(xg) <= eps * (1 + c10.MARGIN)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_fp32_parity_scg_k(scg, torch_mod, oracle_lib, seed):
-    """S-CG-K in FP32. CG-K's recursive gradient amplifies rounding across
-    passes, so the image bound is the oracle's own amplification of a
-    relative change of y (measured in FP64) applied to FP32's unit roundoff,
-    times 10, and it is checked after a fixed number of passes with the
-    oracle's decisions replayed (the stop test then cannot differ). Run to
-    the stop, the FP32 solve meets eps within one pass of the oracle's k."""
+    """S-CG-K in FP32 to the stop, decisions checked as for the other
+    variants. CG-K's recursive gradient amplifies rounding across passes, so
+    the image bound is the larger of 1e-4 and the oracle's own amplification
+    of a relative change of y (measured in FP64) applied to FP32's unit
+    roundoff, times 10; at 2 eps0 the amplification is below 1e3 and the
+    bound is 1e-4."""
     torch = torch_mod
     print(f"[solver fp32] variant=S_CG_K seed={seed}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, "S_CG_K")
     pp = alg.PerturbParams(gamma0)
     ref = alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=1000)
-    passes = max(ref.k - 2, 1)
-    ref_n = alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=passes)
-    alt_n = alg.scg_k(alg.Problem(g, w.y * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
-                      max_iter=passes)
-    amp = _rel(alt_n.x, ref_n.x) / 1e-12
+    alt = alg.scg_k(alg.Problem(g, w.y * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
+                    max_iter=ref.steps)
+    amp = _rel(alt.x, ref.x) / 1e-12
     tol = max(1e-4, 10 * amp * 2.0 ** -24)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        p_n = plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K", prec=scg.SCG_F32,
-                          max_iter=passes)
-        x_n, rep_n, _ = plan.solve(y, p_n, forced=[(t["trials"], t["accepted"])
-                                                   for t in ref_n.trace])
-        x, rep, _ = plan.solve(y, plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
-                                              prec=scg.SCG_F32, max_iter=1000), trace=False)
-    rel_n = _rel(x_n.cpu().numpy().astype(np.float64), ref_n.x)
-    print(f"  {passes} passes: rel={rel_n:.2e} (amplification {amp:.3g}, tolerance {tol:.2e}); "
-          f"full: k={rep.k} ref_k={ref.k}")
-    assert rep_n.status == scg.SCG_ENOCONV and rep_n.k == passes == ref_n.k
-    assert rel_n <= tol
-    xg = x.cpu().numpy().astype(np.float64)
-    assert rep.status == scg.SCG_OK and rep.f_out <= eps and prob.f(xg) <= eps * (1 + 1e-5)
-    assert abs(rep.k - ref.k) <= 1
+        def run_gpu(forced, max_iter):
+            p = plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K", prec=scg.SCG_F32,
+                            max_iter=1000 if max_iter is None else max_iter)
+            x, rep, trace = plan.solve(y, p, forced=forced)
+            return x.cpu().numpy().astype(np.float64), rep, trace
+
+        def run_oracle(max_iter):
+            return alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2,
+                             max_iter=1000 if max_iter is None else max_iter)
+
+        xg, rep, ref, kinds = c10.compare(f"64x64 S_CG_K seed {seed}", run_gpu, run_oracle,
+                                          eps, ref=ref)
+    rel = _rel(xg, ref.x)
+    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e} "
+          f"(amplification {amp:.3g}, tolerance {tol:.2e})")
+    assert rep.k == ref.k and rel <= tol
+    if "stop" not in kinds:
+        assert rep.status == scg.SCG_OK and rep.f_out <= eps
+    assert prob.f(xg) <= eps * (1 + c10.MARGIN)
 
 
 def test_cg_parity(scg, torch_mod, oracle_lib):
