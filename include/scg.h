@@ -144,7 +144,10 @@ typedef struct scg_plan scg_plan;
  * projector's (angle group, 128-bin chunk) blocks at most 65536, about
  * n_angles / 4 * ceil(n_bins / 128)), SCG_ENOMEM, SCG_EDEVICE. The
  * preconditioning filter (SCG_S_PCG, SCG_PCG, SCG_S_PCG_K, scg_filter)
- * needs n_bins <= 2730 and returns SCG_EINVAL otherwise. */
+ * transforms P = 2^ceil(log2(2 n_bins)) complex points in LDS: it needs
+ * n_bins <= 4096 in SCG_F32 and n_bins <= 2048 in SCG_F64 and returns
+ * SCG_EINVAL otherwise. Its tables are allocated here, so solves allocate
+ * nothing for it. */
 int scg_plan_create(const scg_geom *g, int device, scg_plan **out);
 
 /* Frees a plan and its device memory (NULL is accepted). The caller must
@@ -175,7 +178,14 @@ int scg_tv(scg_plan *plan, int prec, const void *x, double kappa, void *s, doubl
  * Preconditioning section applied to every projection of r: zero padding to
  * P = 2^ceil(log2(2 n_bins)) samples, DFT, multiplication by
  * c(w) = (|w| + mu)(0.54 + 0.46 cos w) at w_m = 2 pi m / P, inverse DFT,
- * first n_bins samples kept. mu <= 0 selects 2 pi / P. */
+ * first n_bins samples kept. mu <= 0 selects 2 pi / P. r and out: device,
+ * n_angles * n_bins elements of the precision's type. The transform runs
+ * in the precision `prec` (radix-2, twiddles from FP64 host values).
+ * SCG_EINVAL: n_bins above the precision's bound (see scg_plan_create). A
+ * plan holds one spectrum (one mu) per precision at a time: a call with
+ * another mu rewrites it, so calls and solves that share a plan and
+ * precision must not overlap with different mu (a batch refuses such a
+ * submit with SCG_EINVAL). */
 int scg_filter(scg_plan *plan, int prec, double mu, const void *r, void *out, void *stream);
 
 /* ---- solver ------------------------------------------------------------ */

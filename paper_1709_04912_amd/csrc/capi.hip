@@ -220,38 +220,67 @@ int filter_pad(int nb)
     return P;
 }
 
+// Spectrum of the preconditioning filter at the transform's bit-reversed
+// positions: c(w_k) / P with w_k = 2 pi k / P taken in [-pi, pi), k the
+// frequency stored at position i (k = bit reverse of i over log2 P bits),
+// c(w) = (|w| + mu)(0.54 + 0.46 cos w).
+void filter_spectrum(int P, double mu, std::vector<double> &out)
+{
+    int bits = 0;
+    while ((1 << bits) < P) ++bits;
+    out.resize(P);
+    for (int i = 0; i < P; ++i) {
+        int k = 0;
+        for (int b = 0; b < bits; ++b) k |= ((i >> b) & 1) << (bits - 1 - b);
+        const int m = k < P / 2 ? k : k - P;   // m in [-P/2, P/2)
+        const double w = 2.0 * kPi * m / P;
+        out[i] = (std::fabs(w) + mu) * (0.54 + 0.46 * std::cos(w)) / P;
+    }
+}
+
+template <typename T>
+int upload_filter(scg_plan *p, int pi, double mu, bool twiddles)
+{
+    const int P = filter_pad(p->G.nb);
+    std::vector<double> sp;
+    filter_spectrum(P, mu, sp);
+    std::vector<T> tab(twiddles ? 2 * (size_t)P : (size_t)P);
+    for (int i = 0; i < P; ++i) tab[i] = (T)sp[i];
+    if (twiddles)
+        for (int m = 0; m < P / 2; ++m) {
+            const double w = -2.0 * kPi * m / P;
+            tab[P + 2 * m] = (T)std::cos(w);
+            tab[P + 2 * m + 1] = (T)std::sin(w);
+        }
+    HIP_TRY(hipMemcpy(p->ftab[pi], tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice));
+    p->filt_mu[pi] = mu;
+    return SCG_OK;
+}
+
 }  // namespace
 
 namespace scg {
 
-// k[d] = (1/P) sum_{m=-P/2}^{P/2-1} c(w_m) cos(w_m d), c(w) = (|w| + mu)(0.54 + 0.46 cos w).
-int ensure_filter(scg_plan *p, double mu)
+bool filter_fits(int nb, int prec)
 {
-    const int nb = p->G.nb, P = filter_pad(nb);
-    // a padded projection and the taps of one angle must fit in LDS
-    if ((size_t)3 * nb * sizeof(double) > 65536) return SCG_EINVAL;
-    if (mu <= 0.0) mu = 2.0 * kPi / P;
-    if (p->kern[0] != nullptr && p->kern_mu == mu) return SCG_OK;
-    std::vector<double> k(nb);
-    std::vector<double> cw(P);
-    for (int m = -P / 2; m < P / 2; ++m) {
-        const double w = 2.0 * kPi * m / P;
-        cw[m + P / 2] = (std::fabs(w) + mu) * (0.54 + 0.46 * std::cos(w));
-    }
-    for (int d = 0; d < nb; ++d) {
-        double acc = 0.0;
-        for (int m = -P / 2; m < P / 2; ++m) acc += cw[m + P / 2] * std::cos(2.0 * kPi * m * d / P);
-        k[d] = acc / P;
-    }
-    std::vector<float> kf(k.begin(), k.end());
-    if (p->kern[0] == nullptr) {
-        HIP_TRY(hipMalloc(&p->kern[0], nb * sizeof(float)));
-        HIP_TRY(hipMalloc(&p->kern[1], nb * sizeof(double)));
-    }
-    HIP_TRY(hipMemcpy(p->kern[0], kf.data(), nb * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->kern[1], k.data(), nb * sizeof(double), hipMemcpyHostToDevice));
-    p->kern_mu = mu;
-    return SCG_OK;
+    const size_t esz = prec == SCG_F64 ? sizeof(double) : sizeof(float);
+    return (size_t)filter_pad(nb) * 2 * esz <= kFilterLds;
+}
+
+double filter_mu(const scg_plan *p, double mu)
+{
+    return mu > 0.0 ? mu : 2.0 * kPi / filter_pad(p->G.nb);
+}
+
+// The filter tables of precision prec hold the spectrum for mu (<= 0: 2 pi
+// / P); they were allocated with the plan, so this only uploads.
+int ensure_filter(scg_plan *p, double mu, int prec)
+{
+    const int pi = prec == SCG_F64 ? 1 : 0;
+    if (p->ftab[pi] == nullptr) return SCG_EINVAL;   // n_bins beyond the LDS bound
+    mu = filter_mu(p, mu);
+    if (p->filt_mu[pi] == mu) return SCG_OK;
+    return pi ? upload_filter<double>(p, 1, mu, false) : upload_filter<float>(p, 0, mu, false);
 }
 
 hipEvent_t take_event(scg_plan *p)
@@ -545,6 +574,22 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     }
     int rc = build_proj_tables(p, pa, 8, 0);
     if (rc == SCG_OK) rc = build_proj_tables(p, pa, 4, 1);
+    // filter tables (spectrum for the default mu and twiddles) for each
+    // precision whose transform fits the LDS bound; a solve later changes
+    // only the spectrum, without allocating
+    const double mu0 = 2.0 * kPi / filter_pad(G.nb);
+    if (rc == SCG_OK && scg::filter_fits(G.nb, SCG_F32)) {
+        if (hipMalloc(&p->ftab[0], 2 * (size_t)filter_pad(G.nb) * sizeof(float)) != hipSuccess)
+            rc = SCG_ENOMEM;
+        else
+            rc = upload_filter<float>(p, 0, mu0, true);
+    }
+    if (rc == SCG_OK && scg::filter_fits(G.nb, SCG_F64)) {
+        if (hipMalloc(&p->ftab[1], 2 * (size_t)filter_pad(G.nb) * sizeof(double)) != hipSuccess)
+            rc = SCG_ENOMEM;
+        else
+            rc = upload_filter<double>(p, 1, mu0, true);
+    }
     if (rc != SCG_OK) {
         scg_plan_destroy(p);
         return rc;
@@ -568,7 +613,7 @@ void scg_plan_destroy(scg_plan *p)
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->xs[i]);
         (void)hipFree(p->rpad[i]);
-        (void)hipFree(p->kern[i]);
+        (void)hipFree(p->ftab[i]);
     }
     (void)hipFree(p->partials);
     (void)hipFree(p->tvbuf);
@@ -711,7 +756,7 @@ int scg_filter(scg_plan *plan, int prec, double mu, const void *r, void *out, vo
     if (plan == nullptr || r == nullptr || out == nullptr) return SCG_EINVAL;
     if (prec != SCG_F32 && prec != SCG_F64) return SCG_EINVAL;
     scg::Device dg(plan->device);
-    int rc = scg::ensure_filter(plan, mu);
+    int rc = scg::ensure_filter(plan, mu, prec);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Geo &G = plan->G;
@@ -719,12 +764,12 @@ int scg_filter(scg_plan *plan, int prec, double mu, const void *r, void *out, vo
         float *rp = static_cast<float *>(plan->rpad[0]);
         scg::launch_pad_sino<float>(static_cast<const float *>(r), rp, G, s);
         scg::launch_filter<float>(rp, static_cast<float *>(out),
-                                  static_cast<const float *>(plan->kern[0]), G, 0, s);
+                                  static_cast<const float *>(plan->ftab[0]), G, 0, s);
     } else {
         double *rp = static_cast<double *>(plan->rpad[1]);
         scg::launch_pad_sino<double>(static_cast<const double *>(r), rp, G, s);
         scg::launch_filter<double>(rp, static_cast<double *>(out),
-                                   static_cast<const double *>(plan->kern[1]), G, 0, s);
+                                   static_cast<const double *>(plan->ftab[1]), G, 0, s);
     }
     return hip_status(hipGetLastError());
 }

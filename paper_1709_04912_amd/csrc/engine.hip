@@ -85,7 +85,7 @@ template <typename T> int count_of(const Solve<T> &d, int kind)
     case kKPj: return d.nb_pj;
     case kKBp: return d.nb_bp;
     case kKVec: return d.nb_vec;
-    case kKFilt: return d.G.na;
+    case kKFilt: return (d.G.na + 1) / 2;
     case kKPQ: return d.nb_t32 + d.nb_sv;
     case kKXR: return d.nb_vec + d.nb_sv;
     default: return 0;
@@ -402,7 +402,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.P = proj_tables(plan, tune);
     h.bang = plan->bang;
     h.border = plan->border;
-    h.kern = static_cast<const T *>(plan->kern[prec_index<T>()]);
+    h.ftab = static_cast<const T *>(plan->ftab[prec_index<T>()]);
     h.y = static_cast<const T *>(y_);
     h.x = at(L.x);
     h.xh = at(L.xh);
@@ -510,7 +510,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
                const int32_t *forced_host, int32_t forced_len, hipStream_t st0)
 {
     if (filtered(pr->variant)) {
-        int rc = ensure_filter(plan, pr->precond_mu);
+        int rc = ensure_filter(plan, pr->precond_mu, pr->prec);
         if (rc) return rc;
     }
     // the state and descriptor images are uploaded from the plan's pinned
@@ -1051,7 +1051,14 @@ int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *
                 const void *x0, void *x_out, Slot &slot)
 {
     if (scg::filtered(pr->variant)) {
-        int rc = scg::ensure_filter(plan, pr->precond_mu);
+        // a plan holds one filter spectrum per precision: the resident
+        // filtered solves of this plan must share mu
+        const double mu = scg::filter_mu(plan, pr->precond_mu);
+        for (const Slot &o : b->active)
+            if (o.plan == plan && scg::filtered(o.params.variant) && o.params.prec == pr->prec &&
+                scg::filter_mu(plan, o.params.precond_mu) != mu)
+                return SCG_EINVAL;
+        int rc = scg::ensure_filter(plan, pr->precond_mu, pr->prec);
         if (rc) return rc;
     }
     char *ws = b->arena.base + slot.off;

@@ -137,9 +137,12 @@ __device__ void block_store(const A (&v)[NV], double *dst)
 // first <= k < NV, through LDS: one row per value, eight lanes per row, each
 // lane summing a fixed stride-8 subset in order and a three-step butterfly
 // joining the eight (many values cost a few LDS passes instead of a shuffle
-// tree each). Every thread of the block must call this.
+// tree each). Every thread of the block must call this. With `publish`, every
+// thread that stored a sum issues a device-scope fence before the closing
+// barrier, so the block's sums are visible to other blocks before any
+// thread of the block signals its arrival.
 template <int NV, typename A>
-__device__ void block_store_rows(const A (&v)[NV], double *dst, int first)
+__device__ void block_store_rows(const A (&v)[NV], double *dst, int first, bool publish = false)
 {
     static_assert(NV * 8 <= kBlock, "eight lanes per value");
     constexpr int S = kBlock + 8;   // row stride: the next row's lanes start 8 banks on
@@ -155,7 +158,10 @@ __device__ void block_store_rows(const A (&v)[NV], double *dst, int first)
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 4, 64);
-    if (k < NV && k >= first && p == 0) gl(dst)[k] = acc;
+    if (k < NV && k >= first && p == 0) {
+        gl(dst)[k] = acc;
+        if (publish) __threadfence();
+    }
     __syncthreads();
 }
 
@@ -1349,7 +1355,7 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
         vals[0] = acc[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) vals[1 + m] = acc[m];
-        block_store_rows(vals, dst, c == 0 ? 0 : 1);
+        block_store_rows(vals, dst, c == 0 ? 0 : 1, !with_tvx);
     }
 }
 
@@ -1368,11 +1374,13 @@ __global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap
     if (first_m == 0) return;
     // The second launch, which runs only after the first one found no
     // acceptable step, decides its own trials: the last of the solve's blocks
-    // to store its sums (an arrival count, with fences that publish every
-    // block's sums before its arrival and make them visible to the last
-    // block after it) applies the finisher's trial logic. A step whose first
-    // launch accepted returns above, so it pays neither a finisher launch
-    // nor any fence here.
+    // to store its sums (an arrival count) applies the finisher's trial
+    // logic. Every thread that stored a sum fenced at device scope before
+    // the block's barrier (block_store_rows with publish), so all of the
+    // block's sums are visible before thread 0 counts its arrival; the last
+    // block fences again before it reads the others' sums. A step whose
+    // first launch accepted returns above, so it pays neither a finisher
+    // launch nor any fence here.
     __shared__ int s_last;
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1690,82 +1698,135 @@ void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hip
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioning filter F^T C F per projection, as the linear convolution
-// with k[d] = (1/P) sum_m c(w_m) cos(w_m d) (|d| < n_bins) that the
-// zero-padded DFT product equals. One block per angle; the projection and
-// the kernel are staged in LDS and each thread produces four neighbouring
-// outputs from a sliding window of kernel taps.
+// Preconditioning filter F^T C F per projection: zero padding to P =
+// 2^ceil(log2(2 n_bins)) samples, DFT, multiplication by c(w_m), inverse DFT,
+// the first n_bins samples kept. One block per pair of projections: the two
+// real rows are the real and imaginary parts of one complex sequence (c is
+// real and even, so the product's inverse keeps them apart). The transform
+// runs in LDS: radix-2 decimation in frequency (natural order in, bit-
+// reversed order out), the spectrum multiplied in that order (the table is
+// stored bit-reversed, with 1/P folded in), then radix-2 decimation in time
+// from bit-reversed order back to natural order with conjugate twiddles, so
+// no reordering pass is needed. Table layout: P spectrum values, then P/2
+// twiddles e^{-2 pi i m / P} as (re, im) pairs.
 // ---------------------------------------------------------------------------
+
+template <typename T> struct Cx {
+    T x, y;
+};
+
+__device__ __forceinline__ int filter_len(int nb)
+{
+    return 1 << (32 - __clz(2 * nb - 1));   // smallest power of two >= 2 nb
+}
 
 template <typename T>
 __device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
-                            const T *__restrict__ kern_, const Geo &G, int out_padded, int a)
+                            const T *__restrict__ tab_, const Geo &G, int out_padded, int pair)
 {
     const auto *r = gl(r_);
     auto *out = gl(out_);
-    const auto *kern = gl(kern_);
+    const auto *spec = gl(tab_);
+    const int nb = G.nb, P = filter_len(nb), half = P >> 1;
+    const auto *tw = reinterpret_cast<const Cx<T> *>(spec + P);
     extern __shared__ unsigned char smem[];
-    T *row = reinterpret_cast<T *>(smem);
-    T *kk = row + G.nb;                  // kk[d + nb - 1] = k[|d|], d in (-nb, nb)
-    const int nb = G.nb;
-    const auto *ra = r + (size_t)a * G.rs + kSinoPadL;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) row[b] = ra[b];
-    for (int d = threadIdx.x; d < 2 * nb - 1; d += blockDim.x) {
-        const int dd = d - (nb - 1);
-        kk[d] = kern[dd < 0 ? -dd : dd];
+    Cx<T> *z = reinterpret_cast<Cx<T> *>(smem);
+    const int a0 = 2 * pair, a1 = a0 + 1;
+    const bool two = a1 < G.na;
+    const size_t in_stride = G.rs;
+    const auto *r0 = r + (size_t)a0 * in_stride + kSinoPadL;
+    const auto *r1 = r + (size_t)(two ? a1 : a0) * in_stride + kSinoPadL;
+    for (int b = threadIdx.x; b < P; b += blockDim.x) {
+        Cx<T> v{T(0), T(0)};
+        if (b < nb) {
+            v.x = r0[b];
+            v.y = two ? r1[b] : T(0);
+        }
+        z[b] = v;
     }
     __syncthreads();
-    for (int b0 = threadIdx.x * 4; b0 < nb; b0 += blockDim.x * 4) {
-        // out[b0+t] = sum_bp k[b0 + t - bp] row[bp]
-        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        for (int bp = 0; bp < nb; ++bp) {
-            const T rv = row[bp];
-            const int base = b0 - bp + nb - 1;
-            acc0 = fma(kk[base], rv, acc0);
-            if (b0 + 1 < nb) acc1 = fma(kk[base + 1], rv, acc1);
-            if (b0 + 2 < nb) acc2 = fma(kk[base + 2], rv, acc2);
-            if (b0 + 3 < nb) acc3 = fma(kk[base + 3], rv, acc3);
+    // forward transform: butterflies of span h, twiddle e^{-2 pi i j / (2h)}
+    for (int h = half, ts = 1; h >= 1; h >>= 1, ts <<= 1) {
+        for (int k = threadIdx.x; k < half; k += blockDim.x) {
+            const int j = k & (h - 1);
+            const int i = ((k - j) << 1) + j;
+            const Cx<T> u = z[i], v = z[i + h];
+            const Cx<T> w = tw[j * ts];
+            const T dx = u.x - v.x, dy = u.y - v.y;
+            z[i] = Cx<T>{u.x + v.x, u.y + v.y};
+            z[i + h] = Cx<T>{dx * w.x - dy * w.y, dx * w.y + dy * w.x};
         }
-        auto *oa = out + (size_t)a * (out_padded ? G.rs : nb) + (out_padded ? kSinoPadL : 0);
-        oa[b0] = acc0;
-        if (b0 + 1 < nb) oa[b0 + 1] = acc1;
-        if (b0 + 2 < nb) oa[b0 + 2] = acc2;
-        if (b0 + 3 < nb) oa[b0 + 3] = acc3;
+        __syncthreads();
     }
+    for (int b = threadIdx.x; b < P; b += blockDim.x) {
+        const T c = spec[b];
+        z[b] = Cx<T>{z[b].x * c, z[b].y * c};
+    }
+    __syncthreads();
+    // inverse transform: span h, twiddle e^{+2 pi i j / (2h)}
+    for (int h = 1, ts = half; h < P; h <<= 1, ts >>= 1) {
+        for (int k = threadIdx.x; k < half; k += blockDim.x) {
+            const int j = k & (h - 1);
+            const int i = ((k - j) << 1) + j;
+            const Cx<T> u = z[i], v = z[i + h];
+            const Cx<T> w = tw[j * ts];
+            const Cx<T> t{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
+            z[i] = Cx<T>{u.x + t.x, u.y + t.y};
+            z[i + h] = Cx<T>{u.x - t.x, u.y - t.y};
+        }
+        __syncthreads();
+    }
+    const size_t out_stride = out_padded ? G.rs : nb;
+    const int ofs = out_padded ? kSinoPadL : 0;
+    auto *o0 = out + (size_t)a0 * out_stride + ofs;
+    auto *o1 = out + (size_t)a1 * out_stride + ofs;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const Cx<T> v = z[b];
+        o0[b] = v.x;
+        if (two) o1[b] = v.y;
+    }
+}
+
+// LDS bytes of the filter for n_bins bins in precision T.
+template <typename T> size_t filter_lds(int nb)
+{
+    int P = 1;
+    while (P < 2 * nb) P <<= 1;
+    return (size_t)P * sizeof(Cx<T>);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__restrict__ out,
-                                                 const T *__restrict__ kern, Geo G,
+                                                 const T *__restrict__ tab, Geo G,
                                                  int out_padded)
 {
-    filter_body(r, out, kern, G, out_padded, (int)blockIdx.x);
+    filter_body(r, out, tab, G, out_padded, (int)blockIdx.x);
 }
 
 template <typename T>
-void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
+void launch_filter(const T *r, T *out, const T *tab, const Geo &G, int out_padded,
                    hipStream_t s)
 {
-    size_t shm = (size_t)(3 * G.nb) * sizeof(T);
-    hipLaunchKernelGGL(k_filter<T>, dim3(G.na), dim3(256), shm, s, r, out, kernel, G, out_padded);
+    hipLaunchKernelGGL(k_filter<T>, dim3((G.na + 1) / 2), dim3(256), filter_lds<T>(G.nb), s, r,
+                       out, tab, G, out_padded);
 }
 
-// r~ = F^T C F r of every solve (rt, padded), one block per angle.
+// r~ = F^T C F r of every solve (rt, padded), one block per pair of angles.
 template <typename T>
 __global__ __launch_bounds__(256) void kb_filter(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
-    filter_body(d.r, d.rt, d.kern, d.G, 1, m.local);
+    filter_body(d.r, d.rt, d.ftab, d.G, 1, m.local);
 }
 
 template <typename T>
 void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
                      hipStream_t s)
 {
-    size_t shm = (size_t)(3 * max_nb) * sizeof(T);
-    hipLaunchKernelGGL(kb_filter<T>, dim3(nblocks), dim3(256), shm, s, S, map);
+    hipLaunchKernelGGL(kb_filter<T>, dim3(nblocks), dim3(256), filter_lds<T>(max_nb), s, S,
+                       map);
 }
 
 // ---------------------------------------------------------------------------

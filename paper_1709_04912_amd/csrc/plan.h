@@ -32,9 +32,12 @@ struct scg_plan {
     // pinned host words the solver reads its stop flag and final state into
     // (a read into pinned memory is one DMA, not a staged pageable copy)
     void *host_pinned = nullptr;
-    void *kern[2] = {nullptr, nullptr};   // filter taps k[d], d < n_bins
+    // preconditioning filter per precision: P spectrum values at bit-reversed
+    // positions, then P/2 twiddles (null where the transform exceeds the LDS
+    // bound)
+    void *ftab[2] = {nullptr, nullptr};
     scg_tuning tune[2] = {{4, 4, 8, 0}, {4, 2, 8, 0}};  // launch shapes (F32, F64)
-    double kern_mu = -1.0;
+    double filt_mu[2] = {-1.0, -1.0};      // mu of each precision's spectrum
     // kernel timing (scg_profile): HIP events around launches of chosen classes
     struct ProfRec {
         int cls;
@@ -75,8 +78,12 @@ template <typename T> inline int prec_index();
 template <> inline int prec_index<float>() { return 0; }
 template <> inline int prec_index<double>() { return 1; }
 
-// Filter taps of the S-PCG preconditioner for mu (<= 0: 2 pi / P) on the plan.
-int ensure_filter(scg_plan *p, double mu);
+// Spectrum of the S-PCG preconditioner for mu (<= 0: 2 pi / P) in the plan's
+// table of precision prec; SCG_EINVAL when n_bins exceeds that precision's
+// LDS bound (filter_fits).
+int ensure_filter(scg_plan *p, double mu, int prec);
+bool filter_fits(int nb, int prec);
+double filter_mu(const scg_plan *p, double mu);   // mu, or 2 pi / P for mu <= 0
 
 // Kernel timing of scg_profile: event pairs around launches of timed classes.
 void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin);

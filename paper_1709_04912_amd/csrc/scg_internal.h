@@ -44,6 +44,10 @@ constexpr int kMaxTrials = 1024;     // cap on max_trials
 constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPass;
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
 constexpr int kMaxN = 2880;          // largest accepted image side
+// LDS of the preconditioning filter: one complex sequence of P =
+// 2^ceil(log2(2 n_bins)) points per block, so n_bins <= 4096 (FP32) and
+// n_bins <= 2048 (FP64)
+constexpr size_t kFilterLds = 65536;
 constexpr int kMaxT32Blocks = 8192;  // 32 x 32 image tiles (direction update blocks)
 constexpr size_t kHostPinnedBytes = 4096;   // a plan's pinned host words
 constexpr size_t kPinnedStagingOffset = 2048;   // where a solve's upload images sit in them
@@ -127,7 +131,7 @@ template <typename T> struct Solve {
     ProjTables P;
     const BpAngle *bang;
     const int *border;          // backprojector tile of each local block index
-    const T *kern;              // filter taps (S-PCG)
+    const T *ftab;              // filter spectrum and twiddles (S-PCG, PCG)
     const T *y;                 // data, n_angles x n_bins
     T *x, *xh, *p, *g, *h, *s, *z;
     T *r, *q, *rt;              // padded sinograms (row stride G.rs)
@@ -229,7 +233,7 @@ template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
                double *tv_dst, hipStream_t s);   // partials: vec_blocks(n^2) doubles
 template <typename T>
-void launch_filter(const T *r, T *out, const T *kernel, const Geo &G, int out_padded,
+void launch_filter(const T *r, T *out, const T *table, const Geo &G, int out_padded,
                    hipStream_t s);
 
 // Solver phases over `ns` solves (S: device array; map: device block map of

@@ -29,6 +29,14 @@ FORCED: list = []     # (label, kind, step, relative margin)
 CHECKED: list = []    # labels of every comparison made
 
 
+def fp32_data(y):
+    """The values an FP32 solve receives: y rounded to FP32, held exactly in
+    FP64. FP32 parity runs the oracle on these, so both sides solve the same
+    problem and only arithmetic differs (at 512 x 512 the rounding of y
+    alone moves the oracle's own output by 3.5e-5)."""
+    return np.asarray(y, dtype=np.float32).astype(np.float64)
+
+
 def decisions(trace):
     return [(t["trials"], t["accepted"]) for t in trace]
 

@@ -201,7 +201,7 @@ def test_batch_against_oracle(scg, torch_mod, oracle_lib):
     for seed in (0, 1):
         w = make_workload(1, seed, supersample=2)
         g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
-        prob = alg.Problem(g, w.y)
+        prob = alg.Problem(g, c10.fp32_data(w.y))
         eps = 1.1 * gd[f"cfg1_s{seed}"]["eps0"]
         gamma0 = 0.05 * gd[f"cfg1_s{seed}"]["x1_norm"]
         pp = alg.PerturbParams(gamma0)

@@ -41,11 +41,16 @@ def case256(oracle_lib):
     return w, g, alg.Problem(g, w.y), 1.05 * gd["eps0"], 0.05 * gd["x1_norm"]
 
 
-def _oracle(case256, variant, max_iter=None):
+def _oracle(case256, variant, max_iter=None, fp32_data=False):
+    """The oracle's solve on y, or on y rounded to FP32 (the FP32 solve's
+    input)."""
     w, g, prob, eps, gamma0 = case256
-    key = (variant, max_iter)
+    key = (variant, max_iter, fp32_data)
     if key not in _REFS:
-        print(f"  oracle {variant} 256x256 max_iter={max_iter}", flush=True)
+        print(f"  oracle {variant} 256x256 max_iter={max_iter} fp32 data={fp32_data}",
+              flush=True)
+        if fp32_data:
+            prob = alg.Problem(g, c10.fp32_data(w.y))
         _REFS[key] = ORACLE[variant](prob, np.zeros(g.J), eps=eps,
                                      pp=alg.PerturbParams(gamma0),
                                      max_iter=400 if max_iter is None else max_iter)
@@ -85,9 +90,10 @@ def test_fp32_to_the_stop(scg, case256, variant):
             return x.cpu().numpy().astype(np.float64), rep, trace
 
         xg, rep, ref, kinds = c10.compare(f"256x256 {variant}", run_gpu,
-                                          lambda m: _oracle(case256, variant, m), eps,
-                                          ref=_oracle(case256, variant))
+                                          lambda m: _oracle(case256, variant, m, True), eps,
+                                          ref=_oracle(case256, variant, None, True))
     rel = c10.rel_l2(xg, ref.x)
+    prob = alg.Problem(g, c10.fp32_data(w.y))
     print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e} f={rep.f_out:.8g}")
     assert rep.k == ref.k and rel <= 1e-4
     if "stop" not in kinds:

@@ -4,8 +4,9 @@ eps = f(x_true), gamma0 = 0.05 ||x_1|| with x_1 the oracle's first CG
 iterate): the first step against the FP64 oracle, the whole solve to the
 stop against the oracle's (same k, image within relative L2 1e-4, eps met,
 decisions checked against the oracle's FP64 margins as in
-tests/parity_c10.py), and the abstract's claim that the output's TV is below
-unsuperiorized CG's at the same eps."""
+tests/parity_c10.py, the oracle given the FP32 solve's input values), and
+the abstract's claim that the output's TV is below unsuperiorized CG's at
+the same eps."""
 import numpy as np
 import pytest
 
@@ -33,6 +34,8 @@ def case(oracle_lib):
     plan = scg.Plan(w.n, w.n_angles, w.n_bins)
     plan.autotune(scg.SCG_F32)
     y32 = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
+    # the oracle solves on the values the FP32 solve receives
+    prob = alg.Problem(g, c10.fp32_data(w.y))
     yield scg, plan, w, g, prob, eps, gamma0, y32
     plan.close()
 

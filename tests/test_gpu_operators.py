@@ -105,7 +105,7 @@ def test_tv_and_subgradient(scg, torch_mod, oracle_lib, n):
 
 
 @pytest.mark.parametrize("geom", [(16, 5, 7), (64, 90, 95), (32, 3, 129), (16, 7, 367),
-                                  (16, 5, 729), (16, 3, 1450)])
+                                  (16, 5, 729), (16, 3, 1450), (16, 2, 2048), (8, 1, 1)])
 def test_filter(scg, torch_mod, oracle_lib, geom):
     torch = torch_mod
     n, na, nb = geom
@@ -119,6 +119,35 @@ def test_filter(scg, torch_mod, oracle_lib, geom):
             assert _rel(out, ref) <= tol, (dt, _rel(out, ref))
         out = plan.filter(torch.tensor(r, dtype=torch.float64, device="cuda"), mu=0.3)
         assert _rel(out.cpu().numpy(), g.filter(r, mu=0.3)) <= 1e-12
+
+
+def test_filter_bin_limits(scg, torch_mod, oracle_lib):
+    """The transform of P = 2^ceil(log2(2 n_bins)) complex points fits 64 KB
+    of LDS up to 4096 bins in FP32 (checked against the oracle there) and
+    2048 in FP64; beyond, the filter and the filtered solvers are refused."""
+    torch = torch_mod
+    g = oracle_lib.Geometry(8, 3, 4096)
+    rng = np.random.default_rng(4096)
+    r = rng.standard_normal(3 * 4096)
+    with scg.Plan(8, 3, 4096) as plan:
+        out = plan.filter(torch.tensor(r, dtype=torch.float32, device="cuda")).cpu().numpy()
+        assert _rel(out, g.filter(r)) <= 1e-5
+        with pytest.raises(scg.ScgError):
+            plan.filter(torch.tensor(r, dtype=torch.float64, device="cuda"))
+    with scg.Plan(8, 3, 4097) as plan:
+        with pytest.raises(scg.ScgError):
+            plan.filter(torch.zeros(3 * 4097, dtype=torch.float32, device="cuda"))
+        with pytest.raises(scg.ScgError):
+            plan.solve(torch.zeros(3 * 4097, dtype=torch.float32, device="cuda"),
+                       plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", max_iter=1),
+                       trace=False)
+    with scg.Plan(8, 3, 2049) as plan:
+        with pytest.raises(scg.ScgError):
+            plan.filter(torch.zeros(3 * 2049, dtype=torch.float64, device="cuda"))
+        y = torch.zeros(3 * 2049, dtype=torch.float64, device="cuda")
+        with pytest.raises(scg.ScgError):
+            plan.solve(y, plan.params(eps=1.0, gamma0=0.0, variant="PCG", prec=scg.SCG_F64,
+                                      max_iter=1), trace=False)
 
 
 def test_full_size_sampled(scg, torch_mod, oracle_lib):
@@ -220,8 +249,8 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
 
 def test_size_limits(scg, torch_mod, oracle_lib):
     """The largest accepted image (N = 2880) with a detector of 4076 bins, on sampled rays
-    and pixels against the oracle; one pixel more is rejected, and the
-    filter (only) rejects more than 2730 bins."""
+    and pixels against the oracle, and its FP32 filter; one pixel more is
+    rejected; the FP64 filter (only) rejects more than 2048 bins."""
     torch = torch_mod
     n, na, nb = 2880, 6, 4076
     print(f"[limits] N={n} angles={na} bins={nb}", flush=True)
@@ -235,17 +264,16 @@ def test_size_limits(scg, torch_mod, oracle_lib):
     with scg.Plan(n, na, nb) as plan:
         ax = plan.project(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
         aty = plan.backproject(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
+        filt = plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         with pytest.raises(scg.ScgError):
-            plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda"))
+            plan.filter(torch.tensor(y, dtype=torch.float64, device="cuda"))
         with pytest.raises(scg.ScgError):
-            plan.solve(torch.tensor(y, dtype=torch.float32, device="cuda"),
-                       plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", max_iter=1),
-                       trace=False)
+            plan.solve(torch.tensor(y, dtype=torch.float64, device="cuda"),
+                       plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", prec=scg.SCG_F64,
+                                   max_iter=1), trace=False)
+    assert _rel(filt, g.filter(y)) <= 1e-5
     assert _rel(ax[rays], g.project_rays(x, rays)) <= 1e-5
     assert _rel(aty[pix], g.backproject_pixels(y, pix)) <= 1e-5
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
     with pytest.raises(scg.ScgError):
         scg.Plan(n + 1, na, 64)
-    with scg.Plan(64, 8, 2730) as plan:
-        r = torch.zeros(8 * 2730, dtype=torch.float32, device="cuda")
-        assert float(plan.filter(r).abs().max()) == 0.0

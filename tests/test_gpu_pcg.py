@@ -78,6 +78,7 @@ def test_pcg_fp32(scg, torch_mod, oracle_lib, seed):
     torch = torch_mod
     print(f"[pcg fp32] seed={seed}", flush=True)
     w, g, prob, eps, _ = _case(oracle_lib, seed)
+    prob = alg.Problem(g, c10.fp32_data(w.y))
     steps = 12
     ref_n = alg.pcg(prob, np.zeros(g.J), eps=0.0, max_iter=steps)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
@@ -151,8 +152,10 @@ def test_spcg_k_fp32(scg, torch_mod, oracle_lib, seed):
     print(f"[s-pcg-k fp32] seed={seed}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed)
     pp = alg.PerturbParams(gamma0)
+    y32 = c10.fp32_data(w.y)
+    prob = alg.Problem(g, y32)
     ref = alg.spcg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=1000)
-    alt = alg.spcg_k(alg.Problem(g, w.y * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
+    alt = alg.spcg_k(alg.Problem(g, y32 * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
                      max_iter=ref.steps)
     amp = _rel(alt.x, ref.x) / 1e-12
     tol = max(1e-4, 10 * amp * 2.0 ** -24)

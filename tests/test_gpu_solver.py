@@ -101,6 +101,7 @@ def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
     pp = alg.PerturbParams(gamma0)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
+    prob = alg.Problem(g, c10.fp32_data(w.y))
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
         def run_gpu(forced, max_iter):
             p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
@@ -134,8 +135,10 @@ def test_fp32_parity_scg_k(scg, torch_mod, oracle_lib, seed):
     print(f"[solver fp32] variant=S_CG_K seed={seed}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, "S_CG_K")
     pp = alg.PerturbParams(gamma0)
+    y32 = c10.fp32_data(w.y)
+    prob = alg.Problem(g, y32)
     ref = alg.scg_k(prob, np.zeros(g.J), eps, pp, K=2, max_iter=1000)
-    alt = alg.scg_k(alg.Problem(g, w.y * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
+    alt = alg.scg_k(alg.Problem(g, y32 * (1 + 1e-12)), np.zeros(g.J), eps, pp, K=2,
                     max_iter=ref.steps)
     amp = _rel(alt.x, ref.x) / 1e-12
     tol = max(1e-4, 10 * amp * 2.0 ** -24)
