@@ -2,7 +2,8 @@
 angles, 729 bins, autotuned launch shapes, FP32 operators with FP64 scalars,
 eps = f(x_true), gamma0 = 0.05 ||x_1|| with x_1 the oracle's first CG
 iterate): the first step against the FP64 oracle, the whole solve to the
-stop against the oracle's (same k, image within relative L2 1e-4, eps met,
+stop against the oracle's (same k, image within relative L2 1e-4 or twice
+the oracle's own amplification of FP32 rounding if that is larger, eps met,
 decisions checked against the oracle's FP64 margins as in
 tests/parity_c10.py, the oracle given the FP32 solve's input values), and
 the abstract's claim that the output's TV is below unsuperiorized CG's at
@@ -84,9 +85,20 @@ def test_solve_matches_oracle(case):
                                       lambda m: _oracle(case, 2000 if m is None else m), eps)
     rel = c10.rel_l2(xg, ref.x)
     f_oracle = prob.f(xg)
-    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e} f={rep.f_out:.10g} "
-          f"oracle f of the GPU image={f_oracle:.10g} eps={eps:.10g}")
-    assert rep.k == ref.k and rel <= 1e-4
+    # The image bound: 1e-4, or the oracle's own amplification of a relative
+    # change of y applied to FP32's unit roundoff, times 2, if that is
+    # larger. At this size S-CG amplifies a relative change of y about
+    # 1800-fold, so FP32 storage alone sits near 1e-4: the oracle with its
+    # vectors, or only its operator outputs, rounded to FP32 after each
+    # operation lands 8.7e-5 and 7.7e-5 from its FP64 output.
+    alt = alg.scg(alg.Problem(g, prob.y * (1 + 1e-9)), np.zeros(g.J), eps=eps,
+                  pp=alg.PerturbParams(gamma0), max_iter=ref.steps)
+    amp = c10.rel_l2(alt.x, ref.x) / 1e-9
+    tol = max(1e-4, 2 * amp * 2.0 ** -24)
+    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e} (amplification {amp:.4g}, "
+          f"tolerance {tol:.3g}) f={rep.f_out:.10g} oracle f of the GPU image={f_oracle:.10g} "
+          f"eps={eps:.10g}")
+    assert rep.k == ref.k and rel <= tol
     if "stop" not in kinds:
         assert rep.status == scg.SCG_OK and ref.status == "ok" and rep.f_out <= eps
         assert ref.f_out <= eps
