@@ -205,6 +205,27 @@ int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const voi
               scg_trace_entry *trace, int32_t trace_cap, const int32_t *forced,
               int32_t forced_len, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): scg_solve with
+ * the workspace taken from a static device array of the library instead of
+ * a caller buffer. Same arguments, results and statuses as scg_solve
+ * (bitwise the same output and report for the same inputs and launch
+ * shapes), without ws/ws_bytes; kernel timing (scg_profile) is not applied.
+ * The call allocates no device memory. Limit: scg_workspace_bytes() for
+ * the parameters must not exceed scg_static_workspace_bytes() (32 MiB: FP32
+ * up to about 700 x 700 pixels, FP64 up to 512 x 512 with 720 x 729 rays);
+ * larger problems return SCG_ENOMEM. Each device holds one such array for
+ * the life of the process, shared by every call on that device, which
+ * keeps the previous call's contents (the solve initialises everything it
+ * reads). Calls that overlap in time on one device race on it: callers
+ * serialise them (one stream, or waits between streams). */
+int scg_solve_static(scg_plan *plan, const scg_params *params, const void *y, const void *x0,
+                     void *x_out, scg_report *rep, scg_trace_entry *trace, int32_t trace_cap,
+                     const int32_t *forced, int32_t forced_len, void *stream);
+
+/* Bytes of the static workspace of scg_solve_static (per device). */
+size_t scg_static_workspace_bytes(void);
+
 /* ---- launch shapes ----------------------------------------------------- */
 
 /* Launch shapes of the two operators; results do not depend on them beyond

@@ -17,11 +17,20 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
 
 #include "plan.h"
+
+// Workspace of scg_solve_static: a file-scope device array, one per device
+// the library runs on, held until the process ends. Host code never passes
+// its name to a kernel or a copy (on the host it only stands for the
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current (static_workspace below).
+constexpr size_t kStaticWsBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
 
 using scg::BlkMap;
 using scg::Solve;
@@ -507,7 +516,8 @@ Group<T> single_group(const scg_params *pr, const scg_tuning &tune, const Solve<
 template <typename T>
 int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *x0, void *xout,
                char *ws, scg_report *rep, scg_trace_entry *trace_host, int32_t trace_cap,
-               const int32_t *forced_host, int32_t forced_len, hipStream_t st0)
+               const int32_t *forced_host, int32_t forced_len, hipStream_t st0,
+               bool timed = true)
 {
     if (filtered(pr->variant)) {
         int rc = ensure_filter(plan, pr->precond_mu, pr->prec);
@@ -526,7 +536,8 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     if (rc) return rc;
     const Solve<T> &h = stage.desc;
     Group<T> g = single_group<T>(pr, tune, h, ws);
-    g.prof = plan;
+    // kernel timing takes HIP events from the plan (created on first use)
+    g.prof = timed ? plan : nullptr;
 
     plan->prof_iter = 0;
     enqueue_init(g, st0);
@@ -1073,6 +1084,25 @@ int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *
     return SCG_OK;
 }
 
+std::mutex static_ws_mu;
+std::vector<char *> static_ws;   // device address of `scratch`, by device
+
+// The device address of the calling device's scratch (the device must be
+// current).
+int static_workspace(int device, char **out)
+{
+    std::lock_guard<std::mutex> lock(static_ws_mu);
+    if ((int)static_ws.size() <= device) static_ws.resize(device + 1, nullptr);
+    if (static_ws[device] == nullptr) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+            return SCG_EDEVICE;
+        static_ws[device] = static_cast<char *>(ptr);
+    }
+    *out = static_ws[device];
+    return SCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1107,6 +1137,32 @@ int scg_solve(scg_plan *plan, const scg_params *params, const void *y, const voi
     if (hipGetLastError() != hipSuccess) return SCG_EDEVICE;
     return rc;
 }
+
+int scg_solve_static(scg_plan *plan, const scg_params *params, const void *y, const void *x0,
+                     void *x_out, scg_report *rep, scg_trace_entry *trace, int32_t trace_cap,
+                     const int32_t *forced, int32_t forced_len, void *stream)
+{
+    if (plan == nullptr || y == nullptr || x_out == nullptr) return SCG_EINVAL;
+    int rc = scg::check_params(params);
+    if (rc) return rc;
+    if (scg::workspace_bytes(plan->G, params->prec, params->max_iter) > kStaticWsBytes)
+        return SCG_ENOMEM;
+    scg::Device dg(plan->device);
+    char *ws = nullptr;
+    rc = static_workspace(plan->device, &ws);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (params->prec == SCG_F32)
+        rc = scg::solve_impl<float>(plan, params, y, x0, x_out, ws, rep, trace, trace_cap, forced,
+                                    forced_len, s, false);
+    else
+        rc = scg::solve_impl<double>(plan, params, y, x0, x_out, ws, rep, trace, trace_cap,
+                                     forced, forced_len, s, false);
+    if (hipGetLastError() != hipSuccess) return SCG_EDEVICE;
+    return rc;
+}
+
+size_t scg_static_workspace_bytes(void) { return kStaticWsBytes; }
 
 int scg_batch_create(int device, size_t arena_bytes, int max_slots, uint32_t flags,
                      scg_batch **out)

@@ -87,6 +87,11 @@ def _load() -> C.CDLL:
     L.scg_solve.argtypes = [vp, C.POINTER(scg_params), vp, vp, vp, vp, C.c_size_t,
                             C.POINTER(scg_report), C.POINTER(scg_trace_entry), i32,
                             C.POINTER(i32), i32, vp]
+    L.scg_solve_static.argtypes = [vp, C.POINTER(scg_params), vp, vp, vp,
+                                   C.POINTER(scg_report), C.POINTER(scg_trace_entry), i32,
+                                   C.POINTER(i32), i32, vp]
+    L.scg_static_workspace_bytes.argtypes = []
+    L.scg_static_workspace_bytes.restype = C.c_size_t
     L.scg_profile.argtypes = [vp, C.c_uint32]
     L.scg_profile_read.argtypes = [vp, C.POINTER(scg_kernel_time)]
     L.scg_plan_get_tuning.argtypes = [vp, C.c_int, C.POINTER(scg_tuning)]
@@ -97,7 +102,8 @@ def _load() -> C.CDLL:
     L.scg_strerror.argtypes = [C.c_int]
     L.scg_strerror.restype = C.c_char_p
     for name in ("scg_plan_create", "scg_workspace_bytes", "scg_project", "scg_backproject",
-                 "scg_tv", "scg_filter", "scg_solve", "scg_profile", "scg_profile_read",
+                 "scg_tv", "scg_filter", "scg_solve", "scg_solve_static", "scg_profile",
+                 "scg_profile_read",
                  "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune"):
         getattr(L, name).restype = C.c_int
     return L
@@ -291,14 +297,26 @@ class Plan:
               trace: bool = True, forced=None, stream=None):
         """Runs scg_solve; returns (x, Report, trace list). Statuses
         SCG_ENOCONV, SCG_ENAN and SCG_EBREAKDOWN are reported, not raised."""
+        if ws is None:
+            ws = self.workspace(params)
+        need = self.workspace_bytes(params)
+        return self._run("scg_solve", y, params, x0, out, trace, forced, stream,
+                         (C.c_void_p(ws.data_ptr()), need))
+
+    def solve_static(self, y: torch.Tensor, params: scg_params,
+                     x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                     trace: bool = True, forced=None, stream=None):
+        """scg_solve_static: scg_solve on the library's static device workspace
+        (no device allocation by the library); out must be given by callers
+        that allocate nothing themselves."""
+        return self._run("scg_solve_static", y, params, x0, out, trace, forced, stream, ())
+
+    def _run(self, fn, y, params, x0, out, trace, forced, stream, ws_args):
         prec = _prec_of(y)
         if prec != params.prec:
             raise ValueError("params.prec does not match the tensor dtype")
         if out is None:
             out = torch.empty(self.J, dtype=y.dtype, device=y.device)
-        if ws is None:
-            ws = self.workspace(params)
-        need = self.workspace_bytes(params)
         cap = params.max_iter + 1 if trace else 0
         tr = (scg_trace_entry * max(cap, 1))()
         rep = scg_report()
@@ -309,12 +327,12 @@ class Plan:
                 flat += [int(nt), int(am)]
             farr = (C.c_int32 * max(len(flat), 1))(*flat)
             fptr, flen = farr, len(forced)
-        rc = lib.scg_solve(self._h, C.byref(params), _dev(y, self.L, "y"),
-                           _dev(x0, self.J, "x0") if x0 is not None else None,
-                           _dev(out, self.J, "x_out"), C.c_void_p(ws.data_ptr()), need,
-                           C.byref(rep), tr if trace else None, cap, fptr, flen,
-                           C.c_void_p(_stream_handle(stream)))
-        _check(rc, "scg_solve", ok=(SCG_OK, SCG_ENOCONV, SCG_ENAN, SCG_EBREAKDOWN))
+        rc = getattr(lib, fn)(self._h, C.byref(params), _dev(y, self.L, "y"),
+                              _dev(x0, self.J, "x0") if x0 is not None else None,
+                              _dev(out, self.J, "x_out"), *ws_args,
+                              C.byref(rep), tr if trace else None, cap, fptr, flen,
+                              C.c_void_p(_stream_handle(stream)))
+        _check(rc, fn, ok=(SCG_OK, SCG_ENOCONV, SCG_ENAN, SCG_EBREAKDOWN))
         report = Report(rep.status, rep.k, rep.steps, rep.trials_total, rep.ell, rep.f_out,
                         rep.tv_out)
         entries = []
@@ -324,6 +342,11 @@ class Plan:
                                 "ell": e.ell, "f_half": e.f_half, "tv_x": e.tv_x,
                                 "gamma": e.gamma, "beta": e.beta, "alpha": e.alpha})
         return out, report, entries
+
+
+def static_workspace_bytes() -> int:
+    """Bytes of scg_solve_static's per-device workspace."""
+    return int(lib.scg_static_workspace_bytes())
 
 
 # ---------------------------------------------------------------------------

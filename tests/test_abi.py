@@ -56,3 +56,8 @@ def test_host_only_entry_points(lib):
     assert lib.scg_batch_step(None, 1) == -1
     lib.scg_batch_poll.argtypes = [vp, C.c_uint64, vp]
     assert lib.scg_batch_poll(None, 1, None) == -1
+    lib.scg_static_workspace_bytes.restype = C.c_size_t
+    assert lib.scg_static_workspace_bytes() == 32 << 20
+    lib.scg_solve_static.argtypes = [vp] * 7 + [C.c_int32, vp, C.c_int32, vp]
+    assert lib.scg_solve_static(None, None, None, None, None, None, None, 0, None, 0,
+                                None) == -1
