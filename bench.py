@@ -46,6 +46,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9   # VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 G
 OPS_PER_NNZ = 8                    # weight evaluation + multiply-accumulate per nonzero
 PEAK_HBM = 8.0e12
 ARENA = 16 << 30                   # batch engine arena (bytes of HBM)
+FULL_SOLVE_S = 60.0                # the oracle's 512x512 solve is timed whole below this
 
 
 def log(msg):
@@ -105,9 +106,15 @@ def count_nnz(n, n_angles, n_bins):
 
 
 def cpu_baseline(w, eps, gamma0, steps_gpu):
+    """The FP64 oracle on the host. value: the whole 512x512 S-CG solve on all
+    cores, timed when the initial step plus two steps predict it within
+    FULL_SOLVE_S, else that prediction. Also one A and one A^T on a single
+    core, and full solves of the 64x64 and 256x256 workloads (eps from
+    tests/golden/eps.json) on all cores."""
     import numpy as np
     import oracle
     from oracle import algorithms as alg
+    from synth import make_workload
     threads = oracle.ops.max_threads()
     g = oracle.Geometry(w.n, w.n_angles, w.n_bins, threads=threads)
     prob = alg.Problem(g, w.y)
@@ -121,10 +128,44 @@ def cpu_baseline(w, eps, gamma0, steps_gpu):
     t_two = time.perf_counter() - t
     per_step = max(t_two - t_init, 1e-9) / 2.0
     est = t_init + per_step * steps_gpu
-    return {"value": 1.0 / est, "unit": "recons/s", "cores": threads, "kind": "oracle",
-            "sample": (f"FP64 oracle at {w.n}x{w.n} ({w.n_angles}x{w.n_bins}): initial step "
-                       f"{t_init:.2f} s + 2 S-CG steps ({per_step:.2f} s/step), extrapolated to "
-                       f"the GPU solve's {steps_gpu} steps")}
+    out = {"unit": "recons/s", "cores": threads, "kind": "oracle"}
+    if est <= FULL_SOLVE_S:
+        t = time.perf_counter()
+        ref = alg.scg(prob, x0, eps=eps, pp=pp, max_iter=2000)
+        t_full = time.perf_counter() - t
+        out["value"] = 1.0 / t_full
+        out["sample"] = (f"one whole FP64 oracle S-CG solve at {w.n}x{w.n} ({w.n_angles}x"
+                         f"{w.n_bins}), {ref.steps} steps, {t_full:.1f} s on {threads} threads")
+    else:
+        out["value"] = 1.0 / est
+        out["sample"] = (f"FP64 oracle at {w.n}x{w.n} ({w.n_angles}x{w.n_bins}): initial step "
+                         f"{t_init:.2f} s + 2 S-CG steps ({per_step:.2f} s/step), extrapolated "
+                         f"to the GPU solve's {steps_gpu} steps")
+    g1 = oracle.Geometry(w.n, w.n_angles, w.n_bins, threads=1)
+    xr = np.random.default_rng(0).uniform(0, 1, g.J)
+    t = time.perf_counter()
+    yr = g1.project(xr)
+    t_a1 = time.perf_counter() - t
+    t = time.perf_counter()
+    g1.backproject(yr)
+    t_at1 = time.perf_counter() - t
+    out["single_core"] = {"A_s": t_a1, "AT_s": t_at1,
+                          "note": "one application each at 512x512 (720x729), one thread"}
+    gd = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))
+    configs = {}
+    for key, cfg, factor in (("cfg1_s0", 1, 1.1), ("cfg2_s0", 2, 1.05)):
+        wk = make_workload(cfg, 0, supersample=2)
+        gk = oracle.Geometry(wk.n, wk.n_angles, wk.n_bins, threads=threads)
+        pk = alg.Problem(gk, wk.y)
+        epsk = factor * gd[key]["eps0"]
+        ppk = alg.PerturbParams(RHO * gd[key]["x1_norm"])
+        t = time.perf_counter()
+        rk = alg.scg(pk, np.zeros(gk.J), eps=epsk, pp=ppk, max_iter=1000)
+        tk = time.perf_counter() - t
+        configs[f"{wk.n}x{wk.n}"] = {"seconds": tk, "recons_per_s": 1.0 / tk, "k": rk.k,
+                                     "status": rk.status, "eps": f"{factor} eps0"}
+    out["full_solves"] = configs
+    return out
 
 
 def mixed_runs(n_serve, shape):
@@ -235,6 +276,41 @@ def three_operator_run(plan, y, params, out_scg, ws, stream, w, steps):
                                         / np.linalg.norm(w.x_true))}
 
 
+def spcg_run(plan, y, params, ws, stream, w, steps):
+    """S-PCG (Alg. S-PCG with PCG-PR-STEP, the filtered-residual preconditioner)
+    on the same workload and eps: throughput, stopping step, and the filter's
+    share of a solve (its launches timed with events in one more solve)."""
+    import numpy as np
+    import torch
+    from paper_1709_04912_amd import scg
+    ps = scg.scg_params.from_buffer_copy(params)
+    ps.variant = scg.VARIANTS["S_PCG"]
+    out = torch.empty(plan.J, dtype=torch.float32, device=y.device)
+    _, rep, _ = plan.solve(y, ps, out=out, ws=ws, trace=False, stream=stream)
+    n = max(3, steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        _, rep, _ = plan.solve(y, ps, out=out, ws=ws, trace=False, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.profile(("filter",))
+    plan.solve(y, ps, out=out, ws=ws, trace=False, stream=stream)
+    torch.cuda.synchronize()
+    f = plan.profile_read()["filter"]
+    plan.profile(())
+    per_solve_ms = 1e3 * elapsed / n
+    return {"variant": "S_PCG", "value": n / elapsed, "unit": "recons/s", "solves": n,
+            "status": rep.status, "k": rep.k, "steps_per_solve": rep.steps, "f_out": rep.f_out,
+            "ms_per_solve": per_solve_ms,
+            "filter": {"launches_per_solve": int(f[0]),
+                       "avg_us": 1e3 * f[1] / f[0] if f[0] else 0.0,
+                       "share_of_solve": f[1] / per_solve_ms},
+            "rel_err_vs_phantom": float(np.linalg.norm(out.double().cpu().numpy()
+                                                       - w.x_true.reshape(-1))
+                                        / np.linalg.norm(w.x_true))}
+
+
 def counter_workload(shapes):
     """Workload of the FETCH_SIZE / WRITE_SIZE counter runs: two 512x512
     S-CG solves with fixed launch shapes, then three plain device copies of
@@ -265,6 +341,30 @@ def counter_workload(shapes):
     plan.close()
 
 
+def batched_counter_workload(shapes):
+    """Workload of the batched counter runs: the benchmark's 64-solve mix
+    (make_batch_item 0..63, all submitted at once, 4 iterations per engine
+    step, without the graph so every phase is its own dispatch), run twice,
+    then three plain device copies of 64 MiB for the counters' units."""
+    import torch
+    from paper_1709_04912_amd import serve
+    from synth.workloads import make_batch_item
+    cache = serve.PlanCache(shape=shapes)
+    reqs = [serve.make_request(i, cache, w.y, w.x_true, w.n, w.n_angles, w.n_bins, rho=RHO)
+            for i, w in enumerate(make_batch_item(i) for i in range(64))]
+    for _ in range(2):
+        r = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4, graph=False)
+    dev = torch.device("cuda:0")
+    a = torch.ones(16 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"batched counter workload done: shapes={shapes} solves={len(r.latency_s)} "
+        f"{r.recons_per_s:.1f} recons/s")
+    cache.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +376,8 @@ def main():
     ap.add_argument("--counter-workload", metavar="SHAPES",
                     help="run only the hardware-counter workload with these launch shapes "
                          "(project_groups,backproject_split,project_angles,swizzle)")
+    ap.add_argument("--batched-counter-workload", metavar="SHAPES",
+                    help="run only the batched (64-solve) hardware-counter workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
@@ -283,6 +385,9 @@ def main():
         sys.exit(2)
     if args.counter_workload:
         counter_workload([int(v) for v in args.counter_workload.split(",")])
+        return
+    if args.batched_counter_workload:
+        batched_counter_workload([int(v) for v in args.batched_counter_workload.split(",")])
         return
 
     import numpy as np
@@ -398,6 +503,8 @@ def main():
         },
     }
     result["three_operator"] = three_operator_run(plan, y, params, out, ws, stream, w, args.steps)
+    result["s_pcg"] = spcg_run(plan, y, params, ws, stream, w, args.steps)
+    log(f"s_pcg: {result['s_pcg']}")
     if not args.no_mix:
         shape = (tuning["project_groups"], tuning["backproject_split"],
                  tuning["project_angles"], tuning["swizzle"])

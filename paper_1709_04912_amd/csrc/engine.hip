@@ -308,17 +308,24 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
     }
     e.finish(kFinTrials, 0);
     if (g.any_trB) {
-        // the second trial launch (it runs only where the first accepted no
-        // step) applies its own trial decision in its last block
-        Prof t(g.prof, SCG_KC_TRIALS, s);
-        launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
+        // the second trial launch and its finisher return at once where the
+        // first launch accepted a step
+        {
+            Prof t(g.prof, SCG_KC_TRIALS, s);
+            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
+        }
+        e.finish(kFinTrials, kTrialsPerPass);
     }
     {
         Prof t(g.prof, SCG_KC_VECTOR, s);
         launch_b_perturb<T>(g.S, e.m(kKT32), e.n(kKT32), s);
     }
-    e.project(kPjResXh);
-    e.finish(kFinResidualStep);
+    // S-CG, S-CG-CD, S-PCG: the direction update takes the step's loop test
+    // (no finisher); the others test in a finisher
+    const bool fused_stop = g.variant == SCG_S_CG || g.variant == SCG_S_CG_CD ||
+                            g.variant == SCG_S_PCG;
+    e.project(fused_stop ? kPjResXhF : kPjResXh);
+    if (!fused_stop) e.finish(kFinResidualStep);
     if (g.variant == SCG_S_CG_K) {
         // CG-K from x_{k+1/2} (copied into x by the perturbation): g0 =
         // A^T r (r formed above), p0 = -g0, delta0 = ||g0||^2, then K

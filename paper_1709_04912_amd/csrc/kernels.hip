@@ -137,12 +137,9 @@ __device__ void block_store(const A (&v)[NV], double *dst)
 // first <= k < NV, through LDS: one row per value, eight lanes per row, each
 // lane summing a fixed stride-8 subset in order and a three-step butterfly
 // joining the eight (many values cost a few LDS passes instead of a shuffle
-// tree each). Every thread of the block must call this. With `publish`, every
-// thread that stored a sum issues a device-scope fence before the closing
-// barrier, so the block's sums are visible to other blocks before any
-// thread of the block signals its arrival.
+// tree each). Every thread of the block must call this.
 template <int NV, typename A>
-__device__ void block_store_rows(const A (&v)[NV], double *dst, int first, bool publish = false)
+__device__ void block_store_rows(const A (&v)[NV], double *dst, int first)
 {
     static_assert(NV * 8 <= kBlock, "eight lanes per value");
     constexpr int S = kBlock + 8;   // row stride: the next row's lanes start 8 banks on
@@ -158,10 +155,7 @@ __device__ void block_store_rows(const A (&v)[NV], double *dst, int first, bool 
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 4, 64);
-    if (k < NV && k >= first && p == 0) {
-        gl(dst)[k] = acc;
-        if (publish) __threadfence();
-    }
+    if (k < NV && k >= first && p == 0) gl(dst)[k] = acc;
     __syncthreads();
 }
 
@@ -738,7 +732,8 @@ __global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, co
     const T *y = (q || u) ? nullptr : d.y;
     T *out = q ? d.q : (u ? d.rt : d.r);
     const T *dv = u ? d.q : nullptr;
-    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, dv, d.partials, vb);
+    double *part = phase == kPjResXhF ? d.partials2 : d.partials;
+    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, dv, part, vb);
 }
 
 template <typename T>
@@ -1297,17 +1292,15 @@ void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t
 
 // ---------------------------------------------------------------------------
 // perturbed(): the trials of one step, TV(x + gamma_m v) for gamma_m =
-// gtab[m] (gamma0 a^(l+m)) and v = -s/||s||, in two launches. The first
-// evaluates trials 0..kTrialsPerPass-1 together with TV(x), summed in the
-// same order; the second, which returns at once when the first accepted,
-// evaluates the remaining ones up to max_trials in chunks of kTrialsPerPass.
-// The finisher takes the first m with TV(x + gamma_m v) <= TV(x), exactly as
-// trying the values one after another; l advances by the trials used.
-// Partials per block: [TV(x), trial first_m, first_m + 1, ...].
+// gtab[m] (gamma0 a^(l+m)) and v = -s/||s||, in two launches, each followed
+// by a finisher. The first evaluates trials 0..kTrialsPerPass-1 together
+// with TV(x), summed in the same order; the second, which returns at once
+// when the first accepted, evaluates the remaining ones up to max_trials in
+// chunks of kTrialsPerPass. The finisher takes the first m with
+// TV(x + gamma_m v) <= TV(x), exactly as trying the values one after
+// another; l advances by the trials used. Partials per block: [TV(x), trial
+// first_m, first_m + 1, ...].
 // ---------------------------------------------------------------------------
-
-template <typename T>
-__device__ void finish_body(const Solve<T> *S, int solve, int fin, int arg0, int arg1);
 
 template <typename T>
 __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, const Geo &G,
@@ -1355,7 +1348,7 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
         vals[0] = acc[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) vals[1 + m] = acc[m];
-        block_store_rows(vals, dst, c == 0 ? 0 : 1, !with_tvx);
+        block_store_rows(vals, dst, c == 0 ? 0 : 1);
     }
 }
 
@@ -1371,26 +1364,6 @@ __global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap
     const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
     trials_body(d.x, d.s, d.G, d.gtab, d.partials, d.st, first_m, nchunks,
                 vblk_of(m.local, nblk, 1));
-    if (first_m == 0) return;
-    // The second launch, which runs only after the first one found no
-    // acceptable step, decides its own trials: the last of the solve's blocks
-    // to store its sums (an arrival count) applies the finisher's trial
-    // logic. Every thread that stored a sum fenced at device scope before
-    // the block's barrier (block_store_rows with publish), so all of the
-    // block's sums are visible before thread 0 counts its arrival; the last
-    // block fences again before it reads the others' sums. A step whose
-    // first launch accepted returns above, so it pays neither a finisher
-    // launch nor any fence here.
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int arrived = atomicAdd(&d.st->trB_arrived, 1);
-        s_last = arrived == nblk - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    finish_body(S, m.solve, kFinTrials, first_m, 0);
 }
 
 template <typename T>
@@ -1523,6 +1496,28 @@ __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkM
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     auto *st = gl(d.st);
+    if (rec) {
+        // The step's loop test, f(x_{k+1/2}) <= eps, with f from the
+        // residual projection's partials (kPjResXhF): every block forms the
+        // same f; the solve's first block records it and, when the test
+        // holds (or f is not finite), ends the solve at k + 1 with output
+        // x_{k+1/2}: the rest of the step cannot change the output and is
+        // skipped.
+        const double f = 0.5 * block_sum1(d.partials2, d.nb_pj);
+        const bool stop = !isfinite(f) || f <= st->eps;
+        if (m.local == 0 && threadIdx.x == 0) {
+            st->f_half = f;
+            if (auto *tr = trace_at(st, d.trace)) tr->f_half = f;
+            if (!isfinite(f)) {
+                set_done(st, SCG_ENAN);
+            } else if (stop) {
+                st->steps += 1;
+                st->k += 1;
+                set_done(st, SCG_OK);
+            }
+        }
+        if (stop) return;
+    }
     // beta of rules 0-2 from the backprojection's dot partials, of the
     // others from the state
     double beta = beta_of(st, rule, init);
@@ -1975,7 +1970,6 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         final_sums(d.partials, nblk, stride, stride, tot);
         if (threadIdx.x != 0) return;   // the block's other threads are done
         const bool with_tvx = first_m == 0;
-        if (!with_tvx) st->trB_arrived = 0;   // ready for the next step's launch
         const double tvx = with_tvx ? tot[0] : st->tv_x;
         if (with_tvx) st->tv_x = tvx;
         const int left = st->max_trials - first_m;

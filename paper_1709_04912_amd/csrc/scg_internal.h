@@ -111,7 +111,7 @@ struct DevState {
     // perturbation
     int ell, trials_step, accepted, search_done;
     int trials_total, forced_len, trace_cap;
-    int trB_arrived;   // blocks of the second trial launch that have stored their sums
+    int reserved0;
     double tv_x, s_norm2, inv_snorm, gamma;
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;
@@ -139,7 +139,7 @@ template <typename T> struct Solve {
     T *xout;                    // caller's output image
     double *partials;           // block partial sums of the last reduction
     double *partials2;          // partial sums of the TV pass (it reads the other
-                                // region's sums)
+                                // region's sums) and of ||r||^2 of the step's residual
     double *partials3;          // partials of g'^T p' of the direction update,
                                 // read by the TV pass that forms alpha
     double *gtab;               // gamma0 a^(l+m), m < max_trials
@@ -185,6 +185,9 @@ enum Phase : int {
     kPjU = 8,         // u = A g' into rt, partials of u^T q (S-CG, three operators)
     kBpGT = 9,        // g = A^T r and xs = g^T (S-CG, three operators)
     kBpZ = 10,        // z = A^T rt, partials of z^T g (PCG steps)
+    kPjResXhF = 11,   // r = A x_{k+1/2} - y with the partials of ||r||^2 in partials2:
+                      // the direction update after it forms f and takes the stop test
+                      // (S-CG, S-CG-CD, S-PCG)
 };
 
 // Finishers: one block per solve sums the partials of the previous launch
