@@ -145,7 +145,7 @@ typedef struct scg_plan scg_plan;
  * n_angles / 4 * ceil(n_bins / 128)), SCG_ENOMEM, SCG_EDEVICE. The
  * preconditioning filter (SCG_S_PCG, SCG_PCG, SCG_S_PCG_K, scg_filter)
  * transforms P = 2^ceil(log2(2 n_bins)) complex points in LDS: it needs
- * n_bins <= 4096 in SCG_F32 and n_bins <= 2048 in SCG_F64 and returns
+ * n_bins <= 8192 in SCG_F32 and n_bins <= 4096 in SCG_F64 and returns
  * SCG_EINVAL otherwise. Its tables are allocated here, so solves allocate
  * nothing for it. */
 int scg_plan_create(const scg_geom *g, int device, scg_plan **out);

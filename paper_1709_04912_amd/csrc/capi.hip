@@ -220,6 +220,10 @@ int filter_pad(int nb)
     return P;
 }
 
+// Elements of a filter table: P spectrum values and the P - 1 complex
+// twiddles of the spans 1, 2, ..., P/2.
+size_t filter_table_len(int P) { return (size_t)P + 2 * (size_t)(P - 1); }
+
 // Spectrum of the preconditioning filter at the transform's bit-reversed
 // positions: c(w_k) / P with w_k = 2 pi k / P taken in [-pi, pi), k the
 // frequency stored at position i (k = bit reverse of i over log2 P bits),
@@ -244,14 +248,15 @@ int upload_filter(scg_plan *p, int pi, double mu, bool twiddles)
     const int P = filter_pad(p->G.nb);
     std::vector<double> sp;
     filter_spectrum(P, mu, sp);
-    std::vector<T> tab(twiddles ? 2 * (size_t)P : (size_t)P);
+    std::vector<T> tab(twiddles ? filter_table_len(P) : (size_t)P);
     for (int i = 0; i < P; ++i) tab[i] = (T)sp[i];
     if (twiddles)
-        for (int m = 0; m < P / 2; ++m) {
-            const double w = -2.0 * kPi * m / P;
-            tab[P + 2 * m] = (T)std::cos(w);
-            tab[P + 2 * m + 1] = (T)std::sin(w);
-        }
+        for (int h = 1; h < P; h <<= 1)
+            for (int j = 0; j < h; ++j) {
+                const double w = -kPi * j / h;   // e^{-2 pi i j / (2h)}
+                tab[P + 2 * (h - 1 + j)] = (T)std::cos(w);
+                tab[P + 2 * (h - 1 + j) + 1] = (T)std::sin(w);
+            }
     HIP_TRY(hipMemcpy(p->ftab[pi], tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice));
     p->filt_mu[pi] = mu;
     return SCG_OK;
@@ -579,13 +584,15 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
     // only the spectrum, without allocating
     const double mu0 = 2.0 * kPi / filter_pad(G.nb);
     if (rc == SCG_OK && scg::filter_fits(G.nb, SCG_F32)) {
-        if (hipMalloc(&p->ftab[0], 2 * (size_t)filter_pad(G.nb) * sizeof(float)) != hipSuccess)
+        if (hipMalloc(&p->ftab[0], filter_table_len(filter_pad(G.nb)) * sizeof(float)) !=
+            hipSuccess)
             rc = SCG_ENOMEM;
         else
             rc = upload_filter<float>(p, 0, mu0, true);
     }
     if (rc == SCG_OK && scg::filter_fits(G.nb, SCG_F64)) {
-        if (hipMalloc(&p->ftab[1], 2 * (size_t)filter_pad(G.nb) * sizeof(double)) != hipSuccess)
+        if (hipMalloc(&p->ftab[1], filter_table_len(filter_pad(G.nb)) * sizeof(double)) !=
+            hipSuccess)
             rc = SCG_ENOMEM;
         else
             rc = upload_filter<double>(p, 1, mu0, true);

@@ -156,6 +156,11 @@ template <typename T> struct Enq {
         Prof t(g.prof, SCG_KC_CONTROL, s);
         launch_finish<T>(g.S, g.ns, fin, a0, a1, s);
     }
+    // A single solve's launches form the scalars they need from the previous
+    // launch's partials in every block; a batch of many solves has a
+    // finisher form them once per solve (the same sums, the same bits), so
+    // that its blocks do not each reread the partials.
+    bool given() const { return g.ns > 1; }
     void p_update(int rule, int init) const
     {
         // S-CG, S-CG-CD, S-PCG after the initial step: the update records beta
@@ -164,11 +169,21 @@ template <typename T> struct Enq {
         const bool rec = !init && rule <= 2 &&
                          (g.variant == SCG_S_CG || g.variant == SCG_S_CG_CD ||
                           g.variant == SCG_S_PCG);
+        if (rec && given()) finish(kFinStepScalars, rule);
         {
             Prof t(g.prof, SCG_KC_VECTOR, s);
-            launch_b_p_update<T>(g.S, m(kKT32), n(kKT32), rule, init, rec ? 1 : 0, s);
+            launch_b_p_update<T>(g.S, m(kKT32), n(kKT32), rule, init, rec ? 1 : 0,
+                                 rec && given() ? 1 : 0, s);
         }
         if (!rec) finish(kFinPUpdate, rule, init);
+    }
+    void xtv() const
+    {
+        const bool local = g.variant == SCG_S_CG || g.variant == SCG_S_CG_CD ||
+                           g.variant == SCG_S_PCG;
+        if (local && given()) finish(kFinAlpha);
+        Prof t(g.prof, SCG_KC_TV, s);
+        launch_b_xtv<T>(g.S, m(kKXtv), n(kKXtv), local && given() ? 1 : 0, s);
     }
     void pq_update() const
     {
@@ -297,10 +312,7 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
         e.finish(kFinResidual);
         return;
     }
-    {
-        Prof t(g.prof, SCG_KC_TV, s);
-        launch_b_xtv<T>(g.S, e.m(kKXtv), e.n(kKXtv), s);
-    }
+    e.xtv();
     e.finish(kFinXtv);
     {
         Prof t(g.prof, SCG_KC_TRIALS, s);

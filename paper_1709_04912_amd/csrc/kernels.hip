@@ -1265,7 +1265,7 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *map)
+__global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *map, int given)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
@@ -1273,9 +1273,9 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     const auto *st = gl(d.st);
     // alpha of the open step: from the direction update's and the
     // projection's partials (recorded by this pass's finisher) or from the
-    // state
+    // state (given: a finisher formed it there with the same sums)
     double alpha = st->alpha;
-    if (local_alpha(st->variant) && st->open) {
+    if (!given && local_alpha(st->variant) && st->open) {
         double gp, qq;
         block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
         alpha = -gp / qq;
@@ -1285,9 +1285,9 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
 }
 
 template <typename T>
-void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s)
+void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_xtv<T>, dim3(nblocks), dim3(256), 0, s, S, map);
+    hipLaunchKernelGGL(kb_xtv<T>, dim3(nblocks), dim3(256), 0, s, S, map, given);
 }
 
 // ---------------------------------------------------------------------------
@@ -1489,13 +1489,20 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
 
 template <typename T>
 __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkMap *map,
-                                                    int rule, int init, int rec)
+                                                    int rule, int init, int rec, int given)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     auto *st = gl(d.st);
+    if (given) {
+        // a finisher (kFinStepScalars) took the stop test and left beta in
+        // the state: the same sums, so the same bits
+        p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init, st->beta,
+                      vblk_of(m.local, nt, nt));
+        return;
+    }
     if (rec) {
         // The step's loop test, f(x_{k+1/2}) <= eps, with f from the
         // residual projection's partials (kPjResXhF): every block forms the
@@ -1541,9 +1548,10 @@ __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkM
 
 template <typename T>
 void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
-                       int rec, hipStream_t s)
+                       int rec, int given, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init, rec);
+    hipLaunchKernelGGL(kb_p_update<T>, dim3(nblocks), dim3(256), 0, s, S, map, rule, init, rec,
+                       given);
 }
 
 // S-CG with three operators: q' = -u + beta q over sinogram row a (u = A g'
@@ -1702,8 +1710,10 @@ void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hip
 // reversed order out), the spectrum multiplied in that order (the table is
 // stored bit-reversed, with 1/P folded in), then radix-2 decimation in time
 // from bit-reversed order back to natural order with conjugate twiddles, so
-// no reordering pass is needed. Table layout: P spectrum values, then P/2
-// twiddles e^{-2 pi i m / P} as (re, im) pairs.
+// no reordering pass is needed. Table layout: P spectrum values, then the
+// twiddles of each butterfly span h = 1, 2, 4, ..., P/2 in turn,
+// e^{-2 pi i j / (2h)} for j < h as (re, im) pairs from offset h - 1: the
+// lanes of a stage read consecutive entries.
 // ---------------------------------------------------------------------------
 
 template <typename T> struct Cx {
@@ -1723,7 +1733,8 @@ __device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
     auto *out = gl(out_);
     const auto *spec = gl(tab_);
     const int nb = G.nb, P = filter_len(nb), half = P >> 1;
-    const auto *tw = reinterpret_cast<const Cx<T> *>(spec + P);
+    // span h's twiddles at tw[h + j], j < h
+    const auto *tw = gl(reinterpret_cast<const Cx<T> *>(tab_ + P) - 1);
     extern __shared__ unsigned char smem[];
     Cx<T> *z = reinterpret_cast<Cx<T> *>(smem);
     const int a0 = 2 * pair, a1 = a0 + 1;
@@ -1741,12 +1752,12 @@ __device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
     }
     __syncthreads();
     // forward transform: butterflies of span h, twiddle e^{-2 pi i j / (2h)}
-    for (int h = half, ts = 1; h >= 1; h >>= 1, ts <<= 1) {
+    for (int h = half; h >= 1; h >>= 1) {
         for (int k = threadIdx.x; k < half; k += blockDim.x) {
             const int j = k & (h - 1);
             const int i = ((k - j) << 1) + j;
             const Cx<T> u = z[i], v = z[i + h];
-            const Cx<T> w = tw[j * ts];
+            const Cx<T> w = tw[h + j];
             const T dx = u.x - v.x, dy = u.y - v.y;
             z[i] = Cx<T>{u.x + v.x, u.y + v.y};
             z[i + h] = Cx<T>{dx * w.x - dy * w.y, dx * w.y + dy * w.x};
@@ -1759,12 +1770,12 @@ __device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
     }
     __syncthreads();
     // inverse transform: span h, twiddle e^{+2 pi i j / (2h)}
-    for (int h = 1, ts = half; h < P; h <<= 1, ts >>= 1) {
+    for (int h = 1; h < P; h <<= 1) {
         for (int k = threadIdx.x; k < half; k += blockDim.x) {
             const int j = k & (h - 1);
             const int i = ((k - j) << 1) + j;
             const Cx<T> u = z[i], v = z[i + h];
-            const Cx<T> w = tw[j * ts];
+            const Cx<T> w = tw[h + j];
             const Cx<T> t{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
             z[i] = Cx<T>{u.x + t.x, u.y + t.y};
             z[i + h] = Cx<T>{u.x - t.x, u.y - t.y};
@@ -1782,7 +1793,7 @@ __device__ void filter_body(const T *__restrict__ r_, T *__restrict__ out_,
     }
 }
 
-// LDS bytes of the filter for n_bins bins in precision T.
+// LDS bytes of the filter for n_bins bins in precision T: the sequence.
 template <typename T> size_t filter_lds(int nb)
 {
     int P = 1;
@@ -1790,25 +1801,41 @@ template <typename T> size_t filter_lds(int nb)
     return (size_t)P * sizeof(Cx<T>);
 }
 
+// Threads per filter block: up to P/2 = 1024 butterflies per stage each in
+// a thread of its own (P = 2048 at 729 bins), more in turn.
+constexpr int kFilterThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(const T *__restrict__ r, T *__restrict__ out,
+__global__ __launch_bounds__(kFilterThreads) void k_filter(const T *__restrict__ r, T *__restrict__ out,
                                                  const T *__restrict__ tab, Geo G,
                                                  int out_padded)
 {
     filter_body(r, out, tab, G, out_padded, (int)blockIdx.x);
 }
 
+// Allows the filter kernels more than 64 KB of dynamic LDS (gfx950 has 160
+// KB per workgroup); once per process and device is enough, but repeating
+// it is harmless.
+template <typename T> void allow_filter_lds(const void *kernel, size_t bytes)
+{
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kFilterLds);
+}
+
 template <typename T>
 void launch_filter(const T *r, T *out, const T *tab, const Geo &G, int out_padded,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_filter<T>, dim3((G.na + 1) / 2), dim3(256), filter_lds<T>(G.nb), s, r,
-                       out, tab, G, out_padded);
+    const size_t shm = filter_lds<T>(G.nb);
+    allow_filter_lds<T>(reinterpret_cast<const void *>(&k_filter<T>), shm);
+    hipLaunchKernelGGL(k_filter<T>, dim3((G.na + 1) / 2), dim3(kFilterThreads), shm, s, r, out,
+                       tab, G, out_padded);
 }
 
 // r~ = F^T C F r of every solve (rt, padded), one block per pair of angles.
 template <typename T>
-__global__ __launch_bounds__(256) void kb_filter(const Solve<T> *S, const BlkMap *map)
+__global__ __launch_bounds__(kFilterThreads) void kb_filter(const Solve<T> *S, const BlkMap *map)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
@@ -1820,8 +1847,9 @@ template <typename T>
 void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_nb,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_filter<T>, dim3(nblocks), dim3(256), filter_lds<T>(max_nb), s, S,
-                       map);
+    const size_t shm = filter_lds<T>(max_nb);
+    allow_filter_lds<T>(reinterpret_cast<const void *>(&kb_filter<T>), shm);
+    hipLaunchKernelGGL(kb_filter<T>, dim3(nblocks), dim3(kFilterThreads), shm, s, S, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -2003,6 +2031,43 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
                 tr->tv_x = tvx;
             }
         }
+        return;
+    }
+    case kFinAlpha: {
+        // alpha of the open step for the TV pass (local-alpha variants); the
+        // TV pass's finisher records it
+        if (!(local_alpha(st->variant) && st->open)) return;
+        double gp, qq;
+        block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
+        if (threadIdx.x == 0) st->alpha = -gp / qq;
+        return;
+    }
+    case kFinStepScalars: {
+        // arg0 = rule (0-2): the loop test on f(x_{k+1/2}) from the residual
+        // projection's partials and beta from the backprojection's dot, as
+        // the direction update's blocks form them in a single solve
+        const double f = 0.5 * block_sum1(d.partials2, d.nb_pj);
+        const double dot = block_sum1(d.partials, d.nb_bp);
+        if (threadIdx.x != 0) return;   // the block's other threads are done
+        st->f_half = f;
+        if (auto *tr = trace_at(st, d.trace)) tr->f_half = f;
+        if (!isfinite(f)) {
+            set_done(st, SCG_ENAN);
+            return;
+        }
+        if (f <= st->eps) {
+            st->steps += 1;
+            st->k += 1;
+            set_done(st, SCG_OK);
+            return;
+        }
+        const int rule = arg0;
+        const double beta = rule == 1 ? -dot / st->gp_prev : dot / st->qq_prev;
+        if (rule == 1) st->gg = dot;
+        else st->gh = dot;
+        st->beta = beta;
+        if (!isfinite(beta)) set_done(st, SCG_ENAN);
+        if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
         return;
     }
     case kFinXtv: {
@@ -2194,11 +2259,11 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
                                       int, hipStream_t);                                        \
     template void launch_b_backproject<T>(const Solve<T> *, const BlkMap *, int, int, int,     \
                                           int, int, hipStream_t);                               \
-    template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);         \
+    template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t);    \
     template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
     template void launch_b_perturb<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);     \
     template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int, int,   \
-                                       hipStream_t);                                            \
+                                       int, hipStream_t);                                       \
     template void launch_b_x_update_cg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \
     template void launch_b_pq_update<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);   \
     template void launch_b_x_update_pcg<T>(const Solve<T> *, const BlkMap *, int, hipStream_t); \

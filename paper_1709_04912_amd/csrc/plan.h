@@ -33,8 +33,8 @@ struct scg_plan {
     // (a read into pinned memory is one DMA, not a staged pageable copy)
     void *host_pinned = nullptr;
     // preconditioning filter per precision: P spectrum values at bit-reversed
-    // positions, then P/2 twiddles (null where the transform exceeds the LDS
-    // bound)
+    // positions, then the twiddles of each butterfly span (null where the
+    // transform exceeds the LDS bound)
     void *ftab[2] = {nullptr, nullptr};
     scg_tuning tune[2] = {{4, 4, 8, 0}, {4, 2, 8, 0}};  // launch shapes (F32, F64)
     double filt_mu[2] = {-1.0, -1.0};      // mu of each precision's spectrum

@@ -45,9 +45,9 @@ constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPa
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
 constexpr int kMaxN = 2880;          // largest accepted image side
 // LDS of the preconditioning filter: one complex sequence of P =
-// 2^ceil(log2(2 n_bins)) points per block, so n_bins <= 4096 (FP32) and
-// n_bins <= 2048 (FP64)
-constexpr size_t kFilterLds = 65536;
+// 2^ceil(log2(2 n_bins)) points per block, within gfx950's 160 KB per
+// workgroup, so n_bins <= 8192 (FP32) and n_bins <= 4096 (FP64)
+constexpr size_t kFilterLds = 163840;
 constexpr int kMaxT32Blocks = 8192;  // 32 x 32 image tiles (direction update blocks)
 constexpr size_t kHostPinnedBytes = 4096;   // a plan's pinned host words
 constexpr size_t kPinnedStagingOffset = 2048;   // where a solve's upload images sit in them
@@ -208,6 +208,11 @@ enum Fin : int {
     kFinDotUQ = 12,        // (A g')^T q (S-CG, three operators)
     kFinPQ = 13,           // beta, g^T p, ||q||^2 and alpha of the p and q updates
     kFinDeltaPCG = 14,     // PCG: delta' = g^T z and the step count
+    // Scalars a batched launch's blocks would otherwise each form from the
+    // partials (the same sums, so the same bits): alpha for the TV pass, and
+    // f with the stop test and beta for the direction update
+    kFinAlpha = 15,
+    kFinStepScalars = 16,
 };
 
 // Block counts of the solver kernels for one solve.
@@ -250,7 +255,8 @@ template <typename T>
 void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase,
                           int dot, int split, int swz, hipStream_t s);
 template <typename T>
-void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
+void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given,
+                  hipStream_t s);
 template <typename T>
 void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m,
                      hipStream_t s);
@@ -258,7 +264,7 @@ template <typename T>
 void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 template <typename T>
 void launch_b_p_update(const Solve<T> *S, const BlkMap *map, int nblocks, int rule, int init,
-                       int rec, hipStream_t s);
+                       int rec, int given, hipStream_t s);
 template <typename T>
 void launch_b_x_update_cg(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
 // p' = -g' + beta p (blocks [0, nb_t32)) and q' = -u + beta q (the next

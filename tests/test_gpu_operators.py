@@ -122,29 +122,34 @@ def test_filter(scg, torch_mod, oracle_lib, geom):
 
 
 def test_filter_bin_limits(scg, torch_mod, oracle_lib):
-    """The transform of P = 2^ceil(log2(2 n_bins)) complex points fits 64 KB
-    of LDS up to 4096 bins in FP32 (checked against the oracle there) and
-    2048 in FP64; beyond, the filter and the filtered solvers are refused."""
+    """The transform of P = 2^ceil(log2(2 n_bins)) complex points and its
+    twiddle table fit gfx950's 160 KB of LDS per workgroup up to 8192 bins
+    in FP32 and 4096 in FP64 (both checked against the oracle at the
+    limit); beyond, the filter and the filtered solvers are refused."""
     torch = torch_mod
-    g = oracle_lib.Geometry(8, 3, 4096)
-    rng = np.random.default_rng(4096)
-    r = rng.standard_normal(3 * 4096)
-    with scg.Plan(8, 3, 4096) as plan:
-        out = plan.filter(torch.tensor(r, dtype=torch.float32, device="cuda")).cpu().numpy()
-        assert _rel(out, g.filter(r)) <= 1e-5
+    for nb, tol_ok in ((8192, ((torch.float32, 1e-5),)),
+                       (4096, ((torch.float32, 1e-5), (torch.float64, 1e-12)))):
+        g = oracle_lib.Geometry(8, 3, nb)
+        r = np.random.default_rng(nb).standard_normal(3 * nb)
+        ref = g.filter(r)
+        with scg.Plan(8, 3, nb) as plan:
+            for dt, tol in tol_ok:
+                out = plan.filter(torch.tensor(r, dtype=dt, device="cuda")).cpu().numpy()
+                assert _rel(out, ref) <= tol, (nb, dt)
+            if nb == 8192:
+                with pytest.raises(scg.ScgError):
+                    plan.filter(torch.tensor(r, dtype=torch.float64, device="cuda"))
+    with scg.Plan(8, 3, 8193) as plan:
         with pytest.raises(scg.ScgError):
-            plan.filter(torch.tensor(r, dtype=torch.float64, device="cuda"))
-    with scg.Plan(8, 3, 4097) as plan:
+            plan.filter(torch.zeros(3 * 8193, dtype=torch.float32, device="cuda"))
         with pytest.raises(scg.ScgError):
-            plan.filter(torch.zeros(3 * 4097, dtype=torch.float32, device="cuda"))
-        with pytest.raises(scg.ScgError):
-            plan.solve(torch.zeros(3 * 4097, dtype=torch.float32, device="cuda"),
+            plan.solve(torch.zeros(3 * 8193, dtype=torch.float32, device="cuda"),
                        plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", max_iter=1),
                        trace=False)
-    with scg.Plan(8, 3, 2049) as plan:
+    with scg.Plan(8, 3, 4097) as plan:
         with pytest.raises(scg.ScgError):
-            plan.filter(torch.zeros(3 * 2049, dtype=torch.float64, device="cuda"))
-        y = torch.zeros(3 * 2049, dtype=torch.float64, device="cuda")
+            plan.filter(torch.zeros(3 * 4097, dtype=torch.float64, device="cuda"))
+        y = torch.zeros(3 * 4097, dtype=torch.float64, device="cuda")
         with pytest.raises(scg.ScgError):
             plan.solve(y, plan.params(eps=1.0, gamma0=0.0, variant="PCG", prec=scg.SCG_F64,
                                       max_iter=1), trace=False)
@@ -249,8 +254,8 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
 
 def test_size_limits(scg, torch_mod, oracle_lib):
     """The largest accepted image (N = 2880) with a detector of 4076 bins, on sampled rays
-    and pixels against the oracle, and its FP32 filter; one pixel more is
-    rejected; the FP64 filter (only) rejects more than 2048 bins."""
+    and pixels against the oracle, and its filter in both precisions; one
+    pixel more is rejected."""
     torch = torch_mod
     n, na, nb = 2880, 6, 4076
     print(f"[limits] N={n} angles={na} bins={nb}", flush=True)
@@ -265,13 +270,9 @@ def test_size_limits(scg, torch_mod, oracle_lib):
         ax = plan.project(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
         aty = plan.backproject(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         filt = plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
-        with pytest.raises(scg.ScgError):
-            plan.filter(torch.tensor(y, dtype=torch.float64, device="cuda"))
-        with pytest.raises(scg.ScgError):
-            plan.solve(torch.tensor(y, dtype=torch.float64, device="cuda"),
-                       plan.params(eps=1.0, gamma0=0.0, variant="S_PCG", prec=scg.SCG_F64,
-                                   max_iter=1), trace=False)
-    assert _rel(filt, g.filter(y)) <= 1e-5
+        filt64 = plan.filter(torch.tensor(y, dtype=torch.float64, device="cuda")).cpu().numpy()
+    fref = g.filter(y)
+    assert _rel(filt, fref) <= 1e-5 and _rel(filt64, fref) <= 1e-12
     assert _rel(ax[rays], g.project_rays(x, rays)) <= 1e-5
     assert _rel(aty[pix], g.backproject_pixels(y, pix)) <= 1e-5
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()

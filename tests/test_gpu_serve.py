@@ -67,3 +67,31 @@ def test_admission_waits_for_room(stream):
                             keep_outputs=True)
     assert len(b.reports) == len(reqs)
     _same(serve, p, b)
+
+
+def test_size_aware_engines_and_ls_eps(stream):
+    """Requests of the largest size on an engine of their own, stepped in
+    alternation with the others, and stopping values eps = 1.05 eps0_hat
+    (eps0_hat: f after a run of plain CG): every request still gets its plain
+    result, and the ls rule's eps lies above the CG value it came from."""
+    from paper_1709_04912_amd import scg
+    serve, reqs = stream
+    cache = serve.PlanCache(shape=(4, 4, 4, 0))
+    items = [make_serve_item(i, shapes=SHAPES) for i in range(8)]
+    base = [serve.make_request(i, cache, w.y, w.x_true, w.n, w.n_angles, w.n_bins,
+                               eps_rule="ls", ls_steps=60) for i, w in enumerate(items)]
+    arr = poisson_arrivals(11, 16, 400.0)
+    reqs2 = [serve.Request(i, base[i % 8].plan, base[i % 8].y, base[i % 8].params,
+                           float(arr[i])) for i in range(16)]
+    for r in base:
+        _, rep, _ = r.plan.solve(r.y, r.plan.params(eps=1e-300, gamma0=0.0, variant="CG",
+                                                    max_iter=60), trace=False)
+        assert abs(r.params.eps - 1.05 * rep.f_out) <= 1e-12 * r.params.eps
+    p = serve.serve_plain(reqs2, keep_outputs=True)
+    b = serve.serve_batched(reqs2, arena_bytes=1 << 30, max_slots=16, iters=3,
+                            keep_outputs=True, large_n=64, large_iters=1)
+    assert any(r.n >= 64 for r in reqs2) and any(r.n < 64 for r in reqs2)
+    assert len(b.reports) == len(reqs2)
+    assert all(r.status == scg.SCG_OK for r in b.reports.values())
+    _same(serve, p, b)
+    cache.close()
