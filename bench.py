@@ -53,6 +53,7 @@ ARENA = 16 << 30                   # batch engine arena (bytes of HBM)
 SERVE_POOL = 100                   # distinct requests of the served streams
 LS_FACTOR, LS_STEPS = 1.05, 400    # served eps = LS_FACTOR x f after LS_STEPS CG iterations
 FULL_SOLVE_S = 60.0                # the oracle's 512x512 solve is timed whole below this
+PROFILE_EVERY = 8                  # timed solves: events around one dominant launch in 8
 
 
 def log(msg):
@@ -211,7 +212,7 @@ def mixed_runs(n_serve, shape):
     runs = {"graph": [], "eager": [], "plain": []}
     for _ in range(2):
         runs["graph"].append(serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4,
-                                                 keep_outputs=True))
+                                                 graph=True, keep_outputs=True))
         runs["eager"].append(serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=256, iters=4,
                                                  graph=False, keep_outputs=True))
         runs["plain"].append(serve.serve_plain(reqs, keep_outputs=True))
@@ -224,6 +225,9 @@ def mixed_runs(n_serve, shape):
         "speedup": b.recons_per_s / p.recons_per_s,
         "batched_without_graph_recons_per_s": be.recons_per_s,
         "bitwise_equal_outputs": same(p, b), "bitwise_equal_without_graph": same(p, be),
+        "graph_engine_stats": {k: b.engine_stats[0][k] for k in
+                               ("macro_steps", "graph_builds", "graph_updates", "rebuild_ns")},
+        "eager_engine_stats": {k: be.engine_stats[0][k] for k in ("macro_steps", "rebuild_ns")},
         "solves": len(reqs), "launch_shape": list(shape),
         "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports))}
     log(f"batched: {batched}")
@@ -242,7 +246,9 @@ def mixed_runs(n_serve, shape):
                      f"eps = {LS_FACTOR} eps0_hat, eps0_hat = f after {LS_STEPS} CG iterations "
                      f"(an upper bound of the least-squares floor); {pool} distinct requests, "
                      f"the stream takes them in turn"),
-        "launch_shape": list(shape)}
+        "launch_shape": list(shape),
+        "size_aware": "1024x1024 requests on an engine of their own (2 slots), 4 iterations of "
+                      "it alternating with 4 of the other engine (64 slots)"}
     for tag, rate, seed in (("as_specified_200_per_s", 200.0, 5000),
                             ("sustainable_20_per_s", 20.0, 5001)):
         arr = poisson_arrivals(seed, n_serve, rate)
@@ -250,7 +256,8 @@ def mixed_runs(n_serve, shape):
                               float(arr[i])) for i in range(n_serve)]
         log(f"served {tag}: {n_serve} requests")
         bs = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=64, iters=4,
-                                 keep_outputs=True, large_n=1024, large_iters=1)
+                                 keep_outputs=True, large_n=1024, large_iters=4,
+                                 large_slots=2)
         p = serve.serve_plain(reqs, keep_outputs=True)
         run = {"requests": n_serve, "rate_per_s": rate,
                "batched_size_aware": bs.summary(reqs), "plain": p.summary(reqs),
@@ -448,8 +455,9 @@ def main():
         f"eps={eps:.6g}")
     dominant = max(("project", "backproject"), key=lambda c: prof_all[c][1])
 
-    # timed solves (events only around the dominant kernel)
-    plan.profile((dominant,))
+    # timed solves: events around one launch in PROFILE_EVERY of the dominant
+    # kernel (an event between two launches delays the second by a few us)
+    plan.profile((dominant,), every=PROFILE_EVERY)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -513,7 +521,8 @@ def main():
             # compulsory bytes, and what an explicit sparse matrix (value and
             # column index per nonzero) would have to stream in the same time
             "per_launch": {"nnz": nnz, "ops_per_nnz": OPS_PER_NNZ, "avg_us": avg_s * 1e6,
-                           "launches": int(launches), "tail_launches": int(tail_launches),
+                           "launches_timed": int(launches), "timed_one_in": PROFILE_EVERY,
+                           "tail_launches": int(tail_launches),
                            "measured_hbm_GBs": (traffic / avg_s / 1e9) if traffic else None,
                            "measured_hbm_frac": (traffic / avg_s / PEAK_HBM) if traffic else None,
                            "compulsory_hbm_GBs": compulsory / avg_s / 1e9,

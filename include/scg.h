@@ -284,6 +284,12 @@ typedef struct {
  * accumulated totals. */
 int scg_profile(scg_plan *plan, uint32_t class_mask);
 
+/* Times only one launch in `every` (>= 1; 1 = all, the default) of each
+ * timed class, counting from the last scg_profile call: an event recorded
+ * between two launches delays the second by a few microseconds, so a sampled
+ * solve runs almost as fast as an untimed one. Resets the sampling phase. */
+int scg_profile_every(scg_plan *plan, int32_t every);
+
 /* Accumulated launches and milliseconds per class since the last
  * scg_profile call; out must hold SCG_KC_COUNT entries. */
 int scg_profile_read(scg_plan *plan, scg_kernel_time *out);
@@ -323,6 +329,9 @@ typedef struct {
     uint64_t macro_steps;   /* iterations run (each over all active solves)     */
     uint64_t graph_builds;  /* executable graphs instantiated (a change of the */
                             /* set whose launches differ, or the first one)    */
+    uint64_t rebuild_ns;    /* host time spent recomposing the set (groups,    */
+                            /* descriptors, admission launch, graph capture,   */
+                            /* instantiation or update)                        */
 } scg_batch_stats;
 
 /* Creates a batch on `device` with an arena of arena_bytes and at most

@@ -302,19 +302,25 @@ hipEvent_t take_event(scg_plan *p)
 
 // Marks the start (begin = true) or end of a launch of class `cls` when the
 // class is being timed.
+// Events around one launch in every p->prof_every of a timed class: an event
+// record between two launches holds the next one back by a few
+// microseconds, so sampling keeps the timed solve close to an untimed one.
 void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin)
 {
     if (!(p->prof_mask & (1u << cls))) return;
+    if (begin) {
+        if (p->prof_seq[cls]++ % p->prof_every != 0) return;
+    } else if (p->prof_open[cls] == nullptr) {
+        return;   // the launch was not sampled
+    }
     hipEvent_t e = take_event(p);
     if (e == nullptr) return;
     (void)hipEventRecord(e, s);
     if (begin) {
         p->prof_open[cls] = e;
-    } else if (p->prof_open[cls] != nullptr) {
+    } else {
         p->prof_pending.push_back({cls, p->prof_iter, p->prof_open[cls], e});
         p->prof_open[cls] = nullptr;
-    } else {
-        p->ev_free.push_back(e);
     }
 }
 
@@ -638,6 +644,7 @@ int scg_profile(scg_plan *plan, uint32_t class_mask)
     scg::Device dg(plan->device);
     scg::prof_drain(plan);
     for (int c = 0; c < SCG_KC_COUNT; ++c) {
+        plan->prof_seq[c] = 0;
         plan->prof_count[c] = 0;
         plan->prof_ms[c] = 0.0;
         plan->prof_tail_count[c] = 0;
@@ -646,6 +653,14 @@ int scg_profile(scg_plan *plan, uint32_t class_mask)
         plan->prof_open[c] = nullptr;
     }
     plan->prof_mask = class_mask & ((1u << SCG_KC_COUNT) - 1);
+    return SCG_OK;
+}
+
+int scg_profile_every(scg_plan *plan, int32_t every)
+{
+    if (plan == nullptr || every < 1) return SCG_EINVAL;
+    plan->prof_every = every;
+    for (int c = 0; c < SCG_KC_COUNT; ++c) plan->prof_seq[c] = 0;
     return SCG_OK;
 }
 

@@ -14,6 +14,7 @@
 // finished solves retire between steps and new ones are admitted as slots
 // and arena memory free up.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -1280,7 +1281,11 @@ int scg_batch_step(scg_batch *b, int iters)
     scg::Device dg(b->device);
     if (b->active.empty()) return 0;
     if (b->dirty) {
+        const auto t0 = std::chrono::steady_clock::now();
         int rc = rebuild(b);
+        b->stats.rebuild_ns += (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                   std::chrono::steady_clock::now() - t0)
+                                   .count();
         if (rc) return rc;
     }
     for (int it = 0; it < iters; ++it) {

@@ -46,6 +46,8 @@ struct scg_plan {
     };
     uint32_t prof_mask = 0;
     int prof_iter = 0;
+    int prof_every = 1;                   // time one launch in this many per class
+    int64_t prof_seq[SCG_KC_COUNT] = {};  // launches of each class seen
     std::vector<hipEvent_t> ev_free;
     std::vector<ProfRec> prof_pending;
     hipEvent_t prof_open[SCG_KC_COUNT] = {};

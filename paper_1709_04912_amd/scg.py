@@ -94,6 +94,7 @@ def _load() -> C.CDLL:
     L.scg_static_workspace_bytes.restype = C.c_size_t
     L.scg_profile.argtypes = [vp, C.c_uint32]
     L.scg_profile_read.argtypes = [vp, C.POINTER(scg_kernel_time)]
+    L.scg_profile_every.argtypes = [vp, i32]
     L.scg_plan_get_tuning.argtypes = [vp, C.c_int, C.POINTER(scg_tuning)]
     L.scg_plan_set_tuning.argtypes = [vp, C.c_int, C.POINTER(scg_tuning)]
     L.scg_plan_autotune.argtypes = [vp, C.c_int, vp, C.POINTER(scg_tuning)]
@@ -103,7 +104,7 @@ def _load() -> C.CDLL:
     L.scg_strerror.restype = C.c_char_p
     for name in ("scg_plan_create", "scg_workspace_bytes", "scg_project", "scg_backproject",
                  "scg_tv", "scg_filter", "scg_solve", "scg_solve_static", "scg_profile",
-                 "scg_profile_read",
+                 "scg_profile_read", "scg_profile_every",
                  "scg_plan_get_tuning", "scg_plan_set_tuning", "scg_plan_autotune"):
         getattr(L, name).restype = C.c_int
     return L
@@ -244,12 +245,14 @@ class Plan:
         return t.as_dict()
 
     # -- kernel timing -----------------------------------------------------
-    def profile(self, classes=()):
-        """Times the named kernel classes inside scg_solve (scg_profile)."""
+    def profile(self, classes=(), every: int = 1):
+        """Times the named kernel classes inside scg_solve (scg_profile), one
+        launch in `every` of each (scg_profile_every)."""
         mask = 0
         for c in classes:
             mask |= 1 << KERNEL_CLASSES.index(c)
         _check(lib.scg_profile(self._h, mask), "scg_profile")
+        _check(lib.scg_profile_every(self._h, int(every)), "scg_profile_every")
 
     def profile_read(self) -> dict:
         """Per class: (launches, total_ms, tail_launches, tail_ms); the tail
@@ -358,7 +361,7 @@ class scg_batch_stats(C.Structure):
                 ("graph_updates", C.c_int32), ("arena_bytes", C.c_uint64),
                 ("arena_used", C.c_uint64), ("submitted", C.c_uint64),
                 ("retired", C.c_uint64), ("macro_steps", C.c_uint64),
-                ("graph_builds", C.c_uint64)]
+                ("graph_builds", C.c_uint64), ("rebuild_ns", C.c_uint64)]
 
 
 SCG_BATCH_NO_GRAPH = 1

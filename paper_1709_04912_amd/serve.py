@@ -107,6 +107,7 @@ class Served:
     reports: dict             # rid -> scg.Report
     outputs: dict             # rid -> output tensor
     latency_by_rid: dict = None   # rid -> completion - arrival
+    engine_stats: list = None     # scg_batch_get_stats of each engine at the end
 
     @property
     def recons_per_s(self) -> float:
@@ -168,13 +169,15 @@ def serve_plain(requests: list, keep_outputs: bool = False) -> Served:
 
 
 def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: int = 4,
-                  graph: bool = True, keep_outputs: bool = False,
+                  graph: bool = False, keep_outputs: bool = False,
                   large_n: Optional[int] = None, large_iters: int = 1,
                   large_slots: int = 1) -> Served:
     """Continuous batching on the batch engine: admit every arrived request
     that fits (FIFO; a request that does not fit blocks the ones behind it),
     run `iters` iterations of all resident solves, retire the finished ones,
-    repeat.
+    repeat. graph: replay each iteration as a captured HIP graph (measured a
+    few per cent slower than enqueuing the kernels, whose host cost hides
+    behind the device's work).
 
     With large_n, requests of N >= large_n go to a second batch engine of
     their own with `large_slots` slots (1: the large solves run one after
@@ -237,7 +240,8 @@ def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: 
                     if keep_outputs:
                         outputs[r.rid] = out
         wall = (time.perf_counter() - t0) - (order[0].arrival if order else 0.0)
+        stats = [b.stats() for b in engines]
     finally:
         for b in engines:
             b.close()
-    return Served(np.asarray(lat), wall, reports, outputs, by_rid)
+    return Served(np.asarray(lat), wall, reports, outputs, by_rid, stats)
