@@ -350,6 +350,24 @@ void prof_drain(scg_plan *p, int last_iter)
     p->prof_pending.clear();
 }
 
+// Moves the timing records from index `from` on to the tail sums: launches
+// that returned at once because the solve was suspended.
+void prof_to_tail(scg_plan *p, size_t from)
+{
+    for (size_t i = from; i < p->prof_pending.size(); ++i) {
+        const auto &r = p->prof_pending[i];
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            p->prof_tail_ms[r.cls] += ms;
+            p->prof_tail_count[r.cls] += 1;
+        }
+        p->ev_free.push_back(r.a);
+        p->ev_free.push_back(r.b);
+    }
+    if (from < p->prof_pending.size()) p->prof_pending.resize(from);
+}
+
 int check_params(const scg_params *pr)
 {
     if (pr == nullptr) return SCG_EINVAL;

@@ -279,56 +279,11 @@ template <typename T> void enqueue_init(const Group<T> &g, hipStream_t s)
     if (g.variant != SCG_S_CG_CD && g.variant != SCG_S_CG_3OP) e.backproject(kBpH, 0);
 }
 
-// One loop iteration. S- variants: close the previous step (x_{k+1} =
-// x_{k+1/2} + alpha p), perturbed(x_k) (TV subgradient, trials, x_{k+1/2}),
-// then the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP) from x_{k+1/2}.
-// CG: the cap test, then CG-STEP.
-template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
+// The rest of an S- iteration after the trial search: x_{k+1/2}, then the
+// step from it.
+template <typename T> void enqueue_after_search(const Group<T> &g, hipStream_t s)
 {
     const Enq<T> e{g, s};
-    if (g.variant == SCG_CG) {
-        e.finish(kFinCGCap);
-        e.project(kPjQ);
-        e.finish(kFinNormQCG);
-        e.backproject(kBpH, 0);
-        {
-            Prof t(g.prof, SCG_KC_VECTOR, s);
-            launch_b_x_update_cg<T>(g.S, e.m(kKVec), e.n(kKVec), s);
-        }
-        e.finish(kFinXUpdateCG);
-        e.p_update(3, 0);
-        e.stage(kStageX);
-        e.project(kPjResX);
-        e.finish(kFinResidual);
-        return;
-    }
-    if (g.variant == SCG_PCG) {
-        // cap test, PCG-STEP (recursive g and r), then f(x) explicitly
-        e.finish(kFinCGCap);
-        e.project(kPjQ);
-        e.finish(kFinNormQCG);
-        e.pcg_step(0, false);
-        e.stage(kStageX);
-        e.project(kPjResX);
-        e.finish(kFinResidual);
-        return;
-    }
-    e.xtv();
-    e.finish(kFinXtv);
-    {
-        Prof t(g.prof, SCG_KC_TRIALS, s);
-        launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, s);
-    }
-    e.finish(kFinTrials, 0);
-    if (g.any_trB) {
-        // the second trial launch and its finisher return at once where the
-        // first launch accepted a step
-        {
-            Prof t(g.prof, SCG_KC_TRIALS, s);
-            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
-        }
-        e.finish(kFinTrials, kTrialsPerPass);
-    }
     {
         Prof t(g.prof, SCG_KC_VECTOR, s);
         launch_b_perturb<T>(g.S, e.m(kKT32), e.n(kKT32), s);
@@ -395,6 +350,79 @@ template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
     }
     e.project(kPjQ);
     if (g.variant != SCG_S_CG_CD) e.backproject(kBpH, 0);
+}
+
+// Head of a loop iteration of an S- variant: the TV pass that closes the
+// previous step (x_{k+1} = x_{k+1/2} + alpha p) and opens this one, and the
+// first trial launch of perturbed(x_k). suspend_tag > 0: the second trial
+// launch is left out of this iteration, and a search the first leaves open
+// suspends the solve under that tag.
+template <typename T> void enqueue_head(const Group<T> &g, hipStream_t s, int suspend_tag)
+{
+    const Enq<T> e{g, s};
+    e.xtv();
+    e.finish(kFinXtv);
+    {
+        Prof t(g.prof, SCG_KC_TRIALS, s);
+        launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, s);
+    }
+    e.finish(kFinTrials, 0, g.any_trB ? suspend_tag : 0);
+}
+
+// The rest of the iteration after the head: the second trial launch (with_b),
+// x_{k+1/2}, then the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP, or the
+// CG-K / PCG-K pass) from x_{k+1/2}.
+template <typename T> void enqueue_tail(const Group<T> &g, hipStream_t s, bool with_b)
+{
+    const Enq<T> e{g, s};
+    if (g.any_trB && with_b) {
+        // the second trial launch and its finisher return at once where the
+        // first launch accepted a step
+        {
+            Prof t(g.prof, SCG_KC_TRIALS, s);
+            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
+        }
+        e.finish(kFinTrials, kTrialsPerPass);
+    }
+    enqueue_after_search(g, s);
+}
+
+// One loop iteration. S- variants: close the previous step (x_{k+1} =
+// x_{k+1/2} + alpha p), perturbed(x_k) (TV subgradient, trials, x_{k+1/2}),
+// then the step (CG-PR-STEP / CG-CD-STEP / PCG-PR-STEP) from x_{k+1/2}.
+// CG: the cap test, then CG-STEP.
+template <typename T> void enqueue_iteration(const Group<T> &g, hipStream_t s)
+{
+    const Enq<T> e{g, s};
+    if (g.variant == SCG_CG) {
+        e.finish(kFinCGCap);
+        e.project(kPjQ);
+        e.finish(kFinNormQCG);
+        e.backproject(kBpH, 0);
+        {
+            Prof t(g.prof, SCG_KC_VECTOR, s);
+            launch_b_x_update_cg<T>(g.S, e.m(kKVec), e.n(kKVec), s);
+        }
+        e.finish(kFinXUpdateCG);
+        e.p_update(3, 0);
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        return;
+    }
+    if (g.variant == SCG_PCG) {
+        // cap test, PCG-STEP (recursive g and r), then f(x) explicitly
+        e.finish(kFinCGCap);
+        e.project(kPjQ);
+        e.finish(kFinNormQCG);
+        e.pcg_step(0, false);
+        e.stage(kStageX);
+        e.project(kPjResX);
+        e.finish(kFinResidual);
+        return;
+    }
+    enqueue_head(g, s, 0);
+    enqueue_tail(g, s, true);
 }
 
 // Output image (x_{k+1/2} of the S- variants, x of CG) and its TV.
@@ -563,26 +591,61 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     enqueue_init(g, st0);
     // loop: chunks of iterations (4, 8, 16, 16, ...) queued behind the
     // initial step without waiting for it; the device decides when to stop,
-    // and launches queued after the stop return at once. The flag and the
-    // final state come back through the plan's pinned host words.
+    // and launches queued after the stop return at once. The state comes
+    // back through the plan's pinned host words after each chunk.
+    //
+    // Trial launches: once the global counter ell has grown, a step's search
+    // rarely outlives the first trial launch. The first chunk takes both
+    // launches of every step; later chunks take the first only, and a step
+    // whose search goes on past it suspends the solve (kFinTrials). The host
+    // then clears the flag, enqueues that step's remainder with the second
+    // launch and gives the next chunk both launches; after a second
+    // suspension every chunk has both.
     static_assert(sizeof(DevState) + 2 * sizeof(double) <= kHostPinnedBytes, "pinned words");
-    auto *done_h = static_cast<volatile int *>(plan->host_pinned);
     auto *fs_h = reinterpret_cast<DevState *>(static_cast<char *>(plan->host_pinned) + 64);
     auto *tv_h = reinterpret_cast<double *>(static_cast<char *>(plan->host_pinned) + 64 +
                                             ((sizeof(DevState) + 7) / 8) * 8);
-    *done_h = 0;
+    const bool may_suspend = g.any_trB && !unsuperiorized(pr->variant);
+    int suspensions = 0;
+    bool both = true;                // the next chunk takes both trial launches
+    std::vector<size_t> tail_mark;   // timing records before each iteration's tail
     long issued = 0;
     int chunk = 4;
-    while (!*done_h && issued <= (long)pr->max_iter) {
+    for (;;) {
+        const bool split = may_suspend && !both;
+        tail_mark.assign(chunk, 0);
         for (int c = 0; c < chunk; ++c) {
             plan->prof_iter = (int)std::min<long>(issued + c + 1, INT_MAX - 1);
-            enqueue_iteration(g, st0);
+            if (split) {
+                enqueue_head(g, st0, c + 1);
+                tail_mark[c] = plan->prof_pending.size();
+                enqueue_tail(g, st0, false);
+            } else {
+                enqueue_iteration(g, st0);
+            }
         }
+        const long first = issued + 1;
         issued += chunk;
         chunk = std::min(chunk * 2, 16);
-        HIP_TRY(hipMemcpyAsync(const_cast<int *>(done_h), &h.st->done, sizeof(int),
-                               hipMemcpyDeviceToHost, st0));
+        both = suspensions >= 2;
+        HIP_TRY(hipMemcpyAsync(fs_h, h.st, sizeof(DevState), hipMemcpyDeviceToHost, st0));
         HIP_TRY(hipStreamSynchronize(st0));
+        DevState cs;
+        std::memcpy(&cs, fs_h, sizeof cs);
+        if (split && cs.done == kSuspended) {
+            const int c = cs.susp_tag - 1;
+            if (c < 0 || c >= (int)tail_mark.size()) return SCG_EDEVICE;
+            // the launches after the suspending step's head returned at once
+            if (g.prof) prof_to_tail(plan, tail_mark[c]);
+            HIP_TRY(hipMemsetAsync(&h.st->done, 0, sizeof(int), st0));
+            issued = first + c;
+            plan->prof_iter = (int)std::min<long>(issued, INT_MAX - 1);
+            enqueue_tail(g, st0, true);
+            ++suspensions;
+            both = true;
+            continue;
+        }
+        if (cs.done || issued > (long)pr->max_iter) break;
     }
     plan->prof_iter = INT_MAX;
     g.prof = nullptr;

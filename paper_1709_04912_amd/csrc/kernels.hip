@@ -1988,7 +1988,11 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         return;
     }
     case kFinTrials: {
-        // arg0 = first trial of the launch (0 or kTrialsPerPass)
+        // arg0 = first trial of the launch (0 or kTrialsPerPass). arg1 > 0
+        // (first launch only): the second trial launch does not follow in
+        // this iteration, and a search the first launch leaves open suspends
+        // the solve (done = kSuspended, susp_tag = arg1; every later launch
+        // returns at once) until the host enqueues the rest of the step
         const int first_m = arg0;
         if (st->search_done) return;
         const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
@@ -2030,6 +2034,9 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
                 tr->gamma = st->gamma;
                 tr->tv_x = tvx;
             }
+        } else if (first_m == 0 && arg1 > 0) {
+            st->done = kSuspended;
+            st->susp_tag = arg1;
         }
         return;
     }

@@ -90,6 +90,7 @@ double filter_mu(const scg_plan *p, double mu);   // mu, or 2 pi / P for mu <= 0
 // Kernel timing of scg_profile: event pairs around launches of timed classes.
 void prof_mark(scg_plan *p, int cls, hipStream_t s, bool begin);
 void prof_drain(scg_plan *p, int last_iter = INT_MAX);
+void prof_to_tail(scg_plan *p, size_t from);
 
 int check_params(const scg_params *pr);
 

@@ -40,6 +40,11 @@ constexpr int kSinoPadL = 1;
 constexpr int kSinoPadR = 3;
 
 constexpr int kTrialsPerPass = 16;   // TV trials evaluated per chunk of perturbed()
+// DevState::done of a single solve whose trial search needs the second trial
+// launch in an iteration enqueued without it: every launch returns at once
+// until the host clears the flag and enqueues the rest of that step
+// (DevState::susp_tag names the iteration)
+constexpr int kSuspended = 2;
 constexpr int kMaxTrials = 1024;     // cap on max_trials
 constexpr int kMaxTrialChunks = (kMaxTrials + kTrialsPerPass - 1) / kTrialsPerPass;
 constexpr int kMaxPartials = 65536;  // block partials per reduction (max blocks x values)
@@ -111,7 +116,7 @@ struct DevState {
     // perturbation
     int ell, trials_step, accepted, search_done;
     int trials_total, forced_len, trace_cap;
-    int reserved0;
+    int susp_tag;    // host tag of the loop iteration that suspended the solve
     double tv_x, s_norm2, inv_snorm, gamma;
     // CG scalars
     double f_half, qq_prev, qq, gh, gg, gp, gp_prev, beta, alpha, delta;

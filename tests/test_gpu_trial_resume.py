@@ -1,0 +1,118 @@
+"""Single solves whose trial searches go on past the first trial launch in
+later steps. After its first chunk of iterations the solver enqueues only the
+first trial launch of each step (16 trials); a step whose search goes on
+suspends the solve, and the host enqueues the rest of that step with the
+second launch (the next chunk then takes both launches, and after a second
+suspension every chunk does).
+
+With a = 0.999, gamma0 = 0.5 ||x_1|| and 40 trials per step on the 64 x 64
+workload, steps well past the first chunk need more than 16 trials. TV is
+smoothed (kappa = 1 or 0.1) so that the cases are well conditioned: with
+kappa = 0 and steps this large, a relative change of 1e-12 in y moves the
+oracle's own output by up to 1e-2 (the subgradient flips where a pixel
+difference is near zero), and no image bound would hold.
+
+Bar: the FP64 GPU path takes the oracle's decisions, stops at its step with
+its status, lands within 1e-8 of its image, and equals bitwise the batch
+engine's result for the same solve (the batch engine enqueues both trial
+launches in every step and never suspends); timing the kernels does not
+change a bit."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import algorithms as alg
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg,
+             "S_CG_K": lambda prob, x0, eps, pp, max_iter: alg.scg_k(prob, x0, eps, pp, K=2,
+                                                                     max_iter=max_iter)}
+
+
+def _case(oracle_lib):
+    gd = json.load(open(os.path.join(HERE, "golden", "eps.json")))["cfg1_s0"]
+    w = make_workload(1, 0, supersample=2)
+    g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
+    return w, g, alg.Problem(g, w.y), 1.1 * gd["eps0"], gd["x1_norm"]
+
+
+def suspensions(trials_per_step):
+    """Steps at which the solver's chunk policy suspends a solve, given the
+    trial count of every step: chunks of 4, 8, 16, 16, ... iterations; the
+    first chunk, the chunk after a suspension and every chunk after a second
+    suspension take both trial launches."""
+    out, issued, chunk, both = [], 0, 4, True
+    n = len(trials_per_step)
+    while issued < n:
+        hit = None
+        if not both:
+            hit = next((j for j in range(issued + 1, min(issued + chunk, n) + 1)
+                        if trials_per_step[j - 1] > 16), None)
+        chunk_end = issued + chunk
+        chunk = min(2 * chunk, 16)
+        if hit is not None:
+            out.append(hit)
+            issued, both = hit, True
+        else:
+            issued, both = chunk_end, len(out) >= 2
+    return out
+
+
+def test_suspension_model():
+    assert suspensions([20] * 4 + [1] * 30) == []
+    assert suspensions([20] * 6 + [1] * 30) == [5]
+    assert suspensions([20] * 6 + [1] * 15 + [20] * 30) == [5, 22]
+    assert suspensions([20] * 6 + [1] * 20 + [20] * 30) == [5, 27]
+
+
+@pytest.mark.parametrize("variant,kappa,max_iter", [
+    ("S_CG", 1.0, 60), ("S_CG_CD", 0.1, 60), ("S_PCG", 0.1, 60), ("S_CG_K", 0.1, 30)])
+def test_resumed_searches_match_oracle(oracle_lib, variant, kappa, max_iter):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_04912_amd import scg
+    w, g, prob, eps, x1n = _case(oracle_lib)
+    pp = alg.PerturbParams(0.5 * x1n, a=0.999, max_trials=40, kappa=kappa)
+    print(f"[trial resume] variant={variant} kappa={kappa} max_iter={max_iter}", flush=True)
+    ref = ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=pp, max_iter=max_iter)
+    ref_dec = [(t["trials"], t["accepted"]) for t in ref.trace]
+    sus = suspensions([n for n, _ in ref_dec])
+    assert sus, "the case must suspend at least once"
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        p = plan.params(eps=eps, gamma0=pp.gamma0, variant=variant, prec=scg.SCG_F64,
+                        a=0.999, max_trials=40, max_iter=max_iter, kappa=kappa)
+        x, rep, trace = plan.solve(y, p)
+        dec = [(t["trials"], t["accepted"]) for t in trace]
+        rel = float(np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x))
+        print(f"  suspended at steps {sus}; k={rep.k} ref_k={ref.k} status={rep.status} "
+              f"ref={ref.status} rel={rel:.2e}", flush=True)
+        assert dec == ref_dec
+        assert rep.k == ref.k
+        want = scg.SCG_OK if ref.status == "ok" else scg.SCG_ENOCONV
+        assert rep.status == want
+        assert abs(rep.f_out - ref.f_out) <= 1e-9 * ref.f_out
+        assert rel <= 1e-8
+        with scg.Batch(1 << 28, max_slots=2, graph=False) as bt:
+            ticket, out = bt.submit(plan, y, p)
+            while bt.step(8) > 0:
+                pass
+            rb = bt.poll(ticket)
+        assert torch.equal(x, out)
+        assert (rb.status, rb.k, rb.steps, rb.f_out, rb.tv_out) == \
+            (rep.status, rep.k, rep.steps, rep.f_out, rep.tv_out)
+        if variant == "S_CG":
+            # every launch timed: identical bits, and the launches that
+            # returned at once behind the suspension kept apart
+            plan.profile(classes=scg.KERNEL_CLASSES, every=1)
+            xt, rept, _ = plan.solve(y, p)
+            prof = plan.profile_read()
+            plan.profile(classes=())
+            assert torch.equal(x, xt) and rept.k == rep.k
+            assert prof["trials"][0] > 0 and prof["trials"][2] > 0
+            print(f"  timed: trials {prof['trials']}, control {prof['control']}")
