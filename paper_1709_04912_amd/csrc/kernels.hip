@@ -30,6 +30,7 @@ template <typename P> __device__ __forceinline__ auto gl(P *p)
 }
 
 constexpr int kBlock = 256;
+constexpr int kXtvRows = 16;   // tile height of the step-boundary TV pass (two rows per thread)
 constexpr int kMaxVecBlocks = 512;
 
 // Raw buffer views. A load through the buffer unit whose per-lane byte
@@ -352,8 +353,12 @@ template <typename T> __device__ __forceinline__ Solve<T> load_solve(const Solve
     return gl(S)[i];
 }
 
-// The solve and the local block index of a batched launch's block.
-__device__ __forceinline__ BlkMap locate(const BlkMap *map, int swz = 0)
+// The solve and the local block index of a batched launch's block. The
+// streaming kernels take the XCD-contiguous order (the default): a tile and
+// the neighbours whose edge rows it reads then sit on one XCD, and the rows
+// they share are fetched into one L2 instead of several. The operators pass
+// their tuned order.
+__device__ __forceinline__ BlkMap locate(const BlkMap *map, int swz = 1)
 {
     const int b = launch_index(swz);
     if (map == nullptr) return BlkMap{0, b};
@@ -362,7 +367,7 @@ __device__ __forceinline__ BlkMap locate(const BlkMap *map, int swz = 0)
 
 }  // namespace
 
-int blocks_xtv(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 7) / 8); }
+int blocks_xtv(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + kXtvRows - 1) / kXtvRows); }
 int blocks_t32(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 31) / 32); }
 int blocks_vec(size_t n) { return vec_blocks(n); }
 int blocks_sv(const Geo &G) { return G.na; }
@@ -1210,7 +1215,7 @@ void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t 
 // ---------------------------------------------------------------------------
 // Step boundary of the superiorized solvers, fused with the TV work that opens
 // the next step: x_{k+1} = x_{k+1/2} + alpha p' (the last line of the previous
-// step) on a 32 x 8 tile plus a one-pixel halo held in LDS, then the TV
+// step) on a 32 x 16 tile plus a one-pixel halo held in LDS, then the TV
 // subgradient s at x_{k+1}; the block stores its parts of TV(x_{k+1}) and
 // ||s||^2. The finisher closes the previous step and opens the next.
 // ---------------------------------------------------------------------------
@@ -1225,7 +1230,7 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
     auto *x = gl(x_);
     auto *s_out = gl(s_out_);
     const auto *st = gl(st_);
-    constexpr int TW = 32, TH = 8;
+    constexpr int TW = 32, TH = kXtvRows;
     __shared__ T tile[TH + 2][TW + 2];
     const int n = G.n;
     const int i0 = vb.y * TH, j0 = vb.x * TW;
@@ -1233,32 +1238,52 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
     const T k2 = (T)(st->kappa * st->kappa);
     // S-CG-K, S-PCG-K: x_{k+1} is the pass's output, already in x
     const bool given = st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K;
-    for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
+    // the tile and its halo, (TH + 2) x (TW + 2) values over the block's
+    // kBlock threads: every load is issued before the first is used
+    constexpr int NE = (TH + 2) * (TW + 2), NI = (NE + kBlock - 1) / kBlock;
+    T hv[NI], pv[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int e = threadIdx.x + kBlock * k;
         const int ii = i0 - 1 + e / (TW + 2), jj = j0 - 1 + e % (TW + 2);
-        T v = T(0);
-        if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
+        hv[k] = pv[k] = T(0);
+        if (e < NE && ii >= 0 && ii < n && jj >= 0 && jj < n) {
             const size_t q = (size_t)ii * n + jj;
-            v = given ? x[q] : fma(al, p[q], xh[q]);
+            if (given) {
+                hv[k] = x[q];
+            } else {
+                hv[k] = xh[q];
+                pv[k] = p[q];
+            }
         }
-        tile[e / (TW + 2)][e % (TW + 2)] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int e = threadIdx.x + kBlock * k;
+        if (e < NE) tile[e / (TW + 2)][e % (TW + 2)] = given ? hv[k] : fma(al, pv[k], hv[k]);
     }
     __syncthreads();
-    const int ty = threadIdx.x / TW, tx = threadIdx.x % TW;
-    const int i = i0 + ty, j = j0 + tx;
+    // each thread forms the pixels of rows ty, ty + kBlock / TW, ...
+    constexpr int RS = kBlock / TW;
+    const int tx = threadIdx.x % TW;
     double tv = 0.0, ss = 0.0;
-    if (i < n && j < n) {
-        T X[3][3];
 #pragma unroll
-        for (int di = 0; di < 3; ++di)
+    for (int ty = threadIdx.x / TW; ty < TH; ty += RS) {
+        const int i = i0 + ty, j = j0 + tx;
+        if (i < n && j < n) {
+            T X[3][3];
 #pragma unroll
-            for (int dj = 0; dj < 3; ++dj) X[di][dj] = tile[ty + di][tx + dj];
-        T own;
-        const T sg = tv_pixel(X, i, j, n, k2, own);
-        const size_t q = (size_t)i * n + j;
-        if (!given) x[q] = X[1][1];
-        s_out[q] = sg;
-        tv = (double)own;
-        ss = (double)sg * (double)sg;
+            for (int di = 0; di < 3; ++di)
+#pragma unroll
+                for (int dj = 0; dj < 3; ++dj) X[di][dj] = tile[ty + di][tx + dj];
+            T own;
+            const T sg = tv_pixel(X, i, j, n, k2, own);
+            const size_t q = (size_t)i * n + j;
+            if (!given) x[q] = X[1][1];
+            s_out[q] = sg;
+            tv += (double)own;
+            ss += (double)sg * (double)sg;
+        }
     }
     double v[2] = {tv, ss};
     block_store(v, partials + 2 * (size_t)vb.id());
@@ -1281,7 +1306,7 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
         alpha = -gp / qq;
     }
     xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha,
-             vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + 7) / 8));
+             vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + kXtvRows - 1) / kXtvRows));
 }
 
 template <typename T>
@@ -1302,6 +1327,10 @@ void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given, 
 // first_m, first_m + 1, ...].
 // ---------------------------------------------------------------------------
 
+static_assert((unsigned long long)kMaxN * kMaxN + (unsigned long long)kMaxPartials * kBlock <
+                  (1ull << 32),
+              "32-bit trial term indices");
+
 template <typename T>
 __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, const Geo &G,
                             const double *__restrict__ gtab_, double *partials,
@@ -1316,9 +1345,11 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
     const int stride = 1 + M * nchunks;
     const T inv = (T)st->inv_snorm;
     const T k2 = (T)(st->kappa * st->kappa);
-    const int n = G.n, m1 = n - 1;
-    const size_t terms = (size_t)m1 * m1;
-    const int bid = vb.id(), nblk = vb.count();
+    // 32-bit indices: (n - 1)^2 plus one grid stride stays below 2^32 for
+    // every accepted image side
+    const unsigned n = (unsigned)G.n, m1 = n - 1u;
+    const unsigned terms = m1 * m1;
+    const unsigned bid = (unsigned)vb.id(), nblk = (unsigned)vb.count();
     const bool with_tvx = first_m == 0;
     for (int c = 0; c < nchunks; ++c) {
         const int m0 = first_m + M * c;
@@ -1328,10 +1359,9 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
         T acc[M + 1];
 #pragma unroll
         for (int m = 0; m <= M; ++m) acc[m] = T(0);
-        for (size_t q = bid * (size_t)blockDim.x + threadIdx.x; q < terms;
-             q += (size_t)nblk * blockDim.x) {
-            const int i = (int)(q / m1), j = (int)(q % m1);
-            const size_t cq = (size_t)i * n + j;
+        for (unsigned q = bid * blockDim.x + threadIdx.x; q < terms; q += nblk * blockDim.x) {
+            const unsigned i = q / m1, j = q - i * m1;
+            const unsigned cq = i * n + j;
             const T xc = x[cq], xd = x[cq + n], xr = x[cq + 1];
             const T vc = -s[cq] * inv, vd = -s[cq + n] * inv, vr = -s[cq + 1] * inv;
             if (with_tvx && c == 0) acc[M] += tv_term(xd - xc, xr - xc, k2);
@@ -1403,13 +1433,27 @@ __device__ void perturb_body(T *__restrict__ x_, const T *__restrict__ s_,
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int r = ty; r < 32; r += 8) {
+    // every row's loads are issued before the first store
+    constexpr int R = 4;   // rows per thread
+    T xv[R], sv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = by + ty + 8 * k, j = bx + tx;
+        xv[k] = sv[k] = T(0);
+        if (i < n && j < n) {
+            const size_t q = (size_t)i * n + j;
+            xv[k] = x[q];
+            if (move) sv[k] = s[q];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = ty + 8 * k;
         const int i = by + r, j = bx + tx;
         T v = T(0);
         if (i < n && j < n) {
             const size_t q = (size_t)i * n + j;
-            const T xc = x[q];
-            v = move ? fma(g, -s[q] * inv, xc) : xc;
+            v = move ? fma(g, -sv[k] * inv, xv[k]) : xv[k];
             xh[q] = v;
             if (restart) x[q] = v;
         }
@@ -1464,15 +1508,33 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // every row's loads are issued before the first store (eight or twelve
+    // loads in flight per thread), then the rows are formed in order
+    constexpr int R = 4;   // rows per thread
+    const bool sep = src != g;
+    T sv[R], pv[R], gv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = by + ty + 8 * k, j = bx + tx;
+        sv[k] = pv[k] = gv[k] = T(0);
+        if (i < n && j < n) {
+            const size_t q = (size_t)i * n + j;
+            sv[k] = src[q];
+            if (!init) pv[k] = p[q];
+            if (sep) gv[k] = g[q];
+        }
+    }
     double acc = 0.0;
-    for (int r = ty; r < 32; r += 8) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = ty + 8 * k;
         const int i = by + r, j = bx + tx;
         T pn = T(0);
         if (i < n && j < n) {
             const size_t q = (size_t)i * n + j;
-            pn = init ? -src[q] : fma(bt, p[q], -src[q]);
+            pn = init ? -sv[k] : fma(bt, pv[k], -sv[k]);
             p[q] = pn;
-            acc += (double)g[q] * (double)pn;
+            acc += (double)(sep ? gv[k] : sv[k]) * (double)pn;
         }
         tile[r][tx] = pn;
     }
