@@ -1220,10 +1220,10 @@ void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t 
 // ||s||^2. The finisher closes the previous step and opens the next.
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, typename F>
 __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T *__restrict__ x_,
                          T *__restrict__ s_out_, const Geo &G, double *partials,
-                         const DevState *st_, double alpha, VBlk vb)
+                         const DevState *st_, F alpha_of, VBlk vb)
 {
     const auto *xh = gl(xh_);
     const auto *p = gl(p_);
@@ -1234,12 +1234,12 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
     __shared__ T tile[TH + 2][TW + 2];
     const int n = G.n;
     const int i0 = vb.y * TH, j0 = vb.x * TW;
-    const T al = (T)alpha;
     const T k2 = (T)(st->kappa * st->kappa);
     // S-CG-K, S-PCG-K: x_{k+1} is the pass's output, already in x
     const bool given = st->variant == SCG_S_CG_K || st->variant == SCG_S_PCG_K;
     // the tile and its halo, (TH + 2) x (TW + 2) values over the block's
-    // kBlock threads: every load is issued before the first is used
+    // kBlock threads: every load is issued before alpha is formed (its block
+    // sums overlap the loads) and before the first is used
     constexpr int NE = (TH + 2) * (TW + 2), NI = (NE + kBlock - 1) / kBlock;
     T hv[NI], pv[NI];
 #pragma unroll
@@ -1257,6 +1257,7 @@ __device__ void xtv_body(const T *__restrict__ xh_, const T *__restrict__ p_, T 
             }
         }
     }
+    const T al = (T)alpha_of();
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int e = threadIdx.x + kBlock * k;
@@ -1299,13 +1300,14 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     // alpha of the open step: from the direction update's and the
     // projection's partials (recorded by this pass's finisher) or from the
     // state (given: a finisher formed it there with the same sums)
-    double alpha = st->alpha;
-    if (!given && local_alpha(st->variant) && st->open) {
+    const bool local = !given && local_alpha(st->variant) && st->open;
+    auto alpha_of = [&]() -> double {
+        if (!local) return st->alpha;
         double gp, qq;
         block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
-        alpha = -gp / qq;
-    }
-    xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha,
+        return -gp / qq;
+    };
+    xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha_of,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + kXtvRows - 1) / kXtvRows));
 }
 
@@ -1493,23 +1495,30 @@ template <typename S> __device__ __forceinline__ double beta_of(S *st, int rule,
     return st->gg / st->delta;   // rule 3 (CG-STEP), rule 4 (PCG-STEP: gg holds g^T z)
 }
 
-template <typename T>
+// Scalars of a direction update, formed by the caller's callable once the
+// update's loads are in flight: go = false leaves the vectors untouched.
+struct StepScalars {
+    bool go;
+    double beta;
+};
+
+template <typename T, typename F>
 __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_,
                               T *__restrict__ p_, T *__restrict__ pt_, const Geo &G,
-                              double *partials, int rule, int init, double beta, VBlk vb)
+                              double *partials, int rule, int init, F scalars, VBlk vb)
 {
     const auto *g = gl(g_);
     const auto *z = gl(z_);
     auto *p = gl(p_);
     auto *pt = gl(pt_);
     __shared__ T tile[32][33];
-    const T bt = (T)beta;
     const auto *src = (rule == 2 || rule == 4) ? z : g;   // PCG rules step along -z
     const int n = G.n;
     const int bx = vb.x * 32, by = vb.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    // every row's loads are issued before the first store (eight or twelve
-    // loads in flight per thread), then the rows are formed in order
+    // every row's loads are issued before the scalars are formed (their
+    // block sums overlap the loads) and before the first store (eight or
+    // twelve loads in flight per thread); then the rows are formed in order
     constexpr int R = 4;   // rows per thread
     const bool sep = src != g;
     T sv[R], pv[R], gv[R];
@@ -1524,6 +1533,9 @@ __device__ void p_update_body(const T *__restrict__ g_, const T *__restrict__ z_
             if (sep) gv[k] = g[q];
         }
     }
+    const StepScalars sc = scalars();
+    if (!sc.go) return;
+    const T bt = (T)sc.beta;
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1558,54 +1570,67 @@ __global__ __launch_bounds__(256) void kb_p_update(const Solve<T> *S, const BlkM
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
     auto *st = gl(d.st);
+    const VBlk vb = vblk_of(m.local, nt, nt);
     if (given) {
         // a finisher (kFinStepScalars) took the stop test and left beta in
         // the state: the same sums, so the same bits
-        p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init, st->beta,
-                      vblk_of(m.local, nt, nt));
+        p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init,
+                      [&] { return StepScalars{true, st->beta}; }, vb);
         return;
     }
-    if (rec) {
-        // The step's loop test, f(x_{k+1/2}) <= eps, with f from the
-        // residual projection's partials (kPjResXhF): every block forms the
-        // same f; the solve's first block records it and, when the test
-        // holds (or f is not finite), ends the solve at k + 1 with output
-        // x_{k+1/2}: the rest of the step cannot change the output and is
-        // skipped.
-        const double f = 0.5 * block_sum1(d.partials2, d.nb_pj);
-        const bool stop = !isfinite(f) || f <= st->eps;
-        if (m.local == 0 && threadIdx.x == 0) {
-            st->f_half = f;
-            if (auto *tr = trace_at(st, d.trace)) tr->f_half = f;
-            if (!isfinite(f)) {
-                set_done(st, SCG_ENAN);
-            } else if (stop) {
-                st->steps += 1;
-                st->k += 1;
-                set_done(st, SCG_OK);
+    // formed while the update's loads are in flight
+    auto scalars = [&]() -> StepScalars {
+        // beta of rules 0-2 from the backprojection's dot partials, of the
+        // others from the state
+        const bool need_dot = !init && rule <= 2;
+        double f = 0.0, dot = 0.0;
+        if (rec && need_dot) {
+            block_sum2(d.partials2, d.nb_pj, d.partials, d.nb_bp, f, dot);
+        } else if (rec) {
+            f = block_sum1(d.partials2, d.nb_pj);
+        } else if (need_dot) {
+            dot = block_sum1(d.partials, d.nb_bp);
+        }
+        if (rec) {
+            // The step's loop test, f(x_{k+1/2}) <= eps, with f from the
+            // residual projection's partials (kPjResXhF): every block forms
+            // the same f; the solve's first block records it and, when the
+            // test holds (or f is not finite), ends the solve at k + 1 with
+            // output x_{k+1/2}: the rest of the step cannot change the
+            // output and is skipped.
+            f *= 0.5;
+            const bool stop = !isfinite(f) || f <= st->eps;
+            if (m.local == 0 && threadIdx.x == 0) {
+                st->f_half = f;
+                if (auto *tr = trace_at(st, d.trace)) tr->f_half = f;
+                if (!isfinite(f)) {
+                    set_done(st, SCG_ENAN);
+                } else if (stop) {
+                    st->steps += 1;
+                    st->k += 1;
+                    set_done(st, SCG_OK);
+                }
+            }
+            if (stop) return StepScalars{false, 0.0};
+        }
+        double beta = beta_of(st, rule, init);
+        if (need_dot) {
+            beta = rule == 1 ? -dot / st->gp_prev : dot / st->qq_prev;
+            // rec: no finisher follows; the solve's first block records the
+            // dot and beta (fields the other blocks do not read), and g'^T p'
+            // is recorded by the finisher of the TV pass that forms alpha
+            // from it
+            if (rec && m.local == 0 && threadIdx.x == 0) {
+                if (rule == 1) st->gg = dot;
+                else st->gh = dot;
+                st->beta = beta;
+                if (!isfinite(beta)) set_done(st, SCG_ENAN);
+                if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
             }
         }
-        if (stop) return;
-    }
-    // beta of rules 0-2 from the backprojection's dot partials, of the
-    // others from the state
-    double beta = beta_of(st, rule, init);
-    if (!init && rule <= 2) {
-        const double dot = block_sum1(d.partials, d.nb_bp);
-        beta = rule == 1 ? -dot / st->gp_prev : dot / st->qq_prev;
-        // rec: no finisher follows; the solve's first block records the dot
-        // and beta (fields the other blocks do not read), and g'^T p' is
-        // recorded by the finisher of the TV pass that forms alpha from it
-        if (rec && m.local == 0 && threadIdx.x == 0) {
-            if (rule == 1) st->gg = dot;
-            else st->gh = dot;
-            st->beta = beta;
-            if (!isfinite(beta)) set_done(st, SCG_ENAN);
-            if (auto *tr = trace_at(st, d.trace)) tr->beta = beta;
-        }
-    }
-    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init, beta,
-                  vblk_of(m.local, nt, nt));
+        return StepScalars{true, beta};
+    };
+    p_update_body(d.g, d.z, d.p, d.pt, d.G, d.partials3, rule, init, scalars, vb);
 }
 
 template <typename T>
@@ -1647,7 +1672,8 @@ __global__ __launch_bounds__(256) void kb_pq_update(const Solve<T> *S, const Blk
     if (stopped(d.st)) return;
     if (m.local < d.nb_t32) {
         const int nt = (d.G.n + 31) / 32;
-        p_update_body(d.g, d.z, d.p, (T *)nullptr, d.G, d.partials, 0, 0, beta_of(gl(d.st), 0, 0),
+        p_update_body(d.g, d.z, d.p, (T *)nullptr, d.G, d.partials, 0, 0,
+                      [&] { return StepScalars{true, beta_of(gl(d.st), 0, 0)}; },
                       vblk_of(m.local, nt, nt));
     } else {
         q_update_body(d.rt, d.q, d.G, d.st, d.partials + m.local, m.local - d.nb_t32);
