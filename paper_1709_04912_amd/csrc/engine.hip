@@ -360,13 +360,24 @@ template <typename T> void enqueue_after_search(const Group<T> &g, hipStream_t s
 template <typename T> void enqueue_head(const Group<T> &g, hipStream_t s, int suspend_tag)
 {
     const Enq<T> e{g, s};
+    const int tag = g.any_trB ? suspend_tag : 0;
     e.xtv();
+    if (!e.given()) {
+        // a single solve: the trial launch forms the opening's scalars
+        // itself and one finisher opens the step and decides its trials
+        {
+            Prof t(g.prof, SCG_KC_TRIALS, s);
+            launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, 1, s);
+        }
+        e.finish(kFinOpenTrials, 0, tag);
+        return;
+    }
     e.finish(kFinXtv);
     {
         Prof t(g.prof, SCG_KC_TRIALS, s);
-        launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, s);
+        launch_b_trials<T>(g.S, e.m(kKTrA), e.n(kKTrA), 0, 0, s);
     }
-    e.finish(kFinTrials, 0, g.any_trB ? suspend_tag : 0);
+    e.finish(kFinTrials, 0, tag);
 }
 
 // The rest of the iteration after the head: the second trial launch (with_b),
@@ -380,7 +391,7 @@ template <typename T> void enqueue_tail(const Group<T> &g, hipStream_t s, bool w
         // first launch accepted a step
         {
             Prof t(g.prof, SCG_KC_TRIALS, s);
-            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, s);
+            launch_b_trials<T>(g.S, e.m(kKTrB), e.n(kKTrB), kTrialsPerPass, 0, s);
         }
         e.finish(kFinTrials, kTrialsPerPass);
     }

@@ -223,25 +223,27 @@ __device__ double block_sum1(const double *partials, int nblk)
     return t;
 }
 
-// block_sum1 of two arrays with the loads of both in flight together; each
-// result has the bits block_sum1 gives for its array.
+// block_sum1 of two arrays (element b at pa[b * as], pb[b * bs]) with the
+// loads of both in flight together; each result has the bits block_sum1
+// gives for its array. The first kBlock threads take part, so a wider block
+// forms the same bits; every thread of the block must call it.
 __device__ void block_sum2(const double *pa, int na, const double *pb, int nb, double &sa,
-                           double &sb)
+                           double &sb, int as = 1, int bs = 1)
 {
     __shared__ double wsum[2][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int U = 8;
     const auto *ga = gl(pa);
     const auto *gb = gl(pb);
-    const int n = na > nb ? na : nb;
+    const int n = threadIdx.x < kBlock ? (na > nb ? na : nb) : 0;
     double acc_a = 0.0, acc_b = 0.0;
     for (int b0 = threadIdx.x; b0 < n; b0 += kBlock * U) {
         double va[U], vb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int b = b0 + kBlock * u;
-            va[u] = b < na ? ga[b] : 0.0;
-            vb[u] = b < nb ? gb[b] : 0.0;
+            va[u] = b < na ? ga[(size_t)b * as] : 0.0;
+            vb[u] = b < nb ? gb[(size_t)b * bs] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -252,7 +254,7 @@ __device__ void block_sum2(const double *pa, int na, const double *pb, int nb, d
     acc_a = wave_sum(acc_a);
     acc_b = wave_sum(acc_b);
     __syncthreads();   // a previous call's readers are done with wsum
-    if (lane == 0) {
+    if (lane == 0 && wid < kBlock / 64) {
         wsum[0][wid] = acc_a;
         wsum[1][wid] = acc_b;
     }
@@ -298,15 +300,28 @@ template <typename S> __device__ __forceinline__ void set_done(S *st, int status
 // the step that starts with counter value l (rounded to the image precision,
 // the value the trials and the accepted perturbation use). All threads of
 // the block take part.
+// gamma_{l+m} = gamma0 a^(l+m) (eq. of the gamma sequence), in the solve's
+// precision: every kernel that needs one forms it with this formula, so all
+// get the same bits.
+template <typename S> __device__ __forceinline__ double gamma_at(const S *st, int ell, int m)
+{
+    const double g = st->gamma0 * pow(st->a, (double)(ell + m));
+    return st->is_f32 ? (double)(float)g : g;
+}
+
 template <typename S> __device__ __forceinline__ void fill_gtab(double *gtab, S *st, int ell)
 {
-    const double g0 = st->gamma0, a = st->a;
-    const int mt = st->max_trials, f32 = st->is_f32;
+    const int mt = st->max_trials;
     auto *gt = gl(gtab);
-    for (int m = threadIdx.x; m < mt; m += blockDim.x) {
-        const double g = g0 * pow(a, (double)(ell + m));
-        gt[m] = f32 ? (double)(float)g : g;
-    }
+    for (int m = threadIdx.x; m < mt; m += blockDim.x) gt[m] = gamma_at(st, ell, m);
+}
+
+// The first trial launch's entries of the table, gamma_{l+m} for m <
+// kTrialsPerPass and the current l (the threads below kTrialsPerPass).
+template <typename S> __device__ __forceinline__ void fill_first_gammas(double *gtab, S *st)
+{
+    const int m = threadIdx.x;
+    if (m < kTrialsPerPass && m < st->max_trials) gl(gtab)[m] = gamma_at(st, st->ell, m);
 }
 
 inline int vec_blocks(size_t n)
@@ -1301,14 +1316,23 @@ __global__ __launch_bounds__(256) void kb_xtv(const Solve<T> *S, const BlkMap *m
     // projection's partials (recorded by this pass's finisher) or from the
     // state (given: a finisher formed it there with the same sums)
     const bool local = !given && local_alpha(st->variant) && st->open;
+    double gp = 0.0, qq = 0.0;
     auto alpha_of = [&]() -> double {
         if (!local) return st->alpha;
-        double gp, qq;
         block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
         return -gp / qq;
     };
     xtv_body(d.xh, d.p, d.x, d.s, d.G, d.partials2, d.st, alpha_of,
              vblk_of(m.local, (d.G.n + 31) / 32, (d.G.n + kXtvRows - 1) / kXtvRows));
+    // a single solve has no finisher between this pass and the first trial
+    // launch: the solve's first block records ||A p||^2 and g^T p of the step
+    // being closed for the finisher after that launch (no block reads them
+    // here)
+    if (local && m.local == 0 && threadIdx.x == 0) {
+        auto *stw = gl(d.st);
+        stw->qq = qq;
+        stw->gp = gp;
+    }
 }
 
 template <typename T>
@@ -1333,19 +1357,24 @@ static_assert((unsigned long long)kMaxN * kMaxN + (unsigned long long)kMaxPartia
                   (1ull << 32),
               "32-bit trial term indices");
 
-template <typename T>
+// Scalars of a trial launch: go = false ends the block at once; inv =
+// 1 / ||s||; gam(idx) = gamma_{l+idx}.
+struct TrialScalars {
+    bool go;
+    double inv;
+};
+
+template <typename T, typename F, typename Gam>
 __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, const Geo &G,
-                            const double *__restrict__ gtab_, double *partials,
-                            const DevState *st_, int first_m, int nchunks, VBlk vb)
+                            double *partials, const DevState *st_, int first_m, int nchunks,
+                            F scalars, Gam gam_at, VBlk vb)
 {
     const auto *x = gl(x_);
     const auto *s = gl(s_);
-    const auto *gtab = gl(gtab_);
     const auto *st = gl(st_);
     constexpr int M = kTrialsPerPass;
     const int max_trials = st->max_trials;
     const int stride = 1 + M * nchunks;
-    const T inv = (T)st->inv_snorm;
     const T k2 = (T)(st->kappa * st->kappa);
     // 32-bit indices: (n - 1)^2 plus one grid stride stays below 2^32 for
     // every accepted image side
@@ -1353,19 +1382,51 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
     const unsigned terms = m1 * m1;
     const unsigned bid = (unsigned)vb.id(), nblk = (unsigned)vb.count();
     const bool with_tvx = first_m == 0;
+    // the thread's first term is loaded before the scalars are formed (their
+    // block sums overlap the loads)
+    const unsigned q0 = bid * blockDim.x + threadIdx.x;
+    T f0[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (q0 < terms) {
+        const unsigned i = q0 / m1, j = q0 - i * m1;
+        const unsigned cq = i * n + j;
+        f0[0] = x[cq];
+        f0[1] = x[cq + n];
+        f0[2] = x[cq + 1];
+        f0[3] = s[cq];
+        f0[4] = s[cq + n];
+        f0[5] = s[cq + 1];
+    }
+    const TrialScalars sc = scalars();
+    if (!sc.go) return;
+    const T inv = (T)sc.inv;
     for (int c = 0; c < nchunks; ++c) {
         const int m0 = first_m + M * c;
         T gam[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) gam[m] = (T)gtab[min(m0 + m, max_trials - 1)];
+        for (int m = 0; m < M; ++m) gam[m] = (T)gam_at(min(m0 + m, max_trials - 1));
         T acc[M + 1];
 #pragma unroll
         for (int m = 0; m <= M; ++m) acc[m] = T(0);
-        for (unsigned q = bid * blockDim.x + threadIdx.x; q < terms; q += nblk * blockDim.x) {
-            const unsigned i = q / m1, j = q - i * m1;
-            const unsigned cq = i * n + j;
-            const T xc = x[cq], xd = x[cq + n], xr = x[cq + 1];
-            const T vc = -s[cq] * inv, vd = -s[cq + n] * inv, vr = -s[cq + 1] * inv;
+        for (unsigned q = q0; q < terms; q += nblk * blockDim.x) {
+            T xc, xd, xr, sc_, sd, sr;
+            if (c == 0 && q == q0) {
+                xc = f0[0];
+                xd = f0[1];
+                xr = f0[2];
+                sc_ = f0[3];
+                sd = f0[4];
+                sr = f0[5];
+            } else {
+                const unsigned i = q / m1, j = q - i * m1;
+                const unsigned cq = i * n + j;
+                xc = x[cq];
+                xd = x[cq + n];
+                xr = x[cq + 1];
+                sc_ = s[cq];
+                sd = s[cq + n];
+                sr = s[cq + 1];
+            }
+            const T vc = -sc_ * inv, vd = -sd * inv, vr = -sr * inv;
             if (with_tvx && c == 0) acc[M] += tv_term(xd - xc, xr - xc, k2);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -1384,25 +1445,56 @@ __device__ void trials_body(const T *__restrict__ x_, const T *__restrict__ s_, 
     }
 }
 
+// open = 1 (the first trial launch of a single solve, no finisher between
+// it and the TV pass): the launch forms what the step-opening finisher will
+// record, with the same formulas and the same sums: whether the step runs a
+// search (iteration cap, forced decisions, no perturbation, ||s|| > 0) and
+// 1 / ||s|| from the TV pass's partials. Otherwise those come from the state
+// the finisher left. Either way gamma_{l+m} comes from the table.
 template <typename T>
 __global__ __launch_bounds__(256) void kb_trials(const Solve<T> *S, const BlkMap *map,
-                                                  int first_m)
+                                                  int first_m, int open)
 {
     const BlkMap m = locate(map);
     const Solve<T> d = load_solve(S, m.solve);
-    if (gl(d.st)->done || gl(d.st)->search_done) return;
+    const auto *st = gl(d.st);
+    if (st->done) return;
     const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
     if (nchunks <= 0) return;
     const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
-    trials_body(d.x, d.s, d.G, d.gtab, d.partials, d.st, first_m, nchunks,
-                vblk_of(m.local, nblk, 1));
+    const VBlk vb = vblk_of(m.local, nblk, 1);
+    if (!open) {
+        if (st->search_done) return;
+        const auto *gtab = gl(d.gtab);
+        trials_body(d.x, d.s, d.G, d.partials, d.st, first_m, nchunks,
+                    [&] { return TrialScalars{true, st->inv_snorm}; },
+                    [&](int i) { return gtab[i]; }, vb);
+        return;
+    }
+    // the step the following finisher opens (see its kFinOpenTrials case)
+    const int step_open = st->open ? 1 : 0;
+    if (st->steps + step_open >= st->max_iter) return;
+    if (st->flags & SCG_FLAG_NO_PERTURB) return;
+    const int k = st->k + step_open + st->kofs;
+    if (d.forced != nullptr && k >= 1 && k - 1 < st->forced_len) return;
+    auto scalars = [&]() -> TrialScalars {
+        double tv, s2;
+        block_sum2(d.partials2, d.nb_xtv, d.partials2 + 1, d.nb_xtv, tv, s2, 2, 2);
+        const bool dir = s2 > 0.0 && isfinite(s2);
+        return TrialScalars{dir, dir ? 1.0 / sqrt(s2) : 0.0};
+    };
+    // gamma_{l+m}, m < kTrialsPerPass, for the l this step opens with: left
+    // in the table by the previous step's perturbation or the initial step
+    const auto *gtab = gl(d.gtab);
+    trials_body(d.x, d.s, d.G, d.partials, d.st, 0, 1, scalars,
+                [&](int i) { return gtab[i]; }, vb);
 }
 
 template <typename T>
-void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m,
+void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m, int open,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_trials<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map, first_m);
+    hipLaunchKernelGGL(kb_trials<T>, dim3(nblocks), dim3(kBlock), 0, s, S, map, first_m, open);
 }
 
 // ---------------------------------------------------------------------------
@@ -1475,6 +1567,9 @@ __global__ __launch_bounds__(256) void kb_perturb(const Solve<T> *S, const BlkMa
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     const int nt = (d.G.n + 31) / 32;
+    // the next step's first trial launch reads its gammas from the table: the
+    // solve's first block writes them for the l this step's search ended with
+    if (m.local == 0) fill_first_gammas(d.gtab, gl(d.st));
     perturb_body(d.x, d.s, d.xh, d.xs, d.G, d.st, vblk_of(m.local, nt, nt));
 }
 
@@ -1949,6 +2044,147 @@ void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_
 
 // Scalar logic of the finishers on the LDS copy of the state; every thread
 // of the block calls it (the sums are shared), thread 0 applies the logic.
+// Closes the previous step (alpha of the variants whose TV pass formed it,
+// from the recorded ||A p||^2 and g^T p; k; the carried scalars), applies the
+// iteration cap, and opens the new step: TV(x_k) = tv and ||s||^2 = s2 of the
+// TV pass, v = -s/||s||, replayed decisions, trace, and the trials' table.
+// Every thread of the block calls it.
+template <typename T>
+__device__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, double s2,
+                          int &s_go, int &s_ell, bool fill)
+{
+    if (threadIdx.x == 0) {
+        s_go = 0;
+        if (qa) {
+            const double qq = st->qq, gp = st->gp;
+            if (!isfinite(qq) || !isfinite(gp)) {
+                set_done(st, SCG_ENAN);
+            } else if (qq == 0.0) {
+                set_done(st, SCG_EBREAKDOWN);
+            } else {
+                st->alpha = -gp / qq;
+                if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
+            }
+        }
+    }
+    if (threadIdx.x == 0 && !st->done) {
+        if (st->open) {
+            st->qq_prev = st->qq;
+            st->gp_prev = st->gp;
+            st->k += 1;
+            st->steps += 1;
+        }
+        st->open = 1;
+        if (st->steps >= st->max_iter) {
+            set_done(st, SCG_ENOCONV);
+        } else {
+            const int k = st->k + st->kofs;   // the step opened here
+            st->trials_step = 0;
+            st->accepted = -1;
+            st->gamma = 0.0;
+            st->search_done = (st->flags & SCG_FLAG_NO_PERTURB) ? 1 : 0;
+            st->tv_x = tv;
+            st->s_norm2 = s2;
+            const bool dir = s2 > 0.0 && isfinite(s2);
+            st->inv_snorm = dir ? 1.0 / sqrt(s2) : 0.0;
+            if (auto *tr = trace_at(st, d.trace)) {
+                tr->k = k;
+                tr->accepted = -1;
+                tr->trials = 0;
+                tr->ell = st->ell;
+                tr->gamma = 0.0;
+                tr->beta = 0.0;
+                tr->alpha = 0.0;
+                tr->tv_x = tv;
+                tr->f_half = 0.0;
+            }
+            if (!st->search_done && d.forced != nullptr && k >= 1 && k - 1 < st->forced_len) {
+                const auto *fc = gl(d.forced);
+                const int nt = fc[2 * (k - 1)], am = fc[2 * (k - 1) + 1];
+                const int l0 = st->ell;
+                const double g = am >= 0 && dir ? gamma_at(st, l0, am) : 0.0;
+                st->ell = l0 + nt;
+                st->trials_step = nt;
+                st->trials_total += nt;
+                st->accepted = dir ? am : -1;
+                st->gamma = g;
+                st->search_done = 1;
+                if (auto *tr = trace_at(st, d.trace)) {
+                    tr->accepted = st->accepted;
+                    tr->trials = nt;
+                    tr->ell = st->ell;
+                    tr->gamma = g;
+                }
+            }
+            if (!st->search_done && !dir) {
+                // No nonascending direction: x_{k+1/2} = x_k and l is unchanged.
+                st->search_done = 1;
+            }
+            s_go = !st->search_done;
+            s_ell = st->ell;
+        }
+    }
+    __syncthreads();
+    if (fill && s_go) fill_gtab(d.gtab, st, s_ell);
+}
+
+// The trial decision of perturbed() after a trial launch: the first m with
+// TV(x + gamma_m v) <= TV(x), exactly as trying the values one after another;
+// l advances by the trials used. first_m = first trial of the launch (0 or
+// kTrialsPerPass). tag > 0 (first launch only): the second trial launch does
+// not follow in this iteration, and a search the first launch leaves open
+// suspends the solve (done = kSuspended, susp_tag = tag; every later launch
+// returns at once) until the host enqueues the rest of the step. Every
+// thread of the block calls it.
+template <typename T>
+__device__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int tag, double *tot)
+{
+    if (st->search_done) return;
+    const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
+    if (nchunks <= 0) return;
+    const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
+    const int stride = 1 + kTrialsPerPass * nchunks;
+    final_sums(d.partials, nblk, stride, stride, tot);
+    if (threadIdx.x != 0) return;   // the block's other threads are done
+    const bool with_tvx = first_m == 0;
+    const double tvx = with_tvx ? tot[0] : st->tv_x;
+    if (with_tvx) st->tv_x = tvx;
+    const int left = st->max_trials - first_m;
+    const int cap = kTrialsPerPass * nchunks;
+    const int nv = left < cap ? left : cap;
+    int hit = -1;
+    for (int m = 0; m < nv; ++m)
+        if (tot[1 + m] <= tvx) {
+            hit = m;
+            break;
+        }
+    const int used = hit >= 0 ? hit + 1 : nv;
+    st->ell += used;
+    st->trials_step += used;
+    st->trials_total += used;
+    if (hit >= 0) {
+        st->accepted = first_m + hit;
+        st->gamma = gl(d.gtab)[first_m + hit];
+        st->search_done = 1;
+    } else if (st->trials_step >= st->max_trials) {
+        st->accepted = -1;
+        st->gamma = 0.0;
+        st->search_done = 1;
+    }
+    if (st->search_done) {
+        if (auto *tr = trace_at(st, d.trace)) {
+            tr->accepted = st->accepted;
+            tr->trials = st->trials_step;
+            tr->ell = st->ell;
+            tr->gamma = st->gamma;
+            tr->tv_x = tvx;
+        }
+    } else if (first_m == 0 && tag > 0) {
+        st->done = kSuspended;
+        st->susp_tag = tag;
+    }
+}
+
 template <typename T>
 __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0, int arg1,
                              double *tot, int &s_go, int &s_ell)
@@ -1956,6 +2192,10 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
     switch (fin) {
     case kFinResidual:
     case kFinResidualStep: {
+        // the superiorized variants' initial step: the first trial launch's
+        // gammas (later steps get theirs from the perturbation)
+        if (fin == kFinResidual && st->variant != SCG_CG && st->variant != SCG_PCG)
+            fill_first_gammas(d.gtab, st);
         final_sums(d.partials, d.nb_pj, 1, 1, tot);
         if (threadIdx.x != 0) return;   // the block's other threads are done
         const double f = 0.5 * tot[0];
@@ -2075,59 +2315,9 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         st->steps += 1;
         return;
     }
-    case kFinTrials: {
-        // arg0 = first trial of the launch (0 or kTrialsPerPass). arg1 > 0
-        // (first launch only): the second trial launch does not follow in
-        // this iteration, and a search the first launch leaves open suspends
-        // the solve (done = kSuspended, susp_tag = arg1; every later launch
-        // returns at once) until the host enqueues the rest of the step
-        const int first_m = arg0;
-        if (st->search_done) return;
-        const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
-        if (nchunks <= 0) return;
-        const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
-        const int stride = 1 + kTrialsPerPass * nchunks;
-        final_sums(d.partials, nblk, stride, stride, tot);
-        if (threadIdx.x != 0) return;   // the block's other threads are done
-        const bool with_tvx = first_m == 0;
-        const double tvx = with_tvx ? tot[0] : st->tv_x;
-        if (with_tvx) st->tv_x = tvx;
-        const int left = st->max_trials - first_m;
-        const int cap = kTrialsPerPass * nchunks;
-        const int nv = left < cap ? left : cap;
-        int hit = -1;
-        for (int m = 0; m < nv; ++m)
-            if (tot[1 + m] <= tvx) {
-                hit = m;
-                break;
-            }
-        const int used = hit >= 0 ? hit + 1 : nv;
-        st->ell += used;
-        st->trials_step += used;
-        st->trials_total += used;
-        if (hit >= 0) {
-            st->accepted = first_m + hit;
-            st->gamma = gl(d.gtab)[first_m + hit];
-            st->search_done = 1;
-        } else if (st->trials_step >= st->max_trials) {
-            st->accepted = -1;
-            st->gamma = 0.0;
-            st->search_done = 1;
-        }
-        if (st->search_done) {
-            if (auto *tr = trace_at(st, d.trace)) {
-                tr->accepted = st->accepted;
-                tr->trials = st->trials_step;
-                tr->ell = st->ell;
-                tr->gamma = st->gamma;
-                tr->tv_x = tvx;
-            }
-        } else if (first_m == 0 && arg1 > 0) {
-            st->done = kSuspended;
-            st->susp_tag = arg1;
-        }
+    case kFinTrials:
+        trial_decision(d, st, arg0, arg1, tot);
         return;
-    }
     case kFinAlpha: {
         // alpha of the open step for the TV pass (local-alpha variants); the
         // TV pass's finisher records it
@@ -2166,92 +2356,35 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         return;
     }
     case kFinXtv: {
-        // Closes the previous step (k, the carried ||A p||^2 and g^T p),
-        // applies the iteration cap, opens the new step (TV(x_k), v =
-        // -s/||s||, replayed decisions, trace) and fills the trials' table.
-        // For the variants whose TV pass formed alpha itself, first records
-        // ||A p||^2 and alpha of the step being closed (the same sums).
-        if (threadIdx.x == 0) s_go = 0;
-        final_sums(d.partials2, d.nb_xtv, 2, 2, tot);
+        // Closes the previous step, opens the new one (open_step). For the
+        // variants whose TV pass formed alpha itself, first records ||A p||^2
+        // and g^T p of the step being closed (the same sums).
+        double tv, s2;
+        block_sum2(d.partials2, d.nb_xtv, d.partials2 + 1, d.nb_xtv, tv, s2, 2, 2);
         const bool qa = local_alpha(st->variant) && st->open;
         double qq = 0.0, gp = 0.0;
         if (qa) block_sum2(d.partials3, d.nb_t32, d.partials, d.nb_pj, gp, qq);
         if (threadIdx.x == 0 && qa) {
             st->qq = qq;
             st->gp = gp;
-            if (!isfinite(qq) || !isfinite(gp)) {
-                set_done(st, SCG_ENAN);
-            } else if (qq == 0.0) {
-                set_done(st, SCG_EBREAKDOWN);
-            } else {
-                st->alpha = -st->gp / qq;
-                if (auto *tr = trace_at(st, d.trace)) tr->alpha = st->alpha;
-            }
         }
-        if (threadIdx.x == 0 && !st->done) {
-            if (st->open) {
-                st->qq_prev = st->qq;
-                st->gp_prev = st->gp;
-                st->k += 1;
-                st->steps += 1;
-            }
-            st->open = 1;
-            s_go = 0;
-            if (st->steps >= st->max_iter) {
-                set_done(st, SCG_ENOCONV);
-            } else {
-                const int k = st->k + st->kofs;   // the step opened here
-                st->trials_step = 0;
-                st->accepted = -1;
-                st->gamma = 0.0;
-                st->search_done = (st->flags & SCG_FLAG_NO_PERTURB) ? 1 : 0;
-                st->tv_x = tot[0];
-                st->s_norm2 = tot[1];
-                const bool dir = tot[1] > 0.0 && isfinite(tot[1]);
-                st->inv_snorm = dir ? 1.0 / sqrt(tot[1]) : 0.0;
-                if (auto *tr = trace_at(st, d.trace)) {
-                    tr->k = k;
-                    tr->accepted = -1;
-                    tr->trials = 0;
-                    tr->ell = st->ell;
-                    tr->gamma = 0.0;
-                    tr->beta = 0.0;
-                    tr->alpha = 0.0;
-                    tr->tv_x = tot[0];
-                    tr->f_half = 0.0;
-                }
-                if (!st->search_done && d.forced != nullptr && k >= 1 && k - 1 < st->forced_len) {
-                    const auto *fc = gl(d.forced);
-                    const int nt = fc[2 * (k - 1)], am = fc[2 * (k - 1) + 1];
-                    const int l0 = st->ell;
-                    double g = 0.0;
-                    if (am >= 0 && dir) {
-                        g = st->gamma0 * pow(st->a, (double)(l0 + am));
-                        g = st->is_f32 ? (double)(float)g : g;
-                    }
-                    st->ell = l0 + nt;
-                    st->trials_step = nt;
-                    st->trials_total += nt;
-                    st->accepted = dir ? am : -1;
-                    st->gamma = g;
-                    st->search_done = 1;
-                    if (auto *tr = trace_at(st, d.trace)) {
-                        tr->accepted = st->accepted;
-                        tr->trials = nt;
-                        tr->ell = st->ell;
-                        tr->gamma = g;
-                    }
-                }
-                if (!st->search_done && !dir) {
-                    // No nonascending direction: x_{k+1/2} = x_k and l is unchanged.
-                    st->search_done = 1;
-                }
-                s_go = !st->search_done;
-                s_ell = st->ell;
-            }
-        }
+        open_step(d, st, qa, tv, s2, s_go, s_ell, true);
+        return;
+    }
+    case kFinOpenTrials: {
+        // A single solve: the step-boundary pass recorded ||A p||^2 and g^T p
+        // itself, and the first trial launch formed the opening's scalars with
+        // the same sums; the step is opened as kFinXtv does, then the first
+        // launch's trials are decided as kFinTrials does (arg1: as there).
+        // The table's first kTrialsPerPass entries already hold this step's
+        // gammas; a search that goes on gets the rest for the second launch.
+        double tv, s2;
+        block_sum2(d.partials2, d.nb_xtv, d.partials2 + 1, d.nb_xtv, tv, s2, 2, 2);
+        open_step(d, st, local_alpha(st->variant) && st->open, tv, s2, s_go, s_ell, false);
+        if (st->done) return;
+        trial_decision(d, st, 0, arg1, tot);
         __syncthreads();
-        if (s_go) fill_gtab(d.gtab, st, s_ell);
+        if (!st->search_done) fill_gtab(d.gtab, st, s_ell);
         return;
     }
     default:
@@ -2298,22 +2431,23 @@ __global__ __launch_bounds__(256) void kb_finish(const Solve<T> *S, int fin, int
     finish_body(S, (int)blockIdx.x, fin, arg0, arg1);
 }
 
-// The trials' finisher sums 17 values (or more) per block of the trial
-// launch, one wavefront per value: 16 wavefronts take them in two rounds
-// instead of five. Only the trial case runs here (its sums are
-// width-generic; the single-value block sums of the other cases assume
-// kBlock threads).
+// The trials' finishers (kFinTrials, kFinOpenTrials) sum 17 values (or more)
+// per block of the trial launch, one wavefront per value: 16 wavefronts take
+// them in two rounds instead of five. Only those cases run here: their sums
+// are width-generic or taken by the first kBlock threads (the single-value
+// block sums of the other cases assume kBlock threads).
 template <typename T>
-__global__ __launch_bounds__(1024) void kb_finish_wide(const Solve<T> *S, int arg0, int arg1)
+__global__ __launch_bounds__(1024) void kb_finish_wide(const Solve<T> *S, int fin, int arg0,
+                                                       int arg1)
 {
-    finish_body(S, (int)blockIdx.x, kFinTrials, arg0, arg1);
+    finish_body(S, (int)blockIdx.x, fin, arg0, arg1);
 }
 
 template <typename T>
 void launch_finish(const Solve<T> *S, int ns, int fin, int arg0, int arg1, hipStream_t s)
 {
-    if (fin == kFinTrials)
-        hipLaunchKernelGGL(kb_finish_wide<T>, dim3(ns), dim3(1024), 0, s, S, arg0, arg1);
+    if (fin == kFinTrials || fin == kFinOpenTrials)
+        hipLaunchKernelGGL(kb_finish_wide<T>, dim3(ns), dim3(1024), 0, s, S, fin, arg0, arg1);
     else
         hipLaunchKernelGGL(kb_finish<T>, dim3(ns), dim3(kBlock), 0, s, S, fin, arg0, arg1);
 }
@@ -2355,7 +2489,8 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_b_backproject<T>(const Solve<T> *, const BlkMap *, int, int, int,     \
                                           int, int, hipStream_t);                               \
     template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t);    \
-    template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t); \
+    template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, int,         \
+                                     hipStream_t);                                            \
     template void launch_b_perturb<T>(const Solve<T> *, const BlkMap *, int, hipStream_t);     \
     template void launch_b_p_update<T>(const Solve<T> *, const BlkMap *, int, int, int, int,   \
                                        int, hipStream_t);                                       \

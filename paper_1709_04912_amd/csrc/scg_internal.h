@@ -218,6 +218,9 @@ enum Fin : int {
     // f with the stop test and beta for the direction update
     kFinAlpha = 15,
     kFinStepScalars = 16,
+    // a single solve's step opening (kFinXtv) and first trial decision
+    // (kFinTrials) in one finisher after the first trial launch
+    kFinOpenTrials = 17,
 };
 
 // Block counts of the solver kernels for one solve.
@@ -263,7 +266,7 @@ template <typename T>
 void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given,
                   hipStream_t s);
 template <typename T>
-void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m,
+void launch_b_trials(const Solve<T> *S, const BlkMap *map, int nblocks, int first_m, int open,
                      hipStream_t s);
 template <typename T>
 void launch_b_perturb(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t s);
