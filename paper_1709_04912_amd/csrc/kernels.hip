@@ -2128,6 +2128,77 @@ __device__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, d
     if (fill && s_go) fill_gtab(d.gtab, st, s_ell);
 }
 
+// The two reductions of the step-opening trial finisher at once, in a block
+// wider than kBlock: its first kBlock / 64 waves form TV(x) and ||s||^2 of
+// the TV pass exactly as block_sum2 does (so the bits are those the first
+// trial launch formed), the other waves the first trial launch's 1 +
+// kTrialsPerPass sums into tot exactly as final_sums does (a value's bits do
+// not depend on which wave forms it). Every thread of the block calls it.
+template <typename T>
+__device__ void open_trial_sums(const Solve<T> &d, double &tv, double &s2, double *tot)
+{
+    constexpr int KW = kBlock / 64;
+    constexpr int U = 8;
+    __shared__ double wsum[2][KW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (wid < KW) {
+        const auto *pg = gl(d.partials2);
+        const int n = d.nb_xtv;
+        double acc_a = 0.0, acc_b = 0.0;
+        for (int b0 = threadIdx.x; b0 < n; b0 += kBlock * U) {
+            double va[U], vb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = b0 + kBlock * u;
+                va[u] = b < n ? pg[2 * (size_t)b] : 0.0;
+                vb[u] = b < n ? pg[2 * (size_t)b + 1] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b0 + kBlock * u < n) {
+                    acc_a += va[u];
+                    acc_b += vb[u];
+                }
+            }
+        }
+        acc_a = wave_sum(acc_a);
+        acc_b = wave_sum(acc_b);
+        if (lane == 0) {
+            wsum[0][wid] = acc_a;
+            wsum[1][wid] = acc_b;
+        }
+    } else {
+        const int nw = (int)(blockDim.x >> 6) - KW;
+        constexpr int stride = 1 + kTrialsPerPass;
+        const int nblk = d.nb_trA;
+        const auto *pg = gl(d.partials);
+        for (int k = wid - KW; k < stride; k += nw) {
+            double acc = 0.0;
+            for (int b0 = lane; b0 < nblk; b0 += 64 * U) {
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int b = b0 + 64 * u;
+                    v[u] = b < nblk ? pg[(size_t)b * stride + k] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (b0 + 64 * u < nblk) acc += v[u];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) tot[k] = acc;
+        }
+    }
+    __syncthreads();
+    tv = 0.0;
+    s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) {
+        tv += wsum[0][w];
+        s2 += wsum[1][w];
+    }
+}
+
 // The trial decision of perturbed() after a trial launch: the first m with
 // TV(x + gamma_m v) <= TV(x), exactly as trying the values one after another;
 // l advances by the trials used. first_m = first trial of the launch (0 or
@@ -2137,14 +2208,16 @@ __device__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, d
 // returns at once) until the host enqueues the rest of the step. Every
 // thread of the block calls it.
 template <typename T>
-__device__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int tag, double *tot)
+__device__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int tag, double *tot,
+                               bool summed = false)
 {
     if (st->search_done) return;
     const int nchunks = first_m == 0 ? 1 : d.trB_chunks;
     if (nchunks <= 0) return;
     const int nblk = first_m == 0 ? d.nb_trA : d.nb_trB;
     const int stride = 1 + kTrialsPerPass * nchunks;
-    final_sums(d.partials, nblk, stride, stride, tot);
+    // summed: tot already holds the launch's sums (open_trial_sums)
+    if (!summed) final_sums(d.partials, nblk, stride, stride, tot);
     if (threadIdx.x != 0) return;   // the block's other threads are done
     const bool with_tvx = first_m == 0;
     const double tvx = with_tvx ? tot[0] : st->tv_x;
@@ -2379,10 +2452,10 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
         // The table's first kTrialsPerPass entries already hold this step's
         // gammas; a search that goes on gets the rest for the second launch.
         double tv, s2;
-        block_sum2(d.partials2, d.nb_xtv, d.partials2 + 1, d.nb_xtv, tv, s2, 2, 2);
+        open_trial_sums(d, tv, s2, tot);
         open_step(d, st, local_alpha(st->variant) && st->open, tv, s2, s_go, s_ell, false);
         if (st->done) return;
-        trial_decision(d, st, 0, arg1, tot);
+        trial_decision(d, st, 0, arg1, tot, true);
         __syncthreads();
         if (!st->search_done) fill_gtab(d.gtab, st, s_ell);
         return;
