@@ -86,6 +86,49 @@ def measured_traffic(kernel):
     return int(m.group(1)) if m else None
 
 
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                                    "traffic_batched_64_solves_streaming_kernels.md")
+STREAMING_HBM = ("kb_xtv", "kb_perturb", "kb_p_update")   # bound by HBM (kb_trials: ALU)
+
+
+def batched_roofline():
+    """HBM roofline of the streaming kernels in the 64-solve batch, from the
+    committed rocprofv3 summary (kernel-trace durations, FETCH_SIZE /
+    WRITE_SIZE bytes of the same workload), or None when the kernels or
+    their launch layout have changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(BATCHED_TRAFFIC_FILE):
+        return None
+    text = open(BATCHED_TRAFFIC_FILE).read()
+    m = re.search(r"kernels\.hip \+ capi\.hip sha256: ([0-9a-f]{64})", text)
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if m is None or m.group(1) != h.hexdigest():
+        return None
+    per = {}
+    for k, n, cb, ab, us in re.findall(
+            r"^batched_kernel (\w+): launches=(\d+) counted_bytes=(\d+) "
+            r"algorithmic_bytes=(\d+) avg_us=([0-9.]+)$", text, flags=re.M):
+        d = float(us) * 1e-6
+        per[k] = {"launches": int(n), "avg_us": float(us), "algorithmic_bytes": int(ab),
+                  "traffic": int(cb), "achieved_GBs": int(ab) / d / 1e9,
+                  "frac": int(ab) / d / PEAK_HBM,
+                  "bound": "hbm" if k in STREAMING_HBM else "alu"}
+    hbm = {k: v for k, v in per.items() if v["bound"] == "hbm"}
+    if not hbm:
+        return None
+    dom = max(hbm, key=lambda k: hbm[k]["avg_us"] * hbm[k]["launches"])
+    v = hbm[dom]
+    return {"kernel": dom, "bound": "hbm", "achieved": v["achieved_GBs"],
+            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": v["frac"], "traffic": v["traffic"],
+            "source": os.path.relpath(BATCHED_TRAFFIC_FILE, ROOT) +
+                      " (durations from the rocprofv3 kernel trace of the batched workload, "
+                      "bytes from its FETCH_SIZE / WRITE_SIZE runs; full-batch launches)",
+            "per_kernel": per}
+
+
 def count_nnz(n, n_angles, n_bins):
     """Exact number of nonzero entries of A: for every angle and pixel, the
     bins b whose line crosses the pixel square with positive length, i.e.
@@ -229,7 +272,8 @@ def mixed_runs(n_serve, shape):
                                ("macro_steps", "graph_builds", "graph_updates", "rebuild_ns")},
         "eager_engine_stats": {k: be.engine_stats[0][k] for k in ("macro_steps", "rebuild_ns")},
         "solves": len(reqs), "launch_shape": list(shape),
-        "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports))}
+        "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports)),
+        "roofline": batched_roofline()}
     log(f"batched: {batched}")
     pool = SERVE_POOL
     log(f"served runs: generating {pool} distinct requests (eps = {LS_FACTOR} x f after "
