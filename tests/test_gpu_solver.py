@@ -129,8 +129,8 @@ def test_fp32_parity_scg_k(scg, torch_mod, oracle_lib, seed):
     variants. CG-K's recursive gradient amplifies rounding across passes, so
     the image bound is the larger of 1e-4 and the oracle's own amplification
     of a relative change of y (measured in FP64) applied to FP32's unit
-    roundoff, times 10; at 2 eps0 the amplification is below 1e3 and the
-    bound is 1e-4."""
+    roundoff, times 10; on these three workloads at 2 eps0 the amplification
+    is about 1.5, 7e3 and 1.4e4, so the bound is 1e-4, 4e-3 and 8e-3."""
     torch = torch_mod
     print(f"[solver fp32] variant=S_CG_K seed={seed}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, "S_CG_K")
