@@ -24,9 +24,10 @@ gamma0 = RHO ||x_1|| per request, outputs compared bitwise):
   `served`:  Poisson streams of (N, angles) in {(128, 180), (256, 360),
              (512, 720), (1024, 1440)} with weights 0.4/0.3/0.2/0.1 and
              per-request eps = 1.05 x f after 400 CG iterations (an upper
-             bound of the least-squares floor), at the specified mean rate of
-             200 requests/s (several times what one GPU sustains at that eps)
-             and at 20 requests/s; p50/p99 latency (completion - arrival), also
+             bound of the least-squares floor), 2000 requests at the
+             specified mean rate of 200 requests/s (several times what one GPU
+             sustains at that eps) and 300 at 20 requests/s (--serve-requests,
+             --sustained-requests); p50/p99 latency (completion - arrival), also
              per size, and recons/s of continuous batching with the 1024^2
              requests on an engine of their own against a FIFO of plain
              solves.
@@ -218,7 +219,7 @@ def cpu_baseline(w, eps, gamma0, steps_gpu):
     return out
 
 
-def mixed_runs(n_serve, shape):
+def mixed_runs(n_serve, n_sustained, shape):
     """Batched and served runs against plain one-at-a-time solves. Every plan
     gets `shape` (the autotuner's pick at 512^2): one shape makes each phase
     of the mix one launch, and one-at-a-time solves run as fast with it as
@@ -277,7 +278,7 @@ def mixed_runs(n_serve, shape):
     log(f"batched: {batched}")
     pool = SERVE_POOL
     log(f"served runs: generating {pool} distinct requests (eps = {LS_FACTOR} x f after "
-        f"{LS_STEPS} CG iterations) for streams of {n_serve}")
+        f"{LS_STEPS} CG iterations) for streams of {n_serve} and {n_sustained}")
     items = [make_serve_item(i) for i in range(pool)]
     base = [serve.make_request(i, cache, w.y, w.x_true, w.n, w.n_angles, w.n_bins, rho=RHO,
                                max_iter=2000, eps_rule="ls", ls_factor=LS_FACTOR,
@@ -293,17 +294,18 @@ def mixed_runs(n_serve, shape):
         "launch_shape": list(shape),
         "size_aware": "1024x1024 requests on an engine of their own (2 slots), 4 iterations of "
                       "it alternating with 4 of the other engine (64 slots)"}
-    for tag, rate, seed in (("as_specified_200_per_s", 200.0, 5000),
-                            ("sustainable_20_per_s", 20.0, 5001)):
-        arr = poisson_arrivals(seed, n_serve, rate)
+    for tag, rate, seed, count in (("as_specified_200_per_s", 200.0, 5000, n_serve),
+                                   ("sustainable_20_per_s", 20.0, 5001, n_sustained)):
+        t_run = time.perf_counter()
+        arr = poisson_arrivals(seed, count, rate)
         reqs = [serve.Request(i, base[i % pool].plan, base[i % pool].y, base[i % pool].params,
-                              float(arr[i])) for i in range(n_serve)]
-        log(f"served {tag}: {n_serve} requests")
+                              float(arr[i])) for i in range(count)]
+        log(f"served {tag}: {count} requests")
         bs = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=64, iters=4,
                                  keep_outputs=True, large_n=1024, large_iters=4,
                                  large_slots=2)
         p = serve.serve_plain(reqs, keep_outputs=True)
-        run = {"requests": n_serve, "rate_per_s": rate,
+        run = {"requests": count, "rate_per_s": rate,
                "batched_size_aware": bs.summary(reqs), "plain": p.summary(reqs),
                "bitwise_equal_outputs": same(p, bs),
                "all_eps_met": all(r.status == 0 and r.f_out <= r_.params.eps
@@ -311,6 +313,7 @@ def mixed_runs(n_serve, shape):
         if tag.startswith("sustainable"):
             b1 = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=64, iters=4)
             run["batched_one_engine"] = b1.summary(reqs)
+        run["bench_seconds"] = time.perf_counter() - t_run
         served[tag] = run
         log(f"served {tag}: {run}")
     log(f"served: {served}")
@@ -441,8 +444,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served runs")
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="requests per served stream (the survey's protocol: 2000)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served stream at the specified 200/s")
+    ap.add_argument("--sustained-requests", type=int, default=300,
+                    help="requests of the served stream at the sustainable 20/s")
     ap.add_argument("--counter-workload", metavar="SHAPES",
                     help="run only the hardware-counter workload with these launch shapes "
                          "(project_groups,backproject_split,project_angles,swizzle)")
@@ -580,7 +585,8 @@ def main():
     if not args.no_mix:
         shape = (tuning["project_groups"], tuning["backproject_split"],
                  tuning["project_angles"], tuning["swizzle"])
-        result["batched"], result["served"] = mixed_runs(args.serve_requests, shape)
+        result["batched"], result["served"] = mixed_runs(args.serve_requests,
+                                                         args.sustained_requests, shape)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(w, eps, gamma0, rep.steps)
