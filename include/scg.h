@@ -273,9 +273,12 @@ int scg_plan_autotune(scg_plan *plan, int prec, void *stream, scg_tuning *chosen
 typedef struct {
     int64_t launches;       /* launches that did their work                  */
     double  total_ms;       /* their summed event-to-event time              */
-    int64_t tail_launches;  /* launches enqueued after the solve had stopped  */
-    double  tail_ms;        /* (the last batch of iterations ran past the stop
-                               and its kernels returned at once)              */
+    int64_t tail_launches;  /* launches that returned at once: enqueued after
+                               the solve had stopped (the last batch of
+                               iterations ran past the stop), or behind a
+                               trial search that suspended the solve until
+                               the host enqueued the rest of its step         */
+    double  tail_ms;        /* their summed time                              */
 } scg_kernel_time;
 
 /* Times every kernel launch of the classes in class_mask (bit c = class c)
