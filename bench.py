@@ -262,13 +262,17 @@ def mixed_runs(n_serve, n_sustained, shape):
         runs["plain"].append(serve.serve_plain(reqs, keep_outputs=True))
     b, be, p = (min(runs[k], key=lambda r: r.wall_s) for k in ("graph", "eager", "plain"))
     runs.clear()
+    # the batched figure is the eager engine's, as the serving loop runs it
+    # (an iteration of the mix is milliseconds of GPU work, so the host stays
+    # ahead without a graph, and graph replays run a few per cent slower); the
+    # graph path is reported beside it
     batched = {
         "workload": "64 S-CG solves, N in {128,256,384,512}, angles in {180,360,540,720}, "
                     "bins ceil(sqrt(2)N)+1, sigma U[0.5%,3%], eps = f(x_true)",
-        "batched_recons_per_s": b.recons_per_s, "plain_recons_per_s": p.recons_per_s,
-        "speedup": b.recons_per_s / p.recons_per_s,
-        "batched_without_graph_recons_per_s": be.recons_per_s,
-        "bitwise_equal_outputs": same(p, b), "bitwise_equal_without_graph": same(p, be),
+        "batched_recons_per_s": be.recons_per_s, "plain_recons_per_s": p.recons_per_s,
+        "speedup": be.recons_per_s / p.recons_per_s,
+        "batched_with_graph_recons_per_s": b.recons_per_s,
+        "bitwise_equal_outputs": same(p, be), "bitwise_equal_with_graph": same(p, b),
         "graph_engine_stats": {k: b.engine_stats[0][k] for k in
                                ("macro_steps", "graph_builds", "graph_updates", "rebuild_ns")},
         "eager_engine_stats": {k: be.engine_stats[0][k] for k in ("macro_steps", "rebuild_ns")},
