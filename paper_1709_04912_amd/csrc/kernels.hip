@@ -2050,7 +2050,7 @@ void launch_b_filter(const Solve<T> *S, const BlkMap *map, int nblocks, int max_
 // TV pass, v = -s/||s||, replayed decisions, trace, and the trials' table.
 // Every thread of the block calls it.
 template <typename T>
-__device__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, double s2,
+__device__ __forceinline__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, double s2,
                           int &s_go, int &s_ell, bool fill)
 {
     if (threadIdx.x == 0) {
@@ -2135,7 +2135,7 @@ __device__ void open_step(const Solve<T> &d, DevState *st, bool qa, double tv, d
 // kTrialsPerPass sums into tot exactly as final_sums does (a value's bits do
 // not depend on which wave forms it). Every thread of the block calls it.
 template <typename T>
-__device__ void open_trial_sums(const Solve<T> &d, double &tv, double &s2, double *tot)
+__device__ __forceinline__ void open_trial_sums(const Solve<T> &d, double &tv, double &s2, double *tot)
 {
     constexpr int KW = kBlock / 64;
     constexpr int U = 8;
@@ -2208,7 +2208,7 @@ __device__ void open_trial_sums(const Solve<T> &d, double &tv, double &s2, doubl
 // returns at once) until the host enqueues the rest of the step. Every
 // thread of the block calls it.
 template <typename T>
-__device__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int tag, double *tot,
+__device__ __forceinline__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int tag, double *tot,
                                bool summed = false)
 {
     if (st->search_done) return;
@@ -2259,7 +2259,7 @@ __device__ void trial_decision(const Solve<T> &d, DevState *st, int first_m, int
 }
 
 template <typename T>
-__device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0, int arg1,
+__device__ __forceinline__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0, int arg1,
                              double *tot, int &s_go, int &s_ell)
 {
     switch (fin) {
@@ -2466,7 +2466,7 @@ __device__ void finish_logic(const Solve<T> &d, DevState *st, int fin, int arg0,
 }
 
 template <typename T>
-__device__ void finish_body(const Solve<T> *S, int solve, int fin, int arg0, int arg1)
+__device__ __forceinline__ void finish_body(const Solve<T> *S, int solve, int fin, int arg0, int arg1)
 {
     const Solve<T> d = load_solve(S, solve);
     __shared__ double tot[1 + kTrialsPerPass * kMaxTrialChunks];
