@@ -278,3 +278,28 @@ def test_scg_k_edges(scg, torch_mod, oracle_lib):
         with pytest.raises(scg.ScgError):
             plan.workspace_bytes(plan.params(eps=eps, gamma0=gamma0, variant="S_CG_K",
                                              restart_k=0))
+
+
+@pytest.mark.parametrize("variant,prec", [("S_CG", "f64"), ("S_PCG", "f64"), ("S_CG_K", "f64"),
+                                          ("S_CG", "f32")])
+def test_forced_own_decisions(scg, torch_mod, oracle_lib, variant, prec):
+    """Replaying a solve's own trial decisions through `forced` (for every
+    step, or for the first five only, the search taking over after them)
+    reproduces the solve bitwise: the replay sets the state the search would
+    have set (counter, trial count, accepted index and gamma_{l+m})."""
+    torch = torch_mod
+    w, g, prob, eps, gamma0 = _case(oracle_lib, 0, variant)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    y = torch.tensor(w.y.reshape(-1), dtype=dt, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        p = plan.params(eps=eps, gamma0=gamma0, variant=variant,
+                        prec=scg.SCG_F64 if prec == "f64" else scg.SCG_F32, max_iter=1000)
+        x, rep, trace = plan.solve(y, p)
+        dec = _decisions(trace)
+        assert len(dec) > 5 and any(a >= 0 for _, a in dec)
+        for forced in (dec, dec[:5]):
+            xf, repf, tracef = plan.solve(y, p, forced=forced)
+            assert _decisions(tracef) == dec
+            assert (repf.status, repf.k, repf.steps, repf.trials_total, repf.ell) == \
+                (rep.status, rep.k, rep.steps, rep.trials_total, rep.ell)
+            assert repf.f_out == rep.f_out and torch.equal(xf, x)
