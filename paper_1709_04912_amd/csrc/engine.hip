@@ -165,8 +165,9 @@ template <typename T> struct Enq {
     void p_update(int rule, int init) const
     {
         // S-CG, S-CG-CD, S-PCG after the initial step: the update records beta
-        // itself and the next TV pass's finisher records g'^T p', so no
-        // finisher of its own follows
+        // itself and g'^T p' is recorded with the next step's opening (by the
+        // TV pass's first block in a single solve, by kFinXtv in a batch), so
+        // no finisher of its own follows
         const bool rec = !init && rule <= 2 &&
                          (g.variant == SCG_S_CG || g.variant == SCG_S_CG_CD ||
                           g.variant == SCG_S_PCG);

@@ -1232,7 +1232,8 @@ void launch_b_tv(const Solve<T> *S, const BlkMap *map, int nblocks, hipStream_t 
 // the next step: x_{k+1} = x_{k+1/2} + alpha p' (the last line of the previous
 // step) on a 32 x 16 tile plus a one-pixel halo held in LDS, then the TV
 // subgradient s at x_{k+1}; the block stores its parts of TV(x_{k+1}) and
-// ||s||^2. The finisher closes the previous step and opens the next.
+// ||s||^2. The step is closed and the next opened by a finisher: kFinXtv in a
+// batch, the first trial launch's kFinOpenTrials in a single solve.
 // ---------------------------------------------------------------------------
 
 template <typename T, typename F>
@@ -1343,10 +1344,11 @@ void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given, 
 
 // ---------------------------------------------------------------------------
 // perturbed(): the trials of one step, TV(x + gamma_m v) for gamma_m =
-// gtab[m] (gamma0 a^(l+m)) and v = -s/||s||, in two launches, each followed
-// by a finisher. The first evaluates trials 0..kTrialsPerPass-1 together
-// with TV(x), summed in the same order; the second, which returns at once
-// when the first accepted, evaluates the remaining ones up to max_trials in
+// gtab[m] (gamma0 a^(l+m)) and v = -s/||s||, in up to two launches, each
+// followed by a finisher. The first evaluates trials 0..kTrialsPerPass-1
+// together with TV(x), summed in the same order; the second, which returns
+// at once when the first accepted (and which a single solve enqueues only
+// where a search needs it), evaluates the remaining ones up to max_trials in
 // chunks of kTrialsPerPass. The finisher takes the first m with
 // TV(x + gamma_m v) <= TV(x), exactly as trying the values one after
 // another; l advances by the trials used. Partials per block: [TV(x), trial
