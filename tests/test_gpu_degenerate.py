@@ -9,7 +9,7 @@ that is larger. eps lies 1 % of the way from the least-squares floor to
 f(0): closer to the floor, plain CG on the 5 x 5 image with 63 rays runs 15
 steps and amplifies such a change 1.4e10-fold, which no bound on the image
 survives. Launches here have one block per phase and partial sums of a
-handful of blocks."""
+handful of blocks. The operators alone are checked at the same geometries."""
 import numpy as np
 import pytest
 
@@ -76,3 +76,35 @@ def test_tiny_problem(oracle_lib, case, variant):
     assert err <= max(tol * nrm, 1e-12), (err, nrm)
     if ref.status == "ok":
         assert rep.f_out <= eps
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_tiny_operators(oracle_lib, case):
+    """A, A^T, the ramp filter, TV and its subgradient at the same geometries
+    against the oracle (FP32 within 1e-5, TV's value 1e-6; FP64 within
+    1e-12), and on a flat image, whose TV and subgradient are exactly zero."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_04912_amd import scg
+    n, na, nb = case
+    print(f"[tiny operators] {case}", flush=True)
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(7 * n + na + 3 * nb)
+    x = rng.uniform(-1, 1, n * n)
+    y = rng.uniform(-1, 1, na * nb)
+    refs = (g.project(x), g.backproject(y), g.filter(y), g.tv_subgrad(x))
+    tv_ref = g.tv(x)
+    with scg.Plan(n, na, nb) as plan:
+        for dt, tol, tol_tv in ((torch.float32, 1e-5, 1e-6), (torch.float64, 1e-12, 1e-12)):
+            xd = torch.tensor(x, dtype=dt, device="cuda")
+            yd = torch.tensor(y, dtype=dt, device="cuda")
+            tv, s = plan.tv(xd, subgrad=True)
+            got = (plan.project(xd), plan.backproject(yd), plan.filter(yd), s)
+            for out, ref in zip(got, refs):
+                out = out.cpu().numpy()
+                assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(ref), dt
+            assert abs(tv - tv_ref) <= tol_tv * tv_ref, dt
+            flat = torch.full((n * n,), 0.75, dtype=dt, device="cuda")
+            tv0, s0 = plan.tv(flat, subgrad=True)
+            assert tv0 == 0.0 and not s0.any(), dt
+    assert g.tv(np.full(n * n, 0.75)) == 0.0 and not g.tv_subgrad(np.full(n * n, 0.75)).any()
