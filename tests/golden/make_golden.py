@@ -1,6 +1,10 @@
 """Writes tests/golden/eps.json: the least-squares floor eps0 = min 1/2||y - Ax||^2
 (the paper's eps_0, Appendix) of seeded workloads, and the first CG iterate's
 norm used to set gamma0. Calls only the FP64 oracle and the input generator.
+Entries: the 64 x 64 workload (three seeds, dense least squares), the 256 x 256
+one, and two sizes that are no multiple of any of the library's tiles (97 x 97
+with 131 angles and 139 bins, 161 x 161 with 180 angles and 229 bins), whose
+floors are CG's upper bounds.
 
     python tests/golden/make_golden.py
 """
@@ -41,6 +45,8 @@ def main():
     for seed in (0, 1, 2):
         out[f"cfg1_s{seed}"] = entry(1, seed)
     out["cfg2_s0"] = entry(2, 0, dense=False)
+    out["ragged97_s0"] = entry(1, 0, dense=False, n=97, n_angles=131, n_bins=139)
+    out["ragged161_s0"] = entry(1, 0, dense=False, n=161, n_angles=180, n_bins=229)
     path = os.path.join(HERE, "eps.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)

@@ -1,0 +1,151 @@
+"""Solver parity at image sizes that are no multiple of any of the library's
+tiles, so every kernel runs several full tiles and a ragged one: 97 x 97
+pixels with 131 angles and 139 bins (three 32-row projector bands and one
+row, one full 128-bin chunk and 11 bins, an odd angle count) and 161 x 161
+with 180 angles and 229 bins (five bands and one row, a chunk and 101 bins).
+
+FP64, every variant but plain CG at 97 x 97 and S-CG and S-PCG at
+161 x 161, to the stop against the oracle: status, k, the trial decisions,
+eps met, and the image within 1e-8 relative. The restarted variants update
+their gradient recursively within a pass, and S-CG-K here amplifies a
+random relative change of y about 7e6-fold over its 44 passes; as rounding
+enters at every pass, not only through y, their bound is the larger of
+1e-8 and 10 times the passes times that amplification (measured by the
+test, seeded) applied to FP64's unit roundoff. Plain CG, whose residual
+is a recursion, is chaotic on these workloads once it nears the floor: a
+1e-16 relative change of y moves its f by 0.2 % around step 30 and its stop
+step between 17 and 18 at 161 x 161. It is compared with the oracle at 10
+steps (1e-8) and, at the stop, by the eps test on the oracle's f of the GPU
+image and a k within one step of those the oracle reaches under such
+changes of y. eps is 1.1 (97 x 97) or
+1.5 (161 x 161) times the least-squares floor in tests/golden/eps.json, 2
+times for S-CG-K, whose restarted passes approach the floor slowly. FP32
+operators with FP64 scalars: S-CG and S-PCG against the oracle on the
+FP32-rounded data, decisions checked against the oracle's FP64 margins
+(tests/parity_c10.py), image within 1e-4 with eps met."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import parity_c10 as c10
+from oracle import algorithms as alg
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EPS_FACTOR = {"ragged97_s0": 1.1, "ragged161_s0": 1.5}
+ORACLE = {
+    "CG": lambda p, x0, eps, pp, m: alg.cg(p, x0, eps, max_iter=m),
+    "PCG": lambda p, x0, eps, pp, m: alg.pcg(p, x0, eps, max_iter=m),
+    "S_CG": lambda p, x0, eps, pp, m: alg.scg(p, x0, eps, pp, max_iter=m),
+    "S_CG_CD": lambda p, x0, eps, pp, m: alg.scg_cd(p, x0, eps, pp, max_iter=m),
+    "S_PCG": lambda p, x0, eps, pp, m: alg.spcg(p, x0, eps, pp, max_iter=m),
+    "S_CG_K": lambda p, x0, eps, pp, m: alg.scg_k(p, x0, eps, pp, K=2, max_iter=m),
+    "S_PCG_K": lambda p, x0, eps, pp, m: alg.spcg_k(p, x0, eps, pp, K=2, max_iter=m),
+    "S_CG_3OP": lambda p, x0, eps, pp, m: alg.scg_3op(p, x0, eps, pp, max_iter=m),
+}
+FP64_CASES = [("ragged97_s0", v) for v in ORACLE if v != "CG"] + \
+             [("ragged161_s0", v) for v in ("S_CG", "S_PCG")]
+FP32_CASES = [("ragged97_s0", "S_CG"), ("ragged97_s0", "S_PCG"), ("ragged161_s0", "S_CG")]
+MAX_ITER = 1000
+
+
+def _case(oracle_lib, key, variant, y_of=lambda y: y):
+    with open(os.path.join(HERE, "golden", "eps.json")) as f:
+        gd = json.load(f)[key]
+    w = make_workload(gd["cfg"], gd["seed"], n=gd["n"], n_angles=gd["n_angles"],
+                      n_bins=gd["n_bins"], supersample=2)
+    g = oracle_lib.Geometry(w.n, w.n_angles, w.n_bins)
+    prob = alg.Problem(g, y_of(w.y))
+    eps = (2.0 if variant == "S_CG_K" else EPS_FACTOR[key]) * gd["eps0"]
+    return w, g, prob, eps, 0.05 * gd["x1_norm"]
+
+
+@pytest.mark.parametrize("key,variant", FP64_CASES)
+def test_ragged_fp64(oracle_lib, key, variant):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_04912_amd import scg
+    w, g, prob, eps, gamma0 = _case(oracle_lib, key, variant)
+    print(f"[ragged fp64] {key} {variant} eps={eps:.6g}", flush=True)
+    pp = alg.PerturbParams(gamma0)
+    ref = ORACLE[variant](prob, np.zeros(g.J), eps, pp, MAX_ITER)
+    assert ref.status == "ok"
+    nrm = float(np.linalg.norm(ref.x))
+    amp, tol = 0.0, 1e-8
+    if variant.endswith("_K"):
+        d = 1e-13 * np.random.default_rng(11).uniform(-1, 1, w.y.shape)
+        alt = ORACLE[variant](alg.Problem(g, w.y * (1 + d)), np.zeros(g.J), eps, pp, ref.steps)
+        amp = float(np.linalg.norm(alt.x - ref.x)) / nrm / 1e-13
+        tol = max(tol, 10 * ref.steps * amp * 2.0 ** -52)
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
+                        max_iter=MAX_ITER)
+        x, rep, trace = plan.solve(y, p)
+    rel = float(np.linalg.norm(x.cpu().numpy() - ref.x)) / nrm
+    print(f"  k {rep.k}/{ref.k} rel {rel:.2e} (amplification {amp:.3g}, tolerance {tol:.2e})",
+          flush=True)
+    assert rep.status == scg.SCG_OK and rep.k == ref.k
+    if variant.startswith("S_"):
+        assert [(t["trials"], t["accepted"]) for t in trace] == \
+            [(t["trials"], t["accepted"]) for t in ref.trace]
+    assert rep.f_out <= eps
+    assert rel <= tol
+
+
+@pytest.mark.parametrize("key", list(EPS_FACTOR))
+def test_ragged_cg(oracle_lib, key):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_04912_amd import scg
+    w, g, prob, eps, _ = _case(oracle_lib, key, "CG")
+    print(f"[ragged fp64] {key} CG eps={eps:.6g}", flush=True)
+    ref10 = alg.cg(prob, np.zeros(g.J), 1e-6 * eps, max_iter=10)
+    ks = [alg.cg(alg.Problem(g, w.y * (1 + d)), np.zeros(g.J), eps, max_iter=MAX_ITER).k
+          for d in (0.0, 1e-16, -1e-16, 1e-15, -1e-15)]
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        p = plan.params(eps=1e-6 * eps, gamma0=0.0, variant="CG", prec=scg.SCG_F64, max_iter=10)
+        x10, rep10, _ = plan.solve(y, p, trace=False)
+        p = plan.params(eps=eps, gamma0=0.0, variant="CG", prec=scg.SCG_F64, max_iter=MAX_ITER)
+        x, rep, _ = plan.solve(y, p, trace=False)
+    rel10 = float(np.linalg.norm(x10.cpu().numpy() - ref10.x) / np.linalg.norm(ref10.x))
+    print(f"  10 steps rel {rel10:.2e}; stop k {rep.k}, oracle's under changes of y {ks}",
+          flush=True)
+    assert rep10.status == scg.SCG_ENOCONV and rep10.k == 10 and rel10 <= 1e-8
+    assert rep.status == scg.SCG_OK and rep.f_out <= eps
+    assert prob.f(x.cpu().numpy()) <= eps * (1 + 1e-9)
+    assert min(ks) - 1 <= rep.k <= max(ks) + 1
+
+
+@pytest.mark.parametrize("key,variant", FP32_CASES)
+def test_ragged_fp32(oracle_lib, key, variant):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_04912_amd import scg
+    w, g, prob, eps, gamma0 = _case(oracle_lib, key, variant, c10.fp32_data)
+    print(f"[ragged fp32] {key} {variant} eps={eps:.6g}", flush=True)
+    pp = alg.PerturbParams(gamma0)
+    y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
+    with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        def run_gpu(forced, max_iter):
+            p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
+                            max_iter=MAX_ITER if max_iter is None else max_iter)
+            x, rep, trace = plan.solve(y, p, forced=forced)
+            return x.cpu().numpy().astype(np.float64), rep, trace
+
+        def run_oracle(max_iter):
+            return ORACLE[variant](prob, np.zeros(g.J), eps, pp,
+                                   MAX_ITER if max_iter is None else max_iter)
+
+        xg, rep, ref, kinds = c10.compare(f"{key} {variant}", run_gpu, run_oracle, eps)
+    rel = c10.rel_l2(xg, ref.x)
+    print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e}", flush=True)
+    assert rep.k == ref.k and rel <= 1e-4
+    if "stop" not in kinds:
+        assert rep.status == scg.SCG_OK and ref.status == "ok" and rep.f_out <= eps
+    assert prob.f(xg) <= eps * (1 + c10.MARGIN)
