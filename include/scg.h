@@ -230,15 +230,22 @@ size_t scg_static_workspace_bytes(void);
 
 /* Launch shapes of the two operators; results do not depend on them beyond
  * FP rounding order (the backprojector's angle split adds the groups' partial
- * sums in a fixed order, so each choice is itself deterministic). */
+ * sums in a fixed order, so each choice is itself deterministic). The
+ * mirrored backprojector takes angle theta's parameters for pi - theta (a
+ * trig table made exactly symmetric about the vertical axis), which moves
+ * A^T by about 1e-13 relative in FP64; the filtered variants' two-sinogram
+ * backprojection never runs mirrored. */
 typedef struct {
     int32_t project_groups;     /* 2 or 4: angle groups of 128 rays per projector block
                                    (256 or 512 threads)                               */
-    int32_t backproject_split;  /* 1, 2 or 4: angle split inside each 16 x 16 pixel tile
-                                   (128, 256 or 512 threads)                          */
+    int32_t backproject_split;  /* 1, 2 or 4 (8 with backproject_mirror): angle split
+                                   inside each 16 x 16 pixel tile (128 threads each) */
     int32_t project_angles;     /* 8 or 4: angles per projector block                 */
     int32_t swizzle;            /* 1: consecutive blocks of a launch share an XCD
                                    (chiplet and its L2), 0: hardware order            */
+    int32_t backproject_mirror; /* 1: each backprojector thread also forms the pixels
+                                   mirrored about the vertical axis from the same
+                                   footprint (half the tiles), 0: every tile      */
 } scg_tuning;
 
 /* Current shapes for precision prec. */

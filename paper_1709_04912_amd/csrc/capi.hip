@@ -393,8 +393,9 @@ bool tuning_valid(const scg_tuning &t)
 {
     return (t.project_groups == 2 || t.project_groups == 4) &&
            (t.backproject_split == 1 || t.backproject_split == 2 ||
-            t.backproject_split == 4) &&
-           (t.project_angles == 8 || t.project_angles == 4) && (t.swizzle == 0 || t.swizzle == 1);
+            t.backproject_split == 4 || (t.backproject_split == 8 && t.backproject_mirror == 1)) &&
+           (t.project_angles == 8 || t.project_angles == 4) && (t.swizzle == 0 || t.swizzle == 1) &&
+           (t.backproject_mirror == 0 || t.backproject_mirror == 1);
 }
 
 // Mean time of `reps` launches of `fn` on stream s, after one untimed launch.
@@ -439,20 +440,22 @@ int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
     constexpr int kRounds = 2;
     scg_tuning best = plan->tune[pi];
     struct PjCand { int ga, nq, swz; float ms; };
-    struct BpCand { int sp, swz; float ms; };
+    struct BpCand { int sp, mir, swz; float ms; };
     std::vector<PjCand> pj;
     std::vector<BpCand> bp;
     for (int ga : {8, 4})
         for (int nq : {2, 4})
             for (int swz : {0, 1}) pj.push_back({ga, nq, swz, -1.0f});
-    for (int sp : {1, 2, 4})
-        for (int swz : {0, 1}) bp.push_back({sp, swz, -1.0f});
+    for (int sp : {1, 2, 4, 8})
+        for (int mir : {0, 1})
+            for (int swz : {0, 1})
+                if (sp < 8 || mir) bp.push_back({sp, mir, swz, -1.0f});
     auto run_pj = [&](const PjCand &c) {
         scg::launch_project<T>(x, xs, G, plan->ptab[c.ga == 8 ? 0 : 1], y, G.rs, scg::kSinoPadL,
                                c.nq, c.swz, s);
     };
     auto run_bp = [&](const BpCand &c) {
-        scg::launch_backproject<T>(y, G, plan->bang, plan->border, x, c.sp, c.swz, s);
+        scg::launch_backproject<T>(y, G, plan->bang, plan->border, x, c.sp, c.mir, c.swz, s);
     };
     (void)time_launches([&] { run_pj(pj.front()); run_bp(bp.front()); }, s, 2 * kReps);
     auto keep = [](float &acc, float ms) {
@@ -479,6 +482,7 @@ int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
             best.project_angles = bpj->ga;
             best.project_groups = bpj->nq;
             best.backproject_split = bbp->sp;
+            best.backproject_mirror = bbp->mir;
             best.swizzle = swz;
         }
     }
@@ -732,14 +736,15 @@ int scg_backproject(scg_plan *plan, int prec, const void *y, void *x, void *stre
     if (prec == SCG_F32) {
         float *rp = static_cast<float *>(plan->rpad[0]);
         scg::launch_pad_sino<float>(static_cast<const float *>(y), rp, G, s);
+        const scg_tuning &t = plan->tune[0];
         scg::launch_backproject<float>(rp, G, plan->bang, plan->border, static_cast<float *>(x),
-                                       plan->tune[0].backproject_split, plan->tune[0].swizzle, s);
+                                       t.backproject_split, t.backproject_mirror, t.swizzle, s);
     } else {
         double *rp = static_cast<double *>(plan->rpad[1]);
         scg::launch_pad_sino<double>(static_cast<const double *>(y), rp, G, s);
+        const scg_tuning &t = plan->tune[1];
         scg::launch_backproject<double>(rp, G, plan->bang, plan->border, static_cast<double *>(x),
-                                        plan->tune[1].backproject_split, plan->tune[1].swizzle,
-                                        s);
+                                        t.backproject_split, t.backproject_mirror, t.swizzle, s);
     }
     return hip_status(hipGetLastError());
 }

@@ -106,7 +106,7 @@ template <typename T> int count_of(const Solve<T> &d, int kind)
 template <typename T> struct Group {
     int ns = 0;
     int variant = SCG_S_CG;
-    scg_tuning tune{4, 2, 8, 0};
+    scg_tuning tune{4, 2, 8, 0, 0};
     int max_nb = 1;
     int restart_k = 2;                      // S-CG-K
     const Solve<T> *S = nullptr;            // device descriptors
@@ -150,7 +150,7 @@ template <typename T> struct Enq {
     {
         Prof t(g.prof, SCG_KC_BACKPROJECT, s);
         launch_b_backproject<T>(g.S, m(kKBp), n(kKBp), phase, dot, g.tune.backproject_split,
-                                g.tune.swizzle, s);
+                                g.tune.backproject_mirror, g.tune.swizzle, s);
     }
     void finish(int fin, int a0 = 0, int a1 = 0) const
     {
@@ -230,6 +230,14 @@ inline bool unsuperiorized(int variant) { return variant == SCG_CG || variant ==
 inline bool filtered(int variant)
 {
     return variant == SCG_S_PCG || variant == SCG_PCG || variant == SCG_S_PCG_K;
+}
+// The launch shapes a solve runs with: the filtered variants backproject two
+// sinograms at once in one phase, which has no mirrored form, so their
+// solves keep the full tile grid throughout.
+inline scg_tuning solve_tuning(scg_tuning t, int variant)
+{
+    if (filtered(variant)) t.backproject_mirror = 0;
+    return t;
 }
 
 // Initial step. S- variants (steps 1-6 of the algorithms): x_{1/2} = x0, g0
@@ -498,7 +506,7 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.nb_t32 = blocks_t32(G);
     h.nb_vec = blocks_vec(J);
     h.nb_pj = h.P.n_chunks * h.P.n_groups;
-    h.nb_bp = blocks_bp(G);
+    h.nb_bp = blocks_bp(G, tune.backproject_mirror != 0);
     h.nb_sv = blocks_sv(G);
     h.trB_chunks = (std::max(pr->max_trials - kTrialsPerPass, 0) + kTrialsPerPass - 1) /
                    kTrialsPerPass;
@@ -590,7 +598,7 @@ int solve_impl(scg_plan *plan, const scg_params *pr, const void *y, const void *
     Staging<T> &stage = *new (static_cast<char *>(plan->host_pinned) + kPinnedStagingOffset)
         Staging<T>{};
     const int cap = trace_host != nullptr ? trace_cap : pr->max_iter + 1;
-    const scg_tuning tune = plan->tune[prec_index<T>()];
+    const scg_tuning tune = solve_tuning(plan->tune[prec_index<T>()], pr->variant);
     int rc = prepare_solve<T>(plan, pr, tune, ws, y, x0, xout, cap, forced_host, forced_len,
                               &stage, st0);
     if (rc) return rc;
@@ -964,7 +972,8 @@ int rebuild(scg_batch *b)
         const int pi = s.params.prec == SCG_F64 ? 1 : 0;
         const scg_tuning t = s.tune;
         keys[std::make_tuple(pi, (int)s.params.variant * 100 + s.params.restart_k,
-                             t.project_groups * 100 + t.backproject_split * 10 + t.swizzle,
+                             t.project_groups * 1000 + t.backproject_split * 100 +
+                                 t.backproject_mirror * 10 + t.swizzle,
                              t.project_angles)]
             .push_back(i);
     }
@@ -1169,7 +1178,7 @@ int submit_impl(scg_batch *b, scg_plan *plan, const scg_params *pr, const void *
     }
     char *ws = b->arena.base + slot.off;
     scg::Staging<T> &stage = staging_of<T>(b->staging[slot.staging]);
-    slot.tune = plan->tune[scg::prec_index<T>()];
+    slot.tune = scg::solve_tuning(plan->tune[scg::prec_index<T>()], pr->variant);
     int rc = scg::prepare_solve<T>(plan, pr, slot.tune, ws, y, x0, x_out, 0, nullptr, 0, &stage,
                                    b->stream, true);
     if (rc) return rc;

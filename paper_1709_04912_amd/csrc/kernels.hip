@@ -386,10 +386,10 @@ int blocks_xtv(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + kXtvRows - 1) 
 int blocks_t32(const Geo &G) { return ((G.n + 31) / 32) * ((G.n + 31) / 32); }
 int blocks_vec(size_t n) { return vec_blocks(n); }
 int blocks_sv(const Geo &G) { return G.na; }
-int blocks_bp(const Geo &G)
+int blocks_bp(const Geo &G, bool mirror)
 {
     const int t = (G.n + kBpTile - 1) / kBpTile;
-    return t * t;
+    return t * (mirror ? bp_mirror_cols(G.n) : t);
 }
 int blocks_trials(const Geo &G, int nchunks)
 {
@@ -811,33 +811,51 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 // per angle, its two bins are two LDS reads and its two weights two clamped
 // FMAs. DUAL
 // backprojects a second sinogram with the same weights (S-PCG: g' and z').
-// With partials given, the block stores its part of a dot product: dot = 1,
-// out (or out2 when DUAL) against dotv; dot = 2, out against itself; dot =
-// 3 (DUAL), out against out2.
+// MIR uses the image's mirror symmetry about its vertical axis: the pixel
+// (i, n-1-j) at angle pi - theta lies at the same detector position as
+// (i, j) at theta (and at angle 0 at the mirrored position), so one
+// footprint position and its two weights serve both pixels. The launch then
+// covers the tiles of the left ceil(n/2) columns; each thread reads a second
+// staged window, taken from the mirror angle's row (row 0 reversed for angle
+// 0), and also writes the mirror pixels. This uses angle theta's parameters
+// for pi - theta, i.e. a trig table made exactly symmetric, which moves A^T
+// by about 1e-13 relative in FP64 (the table's asymmetry is a few units in
+// the last place). With partials given, the block stores its part of a dot
+// product: dot = 1, out (or out2 when DUAL) against dotv; dot = 2, out
+// against itself; dot = 3 (DUAL), out against out2.
 // ---------------------------------------------------------------------------
 
 constexpr int kBpPrm = 4;   // per-angle parameters staged in LDS
-// Waves per SIMD the FP32 single-sinogram backprojector is held to (at most
-// 64 VGPRs); the others are left to the compiler.
-template <typename T, bool DUAL> constexpr int kBpWaves = sizeof(T) == 4 && !DUAL ? 8 : 1;
+// Waves per SIMD the FP32 backprojector is held to: eight (at most 64
+// VGPRs) for one sinogram and for the mirrored form's 1024-thread blocks (two
+// fit a CU's LDS), six for its smaller blocks; the others are left to the
+// compiler.
+template <typename T, bool DUAL, bool MIR, int NS>
+constexpr int kBpWaves = sizeof(T) != 4 || DUAL ? 1 : (MIR && NS < 8 ? 6 : 8);
 constexpr int kBpRt = kBpTile / (kBpThreads / kBpChunk);   // row terms per thread
 static_assert(kBpThreads % kBpChunk == 0 && kBpRt * (kBpThreads / kBpChunk) == kBpTile,
               "the threads of an angle cover the tile's rows");
 
-template <typename T, bool DUAL, int NS>
+template <typename T, bool DUAL, int NS, bool MIR = false>
 __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ r2, const Geo &G,
                                  const BpAngle *__restrict__ ang, T *__restrict__ out,
                                  T *__restrict__ out2, T *__restrict__ outT,
                                  const T *__restrict__ dotv, int dot, double *partials, VBlk vb)
 {
-    constexpr int NW = DUAL ? 2 : 1;
-    constexpr int NE = kBpChunk * kBpWin / kBpThreads;   // staged bins per thread and sinogram
-    __shared__ T win[NS][NW][kBpChunk * kBpWin];
+    static_assert(!(DUAL && MIR), "the mirrored form backprojects one sinogram");
+    constexpr int NW = DUAL || MIR ? 2 : 1;
+    // the mirrored form stages half as many angles per chunk, so that two
+    // 1024-thread blocks (eight angle groups) fit a CU's LDS
+    constexpr int CH = MIR ? kBpChunk / 2 : kBpChunk;
+    constexpr int RT = kBpTile / (kBpThreads / CH);   // row terms per thread
+    static_assert(kBpThreads % CH == 0 && RT * (kBpThreads / CH) == kBpTile, "row terms");
+    constexpr int NE = CH * kBpWin / kBpThreads;   // staged bins per thread and sinogram
+    __shared__ T win[NS][NW][CH * kBpWin];
     // angle parameters and row terms, two buffers: the next chunk's are
     // written while the current chunk's are read
-    __shared__ T prm[2][NS][kBpChunk * kBpPrm];
-    __shared__ T rowt[2][NS][kBpChunk * kBpTile];
-    static_assert(NS * NW * kBpChunk * kBpWin >= (NS - 1) * kBpThreads * 2 * NW,
+    __shared__ T prm[2][NS][CH * kBpPrm];
+    __shared__ T rowt[2][NS][CH * kBpTile];
+    static_assert(NS * NW * CH * kBpWin >= (NS - 1) * kBpThreads * 2 * NW,
                   "combine buffer fits in the windows");
     const int gs = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBpThreads);
     const int t = threadIdx.x % kBpThreads;
@@ -846,7 +864,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     const double xc = ((double)j0 + 7.5) - G.h, yc = G.h - ((double)i0 + 7.5);
     const T dx = (T)((double)tx - 7.5);
     T acc0 = T(0), acc1 = T(0), bcc0 = T(0), bcc1 = T(0);
-    const int nchunks = (G.na + kBpChunk - 1) / kBpChunk;
+    const int nchunks = (G.na + CH - 1) / CH;
 
     // Window of each angle of a chunk: first bin and 1/m, from the FP64
     // frame computed once per angle by the params step.
@@ -854,23 +872,23 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         int base;
         T m;
     };
-    __shared__ WinRef wref[NS][kBpChunk];
+    __shared__ WinRef wref[NS][CH];
     const Rsrc sino = buf_rsrc(r, (uint32_t)((size_t)G.na * G.rs * sizeof(T)));
     const Rsrc sino2 = buf_rsrc(DUAL ? r2 : r, (uint32_t)((size_t)G.na * G.rs * sizeof(T)));
 
     T pre[NW][NE];
-    // FP64 frame of the chunk's angles (kBpThreads / kBpChunk threads per
-    // angle, each computing it): the per-pixel parameters and kBpRt of the
+    // FP64 frame of the chunk's angles (kBpThreads / CH threads per
+    // angle, each computing it): the per-pixel parameters and RT of the
     // row terms, written to LDS buffer `buf`, and the window reference the
     // staging loads read.
     auto params = [&](int ch, int buf) {
-        const int al = t * kBpRt / kBpTile, r0 = t * kBpRt % kBpTile;
-        const int a = ch * kBpChunk + al;
-        T pp[kBpPrm], rt[kBpRt];
+        const int al = t * RT / kBpTile, r0 = t * RT % kBpTile;
+        const int a = ch * CH + al;
+        T pp[kBpPrm], rt[RT];
 #pragma unroll
         for (int k = 0; k < kBpPrm; ++k) pp[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < kBpRt; ++k) rt[k] = T(0);
+        for (int k = 0; k < RT; ++k) rt[k] = T(0);
         WinRef w{0, T(0)};
         if (a < G.na) {
             const BpAngle A = gl(ang)[a];
@@ -883,12 +901,12 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             pp[2] = W.C;
             pp[3] = W.CK;
 #pragma unroll
-            for (int k = 0; k < kBpRt; ++k) rt[k] = fma((T)(7.5 - (double)(r0 + k)), W.s, fr);
+            for (int k = 0; k < RT; ++k) rt[k] = fma((T)(7.5 - (double)(r0 + k)), W.s, fr);
             w.base = (int)fb;
             w.m = (T)A.inv_m;
         }
 #pragma unroll
-        for (int k = 0; k < kBpRt; ++k) rowt[buf][gs][t * kBpRt + k] = rt[k];
+        for (int k = 0; k < RT; ++k) rowt[buf][gs][t * RT + k] = rt[k];
         if (r0 == 0) {
 #pragma unroll
             for (int k = 0; k < kBpPrm; ++k) prm[buf][gs][al * kBpPrm + k] = pp[k];
@@ -898,7 +916,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     // staging loads of a chunk (after a barrier that follows its params):
     // bins outside the detector and angles past the last read as zero
     auto prefetch = [&](int ch) {
-        const int a0 = ch * kBpChunk;
+        const int a0 = ch * CH;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int q = t + e * kBpThreads;
@@ -911,6 +929,15 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
                 ok ? (uint32_t)(a * G.rs + kSinoPadL + bb) * (uint32_t)sizeof(T) : kBufOob;
             pre[0][e] = buf_load<T>(sino, vo, 0u) * w.m;
             if (DUAL) pre[NW - 1][e] = buf_load<T>(sino2, vo, 0u) * w.m;
+            if (MIR) {
+                // the mirror pixels' bins: angle na - a at the same bins, or
+                // for angle 0 its own row with the bins reversed
+                const int am = a == 0 ? 0 : G.na - a;
+                const int bm = a == 0 ? G.nb - 1 - bb : bb;
+                const uint32_t vm =
+                    ok ? (uint32_t)(am * G.rs + kSinoPadL + bm) * (uint32_t)sizeof(T) : kBufOob;
+                pre[1][e] = buf_load<T>(sino, vm, 0u) * w.m;
+            }
         }
     };
 
@@ -926,7 +953,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
                 win[gs][0][t + e * kBpThreads] = pre[0][e];
-                if (DUAL) win[gs][NW - 1][t + e * kBpThreads] = pre[NW - 1][e];
+                if (NW == 2) win[gs][NW - 1][t + e * kBpThreads] = pre[NW - 1][e];
             }
         }
         // the previous chunk's window references and the other buffer's
@@ -934,7 +961,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         if (ch + NS < nchunks) params(ch + NS, cb ^ 1);
         __syncthreads();
         if (ch + NS < nchunks) prefetch(ch + NS);
-        const int na = live ? min(kBpChunk, G.na - ch * kBpChunk) : 0;
+        const int na = live ? min(CH, G.na - ch * CH) : 0;
         // the chunk's terms are summed apart and then added to the pixel's
         // sum: rounding grows with the chunk size plus the chunk count
         T s0 = T(0), s1 = T(0), e0 = T(0), e1 = T(0);
@@ -953,7 +980,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             s0 = fma(w01, row[b0 + 1], s0);
             s1 = fma(w10, row[b1], s1);
             s1 = fma(w11, row[b1 + 1], s1);
-            if (DUAL) {
+            if (NW == 2) {
                 const T *row2 = &win[gs][NW - 1][al * kBpWin];
                 e0 = fma(w00, row2[b0], e0);
                 e0 = fma(w01, row2[b0 + 1], e0);
@@ -963,7 +990,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         }
         acc0 += s0;
         acc1 += s1;
-        if (DUAL) {
+        if (NW == 2) {
             bcc0 += e0;
             bcc1 += e1;
         }
@@ -977,7 +1004,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
             T *d = red + ((gs - 1) * kBpThreads + t) * 2 * NW;
             d[0] = acc0;
             d[1] = acc1;
-            if (DUAL) {
+            if (NW == 2) {
                 d[2] = bcc0;
                 d[3] = bcc1;
             }
@@ -988,7 +1015,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
                 const T *d = red + ((g - 1) * kBpThreads + t) * 2 * NW;
                 acc0 += d[0];
                 acc1 += d[1];
-                if (DUAL) {
+                if (NW == 2) {
                     bcc0 += d[2];
                     bcc1 += d[3];
                 }
@@ -1002,7 +1029,33 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     asm volatile("" : "+v"(te));
     const int i = i0 + (te >> 3), j = j0 + (te & 7) * 2;
     double dsum = 0.0;
-    if (gs == 0 && i < G.n) {
+    if (MIR && gs == 0 && i < G.n) {
+        // column j is written when it lies in the left ceil(n/2) columns,
+        // its mirror n-1-j when j lies in the left floor(n/2)
+        auto *og = gl(out);
+        auto *ogt = gl(outT);
+        const auto *dg = gl(dotv);
+        const T va[2] = {acc0, acc1}, vm[2] = {bcc0, bcc1};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int jq = j + q, jm = G.n - 1 - jq;
+            if (jq < jm + 1) {
+                const size_t p = (size_t)i * G.n + jq;
+                og[p] = va[q];
+                if (outT != nullptr) ogt[(size_t)jq * G.n + i] = va[q];
+                if (dot == 1) dsum += (double)va[q] * (double)dg[p];
+                else if (dot == 2) dsum += (double)va[q] * (double)va[q];
+            }
+            if (jq < jm) {
+                const size_t p = (size_t)i * G.n + jm;
+                og[p] = vm[q];
+                if (outT != nullptr) ogt[(size_t)jm * G.n + i] = vm[q];
+                if (dot == 1) dsum += (double)vm[q] * (double)dg[p];
+                else if (dot == 2) dsum += (double)vm[q] * (double)vm[q];
+            }
+        }
+    }
+    if (!MIR && gs == 0 && i < G.n) {
         const size_t p = (size_t)i * G.n + j;
         auto *og = gl(out);
         auto *og2 = gl(out2);
@@ -1030,41 +1083,55 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     block_store(v, partials + vb.id());
 }
 
-template <typename T, int NS>
+template <typename T, int NS, bool MIR>
 __global__ __launch_bounds__(kBpThreads * NS)
-__attribute__((amdgpu_waves_per_eu(kBpWaves<T, false>))) void k_backproject(const T *__restrict__ r, Geo G,
-                                                                  const BpAngle *__restrict__ ang,
-                                                                  const int *__restrict__ border,
-                                                                  T *__restrict__ out, int swz)
+__attribute__((amdgpu_waves_per_eu(kBpWaves<T, false, MIR, NS>))) void k_backproject(
+    const T *__restrict__ r, Geo G, const BpAngle *__restrict__ ang, const int *__restrict__ border,
+    T *__restrict__ out, int swz)
 {
     const int nt = (G.n + kBpTile - 1) / kBpTile;
-    const int tile = (swz || border == nullptr) ? launch_index(swz) : border[blockIdx.x];
-    backproject_body<T, false, NS>(r, nullptr, G, ang, out, nullptr, nullptr, nullptr, 0,
-                                   nullptr, vblk_of(tile, nt, nt));
+    // the heaviest-first tile order covers the full grid only
+    const int tile =
+        (MIR || swz || border == nullptr) ? launch_index(swz) : border[blockIdx.x];
+    backproject_body<T, false, NS, MIR>(r, nullptr, G, ang, out, nullptr, nullptr, nullptr, 0,
+                                        nullptr, vblk_of(tile, MIR ? bp_mirror_cols(G.n) : nt, nt));
+}
+
+template <typename T, bool MIR>
+void launch_bp_split(const T *r, const Geo &G, const BpAngle *ang, const int *border, T *out,
+                     int split, int swz, hipStream_t s)
+{
+    dim3 grid(blocks_bp(G, MIR));
+    if constexpr (MIR) {
+        if (split >= 8) {
+            hipLaunchKernelGGL((k_backproject<T, 8, MIR>), grid, dim3(kBpThreads * 8), 0, s, r,
+                               G, ang, border, out, swz);
+            return;
+        }
+    }
+    if (split >= 4)
+        hipLaunchKernelGGL((k_backproject<T, 4, MIR>), grid, dim3(kBpThreads * 4), 0, s, r, G,
+                           ang, border, out, swz);
+    else if (split == 2)
+        hipLaunchKernelGGL((k_backproject<T, 2, MIR>), grid, dim3(kBpThreads * 2), 0, s, r, G,
+                           ang, border, out, swz);
+    else
+        hipLaunchKernelGGL((k_backproject<T, 1, MIR>), grid, dim3(kBpThreads), 0, s, r, G, ang,
+                           border, out, swz);
 }
 
 template <typename T>
 void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, const int *border, T *out,
-                        int split, int swz, hipStream_t s)
+                        int split, int mirror, int swz, hipStream_t s)
 {
-    const int nt = (G.n + kBpTile - 1) / kBpTile;
-    dim3 grid(nt * nt);
-    if (split >= 4)
-        hipLaunchKernelGGL((k_backproject<T, 4>), grid, dim3(kBpThreads * 4), 0, s, r, G, ang,
-                           border, out, swz);
-    else if (split == 2)
-        hipLaunchKernelGGL((k_backproject<T, 2>), grid, dim3(kBpThreads * 2), 0, s, r, G, ang,
-                           border, out, swz);
-    else
-        hipLaunchKernelGGL((k_backproject<T, 1>), grid, dim3(kBpThreads), 0, s, r, G, ang, border,
-                           out, swz);
+    if (mirror) launch_bp_split<T, true>(r, G, ang, border, out, split, swz, s);
+    else launch_bp_split<T, false>(r, G, ang, border, out, split, swz, s);
 }
 
-template <typename T, bool DUAL, int NS>
+template <typename T, bool DUAL, int NS, bool MIR>
 __global__ __launch_bounds__(kBpThreads * NS)
-__attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL>))) void kb_backproject(const Solve<T> *S,
-                                                                   const BlkMap *map, int phase,
-                                                                   int dot, int swz)
+__attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL, MIR, NS>))) void kb_backproject(
+    const Solve<T> *S, const BlkMap *map, int phase, int dot, int swz)
 {
     const BlkMap m = locate(map, swz);
     const Solve<T> d = load_solve(S, m.solve);
@@ -1075,8 +1142,8 @@ __attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL>))) void kb_backproject(cons
     const int nt = (G.n + kBpTile - 1) / kBpTile;
     // the tile of this launch position (partials are stored by tile, so the
     // sums do not depend on the order)
-    const int tile = (swz || d.border == nullptr) ? m.local : gl(d.border)[m.local];
-    const VBlk vb = vblk_of(tile, nt, nt);
+    const int tile = (MIR || swz || d.border == nullptr) ? m.local : gl(d.border)[m.local];
+    const VBlk vb = vblk_of(tile, MIR ? bp_mirror_cols(G.n) : nt, nt);
     // one body instance: kBpH is h = A^T q (no second sinogram, no dot);
     // kBpG, kBpGZ are g' = A^T r (and z' = A^T rt) with the dot against h or g';
     // kBpGT is g' with its transpose in xs; kBpZ is z = A^T rt with the dot
@@ -1086,33 +1153,44 @@ __attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL>))) void kb_backproject(cons
     T *dst = hq ? d.h : (zq ? d.z : d.g);
     T *dstT = phase == kBpGT ? d.xs : nullptr;
     const T *dv = zq ? d.g : d.h;
-    backproject_body<T, DUAL, NS>(src, d.rt, G, ang, dst, d.z, dstT, dv, hq ? 0 : dot,
-                                  hq ? nullptr : d.partials, vb);
+    backproject_body<T, DUAL, NS, MIR>(src, d.rt, G, ang, dst, d.z, dstT, dv, hq ? 0 : dot,
+                                       hq ? nullptr : d.partials, vb);
 }
 
-template <typename T, bool DUAL>
+template <typename T, bool DUAL, bool MIR>
 void launch_b_bp_split(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int dot,
                        int split, int swz, hipStream_t s)
 {
+    if constexpr (MIR) {
+        if (split >= 8) {
+            hipLaunchKernelGGL((kb_backproject<T, DUAL, 8, MIR>), dim3(nblocks),
+                               dim3(kBpThreads * 8), 0, s, S, map, phase, dot, swz);
+            return;
+        }
+    }
     if (split >= 4)
-        hipLaunchKernelGGL((kb_backproject<T, DUAL, 4>), dim3(nblocks), dim3(kBpThreads * 4), 0,
-                           s, S, map, phase, dot, swz);
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 4, MIR>), dim3(nblocks),
+                           dim3(kBpThreads * 4), 0, s, S, map, phase, dot, swz);
     else if (split == 2)
-        hipLaunchKernelGGL((kb_backproject<T, DUAL, 2>), dim3(nblocks), dim3(kBpThreads * 2), 0,
-                           s, S, map, phase, dot, swz);
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 2, MIR>), dim3(nblocks),
+                           dim3(kBpThreads * 2), 0, s, S, map, phase, dot, swz);
     else
-        hipLaunchKernelGGL((kb_backproject<T, DUAL, 1>), dim3(nblocks), dim3(kBpThreads), 0, s,
-                           S, map, phase, dot, swz);
+        hipLaunchKernelGGL((kb_backproject<T, DUAL, 1, MIR>), dim3(nblocks), dim3(kBpThreads),
+                           0, s, S, map, phase, dot, swz);
 }
 
 template <typename T>
 void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int dot,
-                          int split, int swz, hipStream_t s)
+                          int split, int mirror, int swz, hipStream_t s)
 {
+    // the two-sinogram phase (filtered variants) never runs mirrored: a
+    // solve of such a variant is set up with the full tile grid
     if (phase == kBpGZ)
-        launch_b_bp_split<T, true>(S, map, nblocks, phase, dot, split, swz, s);
+        launch_b_bp_split<T, true, false>(S, map, nblocks, phase, dot, split, swz, s);
+    else if (mirror)
+        launch_b_bp_split<T, false, true>(S, map, nblocks, phase, dot, split, swz, s);
     else
-        launch_b_bp_split<T, false>(S, map, nblocks, phase, dot, split, swz, s);
+        launch_b_bp_split<T, false, false>(S, map, nblocks, phase, dot, split, swz, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -2554,7 +2632,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
                                     int, int, int, int, hipStream_t);                           \
     template void launch_pad_sino<T>(const T *, T *, const Geo &, hipStream_t);                \
     template void launch_backproject<T>(const T *, const Geo &, const BpAngle *, const int *,  \
-                                        T *, int, int, hipStream_t);                            \
+                                        T *, int, int, int, hipStream_t);                       \
     template void launch_tv<T>(const T *, T *, const Geo &, double, double *, double *,        \
                                hipStream_t);                                                    \
     template void launch_filter<T>(const T *, T *, const T *, const Geo &, int, hipStream_t);  \
@@ -2562,7 +2640,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
     template void launch_b_project<T>(const Solve<T> *, const BlkMap *, int, int, int, int,    \
                                       int, hipStream_t);                                        \
     template void launch_b_backproject<T>(const Solve<T> *, const BlkMap *, int, int, int,     \
-                                          int, int, hipStream_t);                               \
+                                          int, int, int, hipStream_t);                          \
     template void launch_b_xtv<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t);    \
     template void launch_b_trials<T>(const Solve<T> *, const BlkMap *, int, int, int,         \
                                      hipStream_t);                                            \

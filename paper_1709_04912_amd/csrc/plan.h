@@ -36,7 +36,7 @@ struct scg_plan {
     // positions, then the twiddles of each butterfly span (null where the
     // transform exceeds the LDS bound)
     void *ftab[2] = {nullptr, nullptr};
-    scg_tuning tune[2] = {{4, 4, 8, 0}, {4, 2, 8, 0}};  // launch shapes (F32, F64)
+    scg_tuning tune[2] = {{4, 4, 8, 0, 0}, {4, 2, 8, 0, 0}};  // launch shapes (F32, F64)
     double filt_mu[2] = {-1.0, -1.0};      // mu of each precision's spectrum
     // kernel timing (scg_profile): HIP events around launches of chosen classes
     struct ProfRec {

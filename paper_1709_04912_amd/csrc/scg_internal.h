@@ -34,6 +34,9 @@ constexpr int kBpThreads = 128;
 constexpr int kBpChunk = 32;
 constexpr int kBpWin = 32;
 constexpr int kBpHalf = 15;       // window start = floor(centre projection) - kBpHalf
+// Column tiles of the mirrored backprojector's launch: the tiles of the left
+// ceil(n/2) columns (each thread also writes the mirror pixels).
+__host__ __device__ inline int bp_mirror_cols(int n) { return ((n + 1) / 2 + kBpTile - 1) / kBpTile; }
 // Padded sinogram layout (solver residuals): rows of n_bins + 4 entries, bin b
 // at offset b + 1; the pads stay zero.
 constexpr int kSinoPadL = 1;
@@ -228,7 +231,7 @@ int blocks_xtv(const Geo &G);
 int blocks_t32(const Geo &G);
 int blocks_vec(size_t n);
 int blocks_trials(const Geo &G, int nchunks);
-int blocks_bp(const Geo &G);
+int blocks_bp(const Geo &G, bool mirror = false);
 int blocks_sv(const Geo &G);   // sinogram vector kernels
 
 // ---- launchers (kernels.hip) -------------------------------------------
@@ -244,7 +247,7 @@ void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, 
 template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hipStream_t s);
 template <typename T>
 void launch_backproject(const T *r, const Geo &G, const BpAngle *ang, const int *border, T *out,
-                        int split, int swz, hipStream_t s);
+                        int split, int mirror, int swz, hipStream_t s);
 template <typename T>
 void launch_tv(const T *x, T *s_out, const Geo &G, double kappa, double *partials,
                double *tv_dst, hipStream_t s);   // partials: vec_blocks(n^2) doubles
@@ -261,7 +264,7 @@ void launch_b_project(const Solve<T> *S, const BlkMap *map, int nblocks, int pha
                       int ga, int swz, hipStream_t s);
 template <typename T>
 void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase,
-                          int dot, int split, int swz, hipStream_t s);
+                          int dot, int split, int mirror, int swz, hipStream_t s);
 template <typename T>
 void launch_b_xtv(const Solve<T> *S, const BlkMap *map, int nblocks, int given,
                   hipStream_t s);

@@ -31,9 +31,12 @@ def torch_mod():
 
 
 # launch shapes per case (project_groups, backproject_split, project_angles,
-# swizzle): solves with different shapes run in different groups of a batch
-SHAPES = [(4, 4, 8, 0), (4, 2, 8, 0), (2, 1, 4, 1), (4, 4, 8, 0), (4, 4, 4, 1), (4, 4, 8, 1),
-          (2, 2, 8, 0), (4, 4, 4, 0), (4, 2, 8, 1), (2, 4, 4, 0), (4, 1, 8, 1)]
+# swizzle, backproject_mirror): solves with different shapes run in different
+# groups of a batch; the filtered variants' solves (S-PCG, PCG, S-PCG-K) drop
+# the mirrored form (their two-sinogram phase has none) and run every tile
+SHAPES = [(4, 4, 8, 0, 0), (4, 8, 8, 0, 1), (2, 1, 4, 1, 0), (4, 4, 8, 0, 1), (4, 4, 4, 1, 0),
+          (4, 8, 4, 1, 1), (2, 2, 8, 0, 0), (2, 2, 4, 0, 1), (4, 4, 8, 1, 1), (2, 4, 4, 0, 0),
+          (4, 1, 8, 1, 0)]
 
 # (n, n_angles, n_bins, variant, precision, seed)
 CASES = [
@@ -189,7 +192,7 @@ def test_arena_admission_and_cancel(scg, torch_mod, oracle_lib):
 
 def test_batch_against_oracle(scg, torch_mod, oracle_lib):
     """Two 64 x 64 workloads in one batch (one with non-default launch
-    shapes) against the FP64 oracle: each batched output is bitwise the one
+    shapes: the mirrored backprojector) against the FP64 oracle: each batched output is bitwise the one
     scg_solve gives alone, and that solve matches the oracle (relative L2
     1e-4, eps met) with its decisions checked against the oracle's FP64
     margins (tests/parity_c10.py), so the bound holds for every case."""
@@ -208,7 +211,7 @@ def test_batch_against_oracle(scg, torch_mod, oracle_lib):
         ref = alg.scg(prob, np.zeros(g.J), eps=eps, pp=pp, max_iter=1000)
         plan = scg.Plan(w.n, w.n_angles, w.n_bins)
         if seed == 1:
-            plan.set_tuning(scg.SCG_F32, 2, 2, 4, 1)
+            plan.set_tuning(scg.SCG_F32, 2, 8, 4, 1, 1)
         p = plan.params(eps=eps, gamma0=gamma0, max_iter=1000)
         items.append(((w.n,), plan, torch.tensor(w.y.reshape(-1), dtype=torch.float32,
                                                   device="cuda"), p))

@@ -45,7 +45,7 @@ def _problem(oracle_lib, case):
     return g, y, prob, eps, gamma0
 
 
-@pytest.mark.parametrize("variant", list(ORACLE))
+@pytest.mark.parametrize("variant", list(ORACLE) + ["S_CG/mirrored", "S_CG_K/mirrored"])
 @pytest.mark.parametrize("case", CASES)
 def test_tiny_problem(oracle_lib, case, variant):
     import torch
@@ -53,6 +53,7 @@ def test_tiny_problem(oracle_lib, case, variant):
     from paper_1709_04912_amd import scg
     g, y, prob, eps, gamma0 = _problem(oracle_lib, case)
     print(f"[tiny] {case} {variant} eps={eps:.4g}", flush=True)
+    variant, _, mirrored = variant.partition("/")
     pp = alg.PerturbParams(gamma0)
     ref = ORACLE[variant](prob, np.zeros(g.J), eps, pp, MAX_ITER)
     alt = ORACLE[variant](alg.Problem(g, y * (1 + 1e-13)), np.zeros(g.J), eps, pp, ref.steps)
@@ -61,6 +62,8 @@ def test_tiny_problem(oracle_lib, case, variant):
     tol = max(1e-8, 10 * amp * 2.0 ** -52)
     n, na, nb = case
     with scg.Plan(n, na, nb) as plan:
+        if mirrored:
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
         p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
                         max_iter=MAX_ITER)
         x, rep, trace = plan.solve(torch.tensor(y, dtype=torch.float64, device="cuda"), p)
@@ -80,9 +83,10 @@ def test_tiny_problem(oracle_lib, case, variant):
 
 @pytest.mark.parametrize("case", CASES)
 def test_tiny_operators(oracle_lib, case):
-    """A, A^T, the ramp filter, TV and its subgradient at the same geometries
-    against the oracle (FP32 within 1e-5, TV's value 1e-6; FP64 within
-    1e-12), and on a flat image, whose TV and subgradient are exactly zero."""
+    """A, A^T (also mirrored), the ramp filter, TV and its subgradient at the
+    same geometries against the oracle (FP32 within 1e-5, TV's value 1e-6;
+    FP64 within 1e-12), and on a flat image, whose TV and subgradient are
+    exactly zero."""
     import torch
     assert torch.cuda.is_available()
     from paper_1709_04912_amd import scg
@@ -95,12 +99,15 @@ def test_tiny_operators(oracle_lib, case):
     refs = (g.project(x), g.backproject(y), g.filter(y), g.tv_subgrad(x))
     tv_ref = g.tv(x)
     with scg.Plan(n, na, nb) as plan:
-        for dt, tol, tol_tv in ((torch.float32, 1e-5, 1e-6), (torch.float64, 1e-12, 1e-12)):
+        for prec, dt, tol, tol_tv in ((scg.SCG_F32, torch.float32, 1e-5, 1e-6),
+                                      (scg.SCG_F64, torch.float64, 1e-12, 1e-12)):
             xd = torch.tensor(x, dtype=dt, device="cuda")
             yd = torch.tensor(y, dtype=dt, device="cuda")
             tv, s = plan.tv(xd, subgrad=True)
-            got = (plan.project(xd), plan.backproject(yd), plan.filter(yd), s)
-            for out, ref in zip(got, refs):
+            got = [plan.project(xd), plan.backproject(yd), plan.filter(yd), s]
+            plan.set_tuning(prec, 4, 8, 8, 0, 1)    # mirrored backprojector
+            got.append(plan.backproject(yd))
+            for out, ref in zip(got, refs + (refs[1],)):
                 out = out.cpu().numpy()
                 assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(ref), dt
             assert abs(tv - tv_ref) <= tol_tv * tv_ref, dt

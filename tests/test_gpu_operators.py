@@ -62,13 +62,18 @@ def test_project_backproject(scg, torch_mod, oracle_lib, geom, kind):
     x, y = _inputs(geom, n * 7 + na, kind)
     ax_ref, aty_ref = g.project(x), g.backproject(y)
     with scg.Plan(n, na, nb) as plan:
-        for dt, tol in ((torch.float32, 1e-5), (torch.float64, 1e-12)):
+        for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
+                              (scg.SCG_F64, torch.float64, 1e-12)):
             xd = torch.tensor(x, dtype=dt, device="cuda")
             yd = torch.tensor(y, dtype=dt, device="cuda")
             ax = plan.project(xd).cpu().numpy()
             aty = plan.backproject(yd).cpu().numpy()
             assert _rel(ax, ax_ref) <= tol, (dt, _rel(ax, ax_ref))
             assert _rel(aty, aty_ref) <= tol, (dt, _rel(aty, aty_ref))
+            # the mirrored backprojector (eight angle groups per tile)
+            plan.set_tuning(prec, 4, 8, 8, 0, 1)
+            aty = plan.backproject(yd).cpu().numpy()
+            assert _rel(aty, aty_ref) <= tol, (dt, "mirrored", _rel(aty, aty_ref))
 
 
 @pytest.mark.parametrize("geom", [(64, 90, 95), (129, 77, 190)])
@@ -156,8 +161,11 @@ def test_filter_bin_limits(scg, torch_mod, oracle_lib):
 
 
 def test_full_size_sampled(scg, torch_mod, oracle_lib):
-    """512 x 512, 720 angles, 729 bins: the benchmark's operator launch,
-    checked on 400 sampled rays and 400 sampled pixels against the oracle."""
+    """512 x 512, 720 angles, 729 bins: the operator launches at the
+    benchmark's size, checked on 400 sampled rays and 400 sampled pixels
+    against the oracle: the default shapes, and the mirrored backprojector
+    with eight angle groups per tile (the autotuner's pick there) in FP32 and
+    FP64."""
     torch = torch_mod
     n, na, nb = 512, 720, 729
     g = oracle_lib.Geometry(n, na, nb)
@@ -174,6 +182,12 @@ def test_full_size_sampled(scg, torch_mod, oracle_lib):
     ref_t = g.backproject_pixels(y, pix)
     assert _rel(ax[rays], ref_a) <= 1e-5
     assert _rel(aty[pix], ref_t) <= 1e-5
+    with scg.Plan(n, na, nb) as plan:
+        for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
+                              (scg.SCG_F64, torch.float64, 1e-12)):
+            plan.set_tuning(prec, 4, 8, 4, 1, 1)
+            atm = plan.backproject(torch.tensor(y, dtype=dt, device="cuda")).cpu().numpy()
+            assert _rel(atm[pix], ref_t) <= tol, (dt, _rel(atm[pix], ref_t))
     # property at any size: the axis-angle projections conserve mass
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
 
@@ -204,22 +218,23 @@ def test_errors(scg, torch_mod):
         assert e.value.status == scg.SCG_EINVAL
 
 
-ALL_SHAPES = [(pg, bs, ga, sw) for pg in (2, 4) for bs in (1, 2, 4) for ga in (8, 4)
-              for sw in (0, 1)]
+ALL_SHAPES = [(pg, bs, ga, sw, mr) for mr in (0, 1) for pg in (2, 4)
+              for bs in ((1, 2, 4, 8) if mr else (1, 2, 4)) for ga in (8, 4) for sw in (0, 1)]
 SHAPE_CASES = ([((128, 180, 183), sh) for sh in ALL_SHAPES]
                + [(g, sh) for g in ((33, 45, 49), (100, 13, 200), (50, 7, 30))
-                  for sh in ((2, 1, 8, 0), (4, 4, 4, 1), (2, 2, 4, 1), (4, 2, 8, 1))])
+                  for sh in ((2, 1, 8, 0, 0), (4, 4, 4, 1, 0), (2, 2, 4, 1, 0), (4, 2, 8, 1, 0),
+                             (4, 8, 8, 0, 1), (2, 1, 4, 1, 1))])
 
 
 @pytest.mark.parametrize("geom,shape", SHAPE_CASES)
 def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
     """Every projector group count and angle-group size, backprojector angle
-    split and block order gives the oracle's A and A^T (FP32 1e-5, FP64
-    1e-12; the dual A^T of S-PCG is covered by the solver tests) and is
-    bitwise repeatable."""
+    split, mirrored or not, and block order gives the oracle's A and A^T (FP32
+    1e-5, FP64 1e-12; the dual A^T of S-PCG is covered by the solver tests)
+    and is bitwise repeatable."""
     torch = torch_mod
     n, na, nb = geom
-    pg, bs, ga, sw = shape
+    pg, bs, ga, sw, mr = shape
     print(f"[op shapes] geom={geom} shape={shape}", flush=True)
     g = oracle_lib.Geometry(n, na, nb)
     x, y = _inputs(geom, 3 * n + nb, "uniform")
@@ -228,9 +243,10 @@ def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
         for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
                               (scg.SCG_F64, torch.float64, 1e-12)):
             plan.set_tuning(prec, project_groups=pg, backproject_split=bs, project_angles=ga,
-                            swizzle=sw)
+                            swizzle=sw, backproject_mirror=mr)
             assert plan.tuning(prec) == {"project_groups": pg, "backproject_split": bs,
-                                         "project_angles": ga, "swizzle": sw}
+                                         "project_angles": ga, "swizzle": sw,
+                                         "backproject_mirror": mr}
             xd = torch.tensor(x, dtype=dt, device="cuda")
             yd = torch.tensor(y, dtype=dt, device="cuda")
             ax, aty = plan.project(xd), plan.backproject(yd)
@@ -244,10 +260,13 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
     with scg.Plan(64, 90, 95) as plan:
         for prec in (scg.SCG_F32, scg.SCG_F64):
             t = plan.autotune(prec)
-            assert t["project_groups"] in (2, 4) and t["backproject_split"] in (1, 2, 4)
+            assert t["project_groups"] in (2, 4) and t["backproject_split"] in (1, 2, 4, 8)
             assert t["project_angles"] in (8, 4) and t["swizzle"] in (0, 1)
+            assert t["backproject_mirror"] in (0, 1)
+            assert t["backproject_split"] < 8 or t["backproject_mirror"] == 1
             assert plan.tuning(prec) == t
-        for bad in ((3, 2, 8, 0), (4, 3, 8, 0), (0, 1, 8, 0), (4, 2, 6, 0), (4, 2, 8, 2)):
+        for bad in ((3, 2, 8, 0), (4, 3, 8, 0), (0, 1, 8, 0), (4, 2, 6, 0), (4, 2, 8, 2),
+                    (4, 8, 8, 0, 0), (4, 2, 8, 0, 2)):
             with pytest.raises(scg.ScgError):
                 plan.set_tuning(scg.SCG_F32, *bad)
 

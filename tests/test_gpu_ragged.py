@@ -48,7 +48,8 @@ ORACLE = {
     "S_CG_3OP": lambda p, x0, eps, pp, m: alg.scg_3op(p, x0, eps, pp, max_iter=m),
 }
 FP64_CASES = [("ragged97_s0", v) for v in ORACLE if v != "CG"] + \
-             [("ragged161_s0", v) for v in ("S_CG", "S_PCG")]
+             [("ragged161_s0", v) for v in ("S_CG", "S_PCG")] + \
+             [("ragged97_s0", "S_CG/mirrored"), ("ragged161_s0", "S_CG/mirrored")]
 FP32_CASES = [("ragged97_s0", "S_CG"), ("ragged97_s0", "S_PCG"), ("ragged161_s0", "S_CG")]
 MAX_ITER = 1000
 
@@ -69,8 +70,9 @@ def test_ragged_fp64(oracle_lib, key, variant):
     import torch
     assert torch.cuda.is_available()
     from paper_1709_04912_amd import scg
+    print(f"[ragged fp64] {key} {variant}", flush=True)
+    variant, _, mirrored = variant.partition("/")
     w, g, prob, eps, gamma0 = _case(oracle_lib, key, variant)
-    print(f"[ragged fp64] {key} {variant} eps={eps:.6g}", flush=True)
     pp = alg.PerturbParams(gamma0)
     ref = ORACLE[variant](prob, np.zeros(g.J), eps, pp, MAX_ITER)
     assert ref.status == "ok"
@@ -83,6 +85,8 @@ def test_ragged_fp64(oracle_lib, key, variant):
         tol = max(tol, 10 * ref.steps * amp * 2.0 ** -52)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        if mirrored:   # the mirrored backprojector, odd N: a centre column
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
         p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
                         max_iter=MAX_ITER)
         x, rep, trace = plan.solve(y, p)

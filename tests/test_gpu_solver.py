@@ -72,17 +72,25 @@ ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg, "S_CG_3O
                                                                      max_iter=max_iter)}
 
 
+# the mirrored backprojector with eight angle groups per tile (the
+# autotuner's pick at 512 x 512); S-PCG's solves keep the full tile grid
+MIRRORED = (4, 8, 8, 0, 1)
+
+
 @pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_K", "S_CG_3OP"])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
+@pytest.mark.parametrize("mirrored", [False, True])
+def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed, mirrored):
     torch = torch_mod
-    print(f"[solver fp64] variant={variant} seed={seed}", flush=True)
+    print(f"[solver fp64] variant={variant} seed={seed} mirrored={mirrored}", flush=True)
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
     ref = ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=alg.PerturbParams(gamma0),
                              max_iter=1000)
     assert ref.status == "ok"
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        if mirrored:
+            plan.set_tuning(scg.SCG_F64, *MIRRORED)
         p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64, max_iter=1000)
         x, rep, trace = plan.solve(y, p)
     assert rep.status == scg.SCG_OK
@@ -93,16 +101,20 @@ def test_fp64_parity(scg, torch_mod, oracle_lib, variant, seed):
     assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
 
 
-@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_3OP"])
+@pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_3OP", "S_CG/mirrored"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
     torch = torch_mod
     print(f"[solver fp32] variant={variant} seed={seed}", flush=True)
+    variant, _, mirrored = variant.partition("/")
     w, g, prob, eps, gamma0 = _case(oracle_lib, seed, variant)
     pp = alg.PerturbParams(gamma0)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float32, device="cuda")
     prob = alg.Problem(g, c10.fp32_data(w.y))
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        if mirrored:
+            plan.set_tuning(scg.SCG_F32, *MIRRORED)
+
         def run_gpu(forced, max_iter):
             p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F32,
                             max_iter=1000 if max_iter is None else max_iter)
@@ -113,8 +125,8 @@ def test_fp32_parity(scg, torch_mod, oracle_lib, variant, seed):
             return ORACLE_FN[variant](prob, np.zeros(g.J), eps=eps, pp=pp,
                                       max_iter=1000 if max_iter is None else max_iter)
 
-        xg, rep, ref, kinds = c10.compare(f"64x64 {variant} seed {seed}", run_gpu, run_oracle,
-                                          eps)
+        xg, rep, ref, kinds = c10.compare(f"64x64 {variant}{'/mirrored' if mirrored else ''} "
+                                          f"seed {seed}", run_gpu, run_oracle, eps)
     rel = _rel(xg, ref.x)
     print(f"  k={rep.k} ref_k={ref.k} replayed={kinds} rel={rel:.2e}")
     assert rep.k == ref.k and rel <= 1e-4
