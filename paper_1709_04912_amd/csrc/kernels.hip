@@ -29,6 +29,19 @@ template <typename P> __device__ __forceinline__ auto gl(P *p)
 #endif
 }
 
+// Read-only data that a kernel indexes uniformly across a wavefront (per-angle
+// constants): constant-qualified views, which the compiler reads through the
+// scalar cache into scalar registers.
+template <typename P> __device__ __forceinline__ auto cst(const P *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    using C = const __attribute__((address_space(4))) P;
+    return (C *)p;
+#else
+    return p;
+#endif
+}
+
 constexpr int kBlock = 256;
 constexpr int kXtvRows = 16;   // tile height of the step-boundary TV pass (two rows per thread)
 constexpr int kMaxVecBlocks = 512;
@@ -850,12 +863,14 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
     constexpr int RT = kBpTile / (kBpThreads / CH);   // row terms per thread
     static_assert(kBpThreads % CH == 0 && RT * (kBpThreads / CH) == kBpTile, "row terms");
     constexpr int NE = CH * kBpWin / kBpThreads;   // staged bins per thread and sinogram
-    __shared__ T win[NS][NW][CH * kBpWin];
+    // an angle's windows side by side (the second one's reads take the
+    // first one's address plus an immediate offset)
+    __shared__ T win[NS][CH][NW][kBpWin];
     // angle parameters and row terms, two buffers: the next chunk's are
     // written while the current chunk's are read
     __shared__ T prm[2][NS][CH * kBpPrm];
     __shared__ T rowt[2][NS][CH * kBpTile];
-    static_assert(NS * NW * CH * kBpWin >= (NS - 1) * kBpThreads * 2 * NW,
+    static_assert(NS * CH * NW * kBpWin >= (NS - 1) * kBpThreads * 2 * NW,
                   "combine buffer fits in the windows");
     const int gs = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBpThreads);
     const int t = threadIdx.x % kBpThreads;
@@ -908,8 +923,10 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 #pragma unroll
         for (int k = 0; k < RT; ++k) rowt[buf][gs][t * RT + k] = rt[k];
         if (r0 == 0) {
+            if (!MIR) {
 #pragma unroll
-            for (int k = 0; k < kBpPrm; ++k) prm[buf][gs][al * kBpPrm + k] = pp[k];
+                for (int k = 0; k < kBpPrm; ++k) prm[buf][gs][al * kBpPrm + k] = pp[k];
+            }
             wref[gs][al] = w;
         }
     };
@@ -952,8 +969,15 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         if (live) {
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
-                win[gs][0][t + e * kBpThreads] = pre[0][e];
-                if (NW == 2) win[gs][NW - 1][t + e * kBpThreads] = pre[NW - 1][e];
+                const unsigned q = t + e * kBpThreads;   // angle q / kBpWin, bin q % kBpWin
+                T *wb = &win[gs][0][0][0];
+                if (NW == 1) {
+                    wb[q] = pre[0][e];
+                } else {
+                    const unsigned o = (q / kBpWin) * (NW * kBpWin) + q % kBpWin;
+                    wb[o] = pre[0][e];
+                    wb[o + kBpWin] = pre[NW - 1][e];
+                }
             }
         }
         // the previous chunk's window references and the other buffer's
@@ -967,25 +991,56 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
         T s0 = T(0), s1 = T(0), e0 = T(0), e1 = T(0);
 #pragma unroll 2
         for (int al = 0; al < na; ++al) {
-            const T *pr = &prm[cb][gs][al * kBpPrm];
-            const T c = pr[0], K = pr[1], C = pr[2], CK = pr[3];
+            // the angle's footprint constants, uniform across the wavefront:
+            // the mirrored form, whose LDS reads are twice as many, takes
+            // them from the angle table through the scalar cache; the others
+            // from the chunk's LDS copy
+            T c, K, C, CK;
+            if constexpr (MIR) {
+                const auto &A = cst(ang)[ch * CH + al];
+                if constexpr (sizeof(T) == 4) {
+                    c = A.cf;
+                    K = A.Kf;
+                    C = A.Cf;
+                    CK = A.CKf;
+                } else {
+                    c = A.c;
+                    K = A.K;
+                    C = A.C;
+                    CK = A.C - A.K;
+                }
+            } else {
+                const T *pr = &prm[cb][gs][al * kBpPrm];
+                c = pr[0];
+                K = pr[1];
+                C = pr[2];
+                CK = pr[3];
+            }
             const T u0 = fma(dx, c, rowt[cb][gs][al * kBpTile + ty]);
             const T u1 = u0 + c;
-            const T *row = &win[gs][0][al * kBpWin];
+            const T *row = &win[gs][al][0][0];
             const int b0 = (int)u0, b1 = (int)u1;   // u > 0: truncation is floor
             const T f0 = frc(u0), f1 = frc(u1);
             const T w00 = sat(fma(f0, -K, C)), w01 = sat(fma(f0, K, CK));
             const T w10 = sat(fma(f1, -K, C)), w11 = sat(fma(f1, K, CK));
-            s0 = fma(w00, row[b0], s0);
-            s0 = fma(w01, row[b0 + 1], s0);
-            s1 = fma(w10, row[b1], s1);
-            s1 = fma(w11, row[b1 + 1], s1);
             if (NW == 2) {
-                const T *row2 = &win[gs][NW - 1][al * kBpWin];
-                e0 = fma(w00, row2[b0], e0);
-                e0 = fma(w01, row2[b0 + 1], e0);
-                e1 = fma(w10, row2[b1], e1);
-                e1 = fma(w11, row2[b1 + 1], e1);
+                // both windows' bins are read before they are summed
+                const T x00 = row[b0], x01 = row[b0 + 1], x10 = row[b1], x11 = row[b1 + 1];
+                const T y00 = row[kBpWin + b0], y01 = row[kBpWin + b0 + 1];
+                const T y10 = row[kBpWin + b1], y11 = row[kBpWin + b1 + 1];
+                s0 = fma(w00, x00, s0);
+                s0 = fma(w01, x01, s0);
+                s1 = fma(w10, x10, s1);
+                s1 = fma(w11, x11, s1);
+                e0 = fma(w00, y00, e0);
+                e0 = fma(w01, y01, e0);
+                e1 = fma(w10, y10, e1);
+                e1 = fma(w11, y11, e1);
+            } else {
+                s0 = fma(w00, row[b0], s0);
+                s0 = fma(w01, row[b0 + 1], s0);
+                s1 = fma(w10, row[b1], s1);
+                s1 = fma(w11, row[b1 + 1], s1);
             }
         }
         acc0 += s0;
@@ -998,7 +1053,7 @@ __device__ void backproject_body(const T *__restrict__ r, const T *__restrict__ 
 
     if (NS > 1) {
         // groups 1..NS-1 hand their sums to group 0 through the windows
-        T *red = &win[0][0][0];
+        T *red = &win[0][0][0][0];
         __syncthreads();
         if (gs > 0) {
             T *d = red + ((gs - 1) * kBpThreads + t) * 2 * NW;

@@ -76,7 +76,7 @@ def test_size_aware_engines_and_ls_eps(stream):
     result, and the ls rule's eps lies above the CG value it came from."""
     from paper_1709_04912_amd import scg
     serve, reqs = stream
-    cache = serve.PlanCache(shape=(4, 4, 4, 0))
+    cache = serve.PlanCache(shape=(4, 8, 4, 0, 1))
     items = [make_serve_item(i, shapes=SHAPES) for i in range(8)]
     base = [serve.make_request(i, cache, w.y, w.x_true, w.n, w.n_angles, w.n_bins,
                                eps_rule="ls", ls_steps=60) for i, w in enumerate(items)]
