@@ -119,3 +119,37 @@ def test_edge_ray_halves(oracle_lib):
     r[0, nz[0]] = 1.0
     bp = g.backproject(r).reshape(n, n)
     assert bp[3, 4] == 0.5 and bp[3, 3] == 0.5
+
+
+@pytest.mark.parametrize("geom", [(7, 9, 11), (8, 12, 10), (33, 45, 49), (64, 90, 95),
+                                  (5, 1, 8), (20, 7, 12)])
+def test_mirror_symmetry(oracle_lib, geom):
+    """The symmetry the mirrored backprojector relies on: mirroring the image
+    about its vertical axis maps the ray at angle theta_a and bin b to the ray
+    at angle theta_{n_a - a} and the same bin (a >= 1), and angle 0's rays to
+    the reversed bins of angle 0. So A^T of the sinogram with its rows
+    mirrored that way is A^T y mirrored, and A of the mirrored image is A x
+    with its rows mirrored, up to the rounding of the trig table."""
+    n, na, nb = geom
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(n + na)
+    x = rng.uniform(-1, 1, (n, n))
+    y = rng.uniform(-1, 1, (na, nb))
+
+    def mirror_rows(s):
+        m = np.empty_like(s)
+        m[0] = s[0, ::-1]
+        m[1:] = s[:0:-1]
+        return m
+
+    aty = g.backproject(y.reshape(-1)).reshape(n, n)
+    aty_m = g.backproject(mirror_rows(y).reshape(-1)).reshape(n, n)
+    assert np.linalg.norm(aty_m - aty[:, ::-1]) <= 1e-13 * np.linalg.norm(aty)
+    ax = g.project(x.reshape(-1)).reshape(na, nb)
+    ax_m = g.project(x[:, ::-1].reshape(-1)).reshape(na, nb)
+    assert np.linalg.norm(ax_m - mirror_rows(ax)) <= 1e-13 * np.linalg.norm(ax)
+    # a plausible mistake fails: pairing angle a with n_a - 1 - a instead
+    if na > 2:
+        wrong = y[::-1]
+        aty_w = g.backproject(wrong.reshape(-1)).reshape(n, n)
+        assert np.linalg.norm(aty_w - aty[:, ::-1]) > 1e-3 * np.linalg.norm(aty)
