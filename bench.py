@@ -297,7 +297,9 @@ def mixed_runs(n_serve, n_sustained, shape):
                      f"the stream takes them in turn"),
         "launch_shape": list(shape),
         "size_aware": "1024x1024 requests on an engine of their own (2 slots), 4 iterations of "
-                      "it alternating with 4 of the other engine (64 slots)"}
+                      "it alternating with 4 of the other engine (64 slots); a smaller request "
+                      "that finds nothing resident or waiting is solved on its own "
+                      "(scg_solve, the same result bit for bit)"}
     for tag, rate, seed, count in (("as_specified_200_per_s", 200.0, 5000, n_serve),
                                    ("sustainable_20_per_s", 20.0, 5001, n_sustained)):
         t_run = time.perf_counter()
@@ -307,7 +309,7 @@ def mixed_runs(n_serve, n_sustained, shape):
         log(f"served {tag}: {count} requests")
         bs = serve.serve_batched(reqs, arena_bytes=ARENA, max_slots=64, iters=4,
                                  keep_outputs=True, large_n=1024, large_iters=4,
-                                 large_slots=2)
+                                 large_slots=2, direct_when_idle=True)
         p = serve.serve_plain(reqs, keep_outputs=True)
         run = {"requests": count, "rate_per_s": rate,
                "batched_size_aware": bs.summary(reqs), "plain": p.summary(reqs),

@@ -108,6 +108,7 @@ class Served:
     outputs: dict             # rid -> output tensor
     latency_by_rid: dict = None   # rid -> completion - arrival
     engine_stats: list = None     # scg_batch_get_stats of each engine at the end
+    direct: int = 0               # requests solved on their own (serve_batched's idle path)
 
     @property
     def recons_per_s(self) -> float:
@@ -122,6 +123,8 @@ class Served:
                "latency_ms": {"p50": float(np.percentile(lat, 50)),
                               "p99": float(np.percentile(lat, 99)),
                               "mean": float(np.mean(lat))}}
+        if self.direct:
+            out["solved_directly"] = self.direct
         if requests is not None and self.latency_by_rid:
             by = {}
             for r in requests:
@@ -171,7 +174,7 @@ def serve_plain(requests: list, keep_outputs: bool = False) -> Served:
 def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: int = 4,
                   graph: bool = False, keep_outputs: bool = False,
                   large_n: Optional[int] = None, large_iters: int = 1,
-                  large_slots: int = 1) -> Served:
+                  large_slots: int = 1, direct_when_idle: bool = False) -> Served:
     """Continuous batching on the batch engine: admit every arrived request
     that fits (FIFO; a request that does not fit blocks the ones behind it),
     run `iters` iterations of all resident solves, retire the finished ones,
@@ -187,11 +190,19 @@ def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: 
     small solve then advances at its own iteration cost instead of a large
     solve's (one launch per phase covers every resident solve, so in a
     shared batch each small iteration lasts as long as the large one's),
-    while the large solves keep most of the device."""
+    while the large solves keep most of the device.
+
+    direct_when_idle: a request of the first engine that arrives while
+    nothing is resident or waiting is solved on its own with scg_solve (the
+    single-solve path, the same result bit for bit); the requests that
+    arrive meanwhile wait for it, then are batched as usual. At low load
+    most requests find the device idle and skip the engine's per-step host
+    work."""
     order = sorted(requests, key=lambda r: r.arrival)
     pool = _outputs(order)
     lat, reports, outputs, by_rid = [], {}, {}, {}
     nxt = 0
+    direct = 0
     n_eng = 2 if large_n is not None else 1
     slots = [max_slots] if n_eng == 1 else [max_slots, max(1, large_slots)]
     engines = [scg.Batch(arena_bytes // n_eng, max_slots=slots[e], graph=graph)
@@ -202,6 +213,21 @@ def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: 
 
     def engine_of(r):
         return 1 if (large_n is not None and r.n >= large_n) else 0
+
+    ws = {}
+    if direct_when_idle:
+        for r in order:
+            if engine_of(r) == 0:
+                need = r.plan.workspace_bytes(r.params)
+                if id(r.plan) not in ws or ws[id(r.plan)].numel() < need:
+                    ws[id(r.plan)] = r.plan.workspace(r.params)
+
+    def finish(r, rep, out):
+        lat.append(time.perf_counter() - t0 - r.arrival)
+        by_rid[r.rid] = lat[-1]
+        reports[r.rid] = rep
+        if keep_outputs:
+            outputs[r.rid] = out
 
     try:
         torch.cuda.synchronize()
@@ -215,6 +241,14 @@ def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: 
             while nxt < len(order) and order[nxt].arrival <= now:
                 waiting[engine_of(order[nxt])].append(order[nxt])
                 nxt += 1
+            if direct_when_idle and not any(inflight) and len(waiting[0]) == 1 \
+                    and not any(waiting[1:]):
+                r = waiting[0].pop()
+                out, rep, _ = r.plan.solve(r.y, r.params, out=pool[r.rid], ws=ws[id(r.plan)],
+                                           trace=False)
+                finish(r, rep, out)
+                direct += 1
+                continue
             for e, b in enumerate(engines):
                 while waiting[e]:
                     r = waiting[e][0]
@@ -234,14 +268,10 @@ def serve_batched(requests: list, arena_bytes: int, max_slots: int = 64, iters: 
                     if rep is None:
                         continue
                     r, out = inflight[e].pop(t)
-                    lat.append(time.perf_counter() - t0 - r.arrival)
-                    by_rid[r.rid] = lat[-1]
-                    reports[r.rid] = rep
-                    if keep_outputs:
-                        outputs[r.rid] = out
+                    finish(r, rep, out)
         wall = (time.perf_counter() - t0) - (order[0].arrival if order else 0.0)
         stats = [b.stats() for b in engines]
     finally:
         for b in engines:
             b.close()
-    return Served(np.asarray(lat), wall, reports, outputs, by_rid, stats)
+    return Served(np.asarray(lat), wall, reports, outputs, by_rid, stats, direct)

@@ -95,3 +95,25 @@ def test_size_aware_engines_and_ls_eps(stream):
     assert all(r.status == scg.SCG_OK for r in b.reports.values())
     _same(serve, p, b)
     cache.close()
+
+
+def test_direct_when_idle(stream):
+    """The idle path: requests that find nothing resident or waiting are
+    solved on their own, the others batched; every request gets its plain
+    result bit for bit. Arrivals: eight spaced 0.2 s apart (each finds the
+    device idle), then eight at one instant (batched behind the first)."""
+    from paper_1709_04912_amd import scg
+    serve, reqs = stream
+    arr = [0.2 * i for i in range(8)] + [1.8] * 8
+    reqs3 = [serve.Request(i, reqs[i].plan, reqs[i].y, reqs[i].params, arr[i])
+             for i in range(16)]
+    p = serve.serve_plain(reqs3, keep_outputs=True)
+    b = serve.serve_batched(reqs3, arena_bytes=1 << 30, max_slots=16, iters=2,
+                            keep_outputs=True, direct_when_idle=True)
+    assert len(b.reports) == len(reqs3)
+    assert all(r.status == scg.SCG_OK for r in b.reports.values())
+    # the spaced ones go direct (unless a solve outlasts the spacing); the
+    # burst arrives together and is batched
+    assert 4 <= b.direct <= 8
+    assert b.summary()["solved_directly"] == b.direct
+    _same(serve, p, b)
