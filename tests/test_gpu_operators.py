@@ -273,8 +273,8 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
 
 def test_size_limits(scg, torch_mod, oracle_lib):
     """The largest accepted image (N = 2880) with a detector of 4076 bins, on sampled rays
-    and pixels against the oracle, and its filter in both precisions; one
-    pixel more is rejected."""
+    and pixels against the oracle (A^T also mirrored, in both precisions), and
+    its filter in both precisions; one pixel more is rejected."""
     torch = torch_mod
     n, na, nb = 2880, 6, 4076
     print(f"[limits] N={n} angles={na} bins={nb}", flush=True)
@@ -290,10 +290,17 @@ def test_size_limits(scg, torch_mod, oracle_lib):
         aty = plan.backproject(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         filt = plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         filt64 = plan.filter(torch.tensor(y, dtype=torch.float64, device="cuda")).cpu().numpy()
+        # the mirrored backprojector at the largest image, both precisions
+        atm = []
+        for prec, dt in ((scg.SCG_F32, torch.float32), (scg.SCG_F64, torch.float64)):
+            plan.set_tuning(prec, 4, 8, 8, 0, 1)
+            atm.append(plan.backproject(torch.tensor(y, dtype=dt, device="cuda")).cpu().numpy())
     fref = g.filter(y)
     assert _rel(filt, fref) <= 1e-5 and _rel(filt64, fref) <= 1e-12
     assert _rel(ax[rays], g.project_rays(x, rays)) <= 1e-5
-    assert _rel(aty[pix], g.backproject_pixels(y, pix)) <= 1e-5
+    ref_t = g.backproject_pixels(y, pix)
+    assert _rel(aty[pix], ref_t) <= 1e-5
+    assert _rel(atm[0][pix], ref_t) <= 1e-5 and _rel(atm[1][pix], ref_t) <= 1e-12
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
     with pytest.raises(scg.ScgError):
         scg.Plan(n + 1, na, 64)

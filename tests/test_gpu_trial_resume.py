@@ -71,11 +71,13 @@ def test_suspension_model():
 
 
 @pytest.mark.parametrize("variant,kappa,max_iter", [
-    ("S_CG", 1.0, 60), ("S_CG_CD", 0.1, 60), ("S_PCG", 0.1, 60), ("S_CG_K", 0.1, 30)])
+    ("S_CG", 1.0, 60), ("S_CG_CD", 0.1, 60), ("S_PCG", 0.1, 60), ("S_CG_K", 0.1, 30),
+    ("S_CG/mirrored", 1.0, 60)])
 def test_resumed_searches_match_oracle(oracle_lib, variant, kappa, max_iter):
     import torch
     assert torch.cuda.is_available()
     from paper_1709_04912_amd import scg
+    variant, _, mirrored = variant.partition("/")
     w, g, prob, eps, x1n = _case(oracle_lib)
     pp = alg.PerturbParams(0.5 * x1n, a=0.999, max_trials=40, kappa=kappa)
     print(f"[trial resume] variant={variant} kappa={kappa} max_iter={max_iter}", flush=True)
@@ -85,6 +87,8 @@ def test_resumed_searches_match_oracle(oracle_lib, variant, kappa, max_iter):
     assert sus, "the case must suspend at least once"
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
+        if mirrored:   # the mirrored backprojector (its solves resume the same way)
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
         p = plan.params(eps=eps, gamma0=pp.gamma0, variant=variant, prec=scg.SCG_F64,
                         a=0.999, max_trials=40, max_iter=max_iter, kappa=kappa)
         x, rep, trace = plan.solve(y, p)
@@ -106,7 +110,7 @@ def test_resumed_searches_match_oracle(oracle_lib, variant, kappa, max_iter):
         assert torch.equal(x, out)
         assert (rb.status, rb.k, rb.steps, rb.f_out, rb.tv_out) == \
             (rep.status, rep.k, rep.steps, rep.f_out, rep.tv_out)
-        if variant == "S_CG":
+        if variant == "S_CG" and not mirrored:
             # every launch timed: identical bits, and the launches that
             # returned at once behind the suspension kept apart
             plan.profile(classes=scg.KERNEL_CLASSES, every=1)
