@@ -813,7 +813,8 @@ template <typename T> void launch_pad_sino(const T *y, T *rpad, const Geo &G, hi
 // by NS groups of 128 threads; thread t of a group owns the pixels (t >> 3,
 // 2(t & 7)) and (t >> 3, 2(t & 7) + 1), and group gs takes the angle chunks
 // gs, gs + NS, ... (the groups' sums are added in a fixed order at the end).
-// Angles are processed in chunks of kBpChunk: for each angle the kBpWin bins
+// Angles are processed in chunks of kBpChunk (half that in the mirrored form
+// below): for each angle the kBpWin bins
 // around the tile centre's projection are staged in LDS, already scaled by
 // 1/m, next to the angle's parameters (cos and the weight constants) and,
 // for each of the tile's 16 rows, the row's part of the footprint position
@@ -1145,9 +1146,11 @@ __attribute__((amdgpu_waves_per_eu(kBpWaves<T, false, MIR, NS>))) void k_backpro
     T *__restrict__ out, int swz)
 {
     const int nt = (G.n + kBpTile - 1) / kBpTile;
-    // the heaviest-first tile order covers the full grid only
-    const int tile =
-        (MIR || swz || border == nullptr) ? launch_index(swz) : border[blockIdx.x];
+    // the heaviest-first tile order covers the full grid only; the mirrored
+    // form always takes the XCD-contiguous order (an XCD's tiles are a band
+    // of rows, whose footprint of every projection its L2 then holds)
+    const int tile = (MIR || swz || border == nullptr) ? launch_index(MIR ? 1 : swz)
+                                                       : border[blockIdx.x];
     backproject_body<T, false, NS, MIR>(r, nullptr, G, ang, out, nullptr, nullptr, nullptr, 0,
                                         nullptr, vblk_of(tile, MIR ? bp_mirror_cols(G.n) : nt, nt));
 }
@@ -1188,7 +1191,7 @@ __global__ __launch_bounds__(kBpThreads * NS)
 __attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL, MIR, NS>))) void kb_backproject(
     const Solve<T> *S, const BlkMap *map, int phase, int dot, int swz)
 {
-    const BlkMap m = locate(map, swz);
+    const BlkMap m = locate(map, MIR ? 1 : swz);   // mirrored: XCD-contiguous always
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     // descriptor fields into registers: the body's stores cannot alias them
