@@ -1191,7 +1191,10 @@ __global__ __launch_bounds__(kBpThreads * NS)
 __attribute__((amdgpu_waves_per_eu(kBpWaves<T, DUAL, MIR, NS>))) void kb_backproject(
     const Solve<T> *S, const BlkMap *map, int phase, int dot, int swz)
 {
-    const BlkMap m = locate(map, MIR ? 1 : swz);   // mirrored: XCD-contiguous always
+    // a single solve's mirrored launch takes the XCD-contiguous order always;
+    // a batch's keeps the chosen one (contiguous ranges of a mixed batch give
+    // XCDs unequal shares of its heavier solves)
+    const BlkMap m = locate(map, MIR && map == nullptr ? 1 : swz);
     const Solve<T> d = load_solve(S, m.solve);
     if (stopped(d.st)) return;
     // descriptor fields into registers: the body's stores cannot alias them
