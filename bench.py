@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--counter-workload", metavar="SHAPES",
                     help="run only the hardware-counter workload with these launch shapes "
                          "(project_groups,backproject_split,project_angles,swizzle"
-                         "[,backproject_mirror])")
+                         "[,backproject_mirror[,project_mirror]])")
     ap.add_argument("--batched-counter-workload", metavar="SHAPES",
                     help="run only the batched (64-solve) hardware-counter workload")
     args = ap.parse_args()
@@ -591,7 +591,8 @@ def main():
     log(f"s_pcg: {result['s_pcg']}")
     if not args.no_mix:
         shape = (tuning["project_groups"], tuning["backproject_split"],
-                 tuning["project_angles"], tuning["swizzle"], tuning["backproject_mirror"])
+                 tuning["project_angles"], tuning["swizzle"], tuning["backproject_mirror"],
+                 tuning["project_mirror"])
         result["batched"], result["served"] = mixed_runs(args.serve_requests,
                                                          args.sustained_requests, shape)
     if not args.no_cpu_baseline:

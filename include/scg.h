@@ -234,7 +234,9 @@ size_t scg_static_workspace_bytes(void);
  * mirrored backprojector takes angle theta's parameters for pi - theta (a
  * trig table made exactly symmetric about the vertical axis), which moves
  * A^T by about 1e-13 relative in FP64; the filtered variants' two-sinogram
- * backprojection never runs mirrored. */
+ * backprojection never runs mirrored. The mirrored projector does the same
+ * for A (each ray (a, b) with a <= n_a / 2 also forms ray (n_a - a, b) from
+ * the image mirrored about the vertical axis). */
 typedef struct {
     int32_t project_groups;     /* 2 or 4: angle groups of 128 rays per projector block
                                    (256 or 512 threads)                               */
@@ -246,6 +248,9 @@ typedef struct {
     int32_t backproject_mirror; /* 1: each backprojector thread also forms the pixels
                                    mirrored about the vertical axis from the same
                                    footprint (half the tiles), 0: every tile      */
+    int32_t project_mirror;     /* 1: each projector thread also forms the ray of the
+                                   mirror angle n_a - a from the same crossings and
+                                   weights (half the blocks), 0: every angle      */
 } scg_tuning;
 
 /* Current shapes for precision prec. */

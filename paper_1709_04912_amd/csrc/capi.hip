@@ -78,17 +78,23 @@ void build_angles(const Geo &G, const std::vector<double> &cv, const std::vector
 // (group, bin chunk, band), the first LDS-staged column: the band's columns
 // crossed by any of the block's rays, with two columns of margin each side.
 // Starting from `start` angles, the group size shrinks until every window
-// fits kPjWin columns. Tables for group sizes of 8 and 4 (index 0 and 1).
-int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, int ti)
+// fits kPjWin columns. Tables for group sizes of 8 and 4 (index 0 and 1),
+// and their mirrored forms (index 2 and 3), whose groups cover only the
+// angles a <= n_a / 2: the rays of angle n_a - a are those of angle a in the
+// image mirrored about the vertical axis, so they cross the same window
+// columns of the mirrored band.
+int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, int ti,
+                      bool mirror)
 {
     const Geo &G = p->G;
     const int n_chunks = (G.nb + scg::kPjBins - 1) / scg::kPjBins;
     const int n_bands = (G.n + scg::kPjBand - 1) / scg::kPjBand;
+    const int a_end = mirror ? G.na / 2 + 1 : G.na;
     for (int gmax = start; gmax >= 1; --gmax) {
         std::vector<PjGroup> groups;
-        for (int a = 0; a < G.na;) {
+        for (int a = 0; a < a_end;) {
             PjGroup g{a, 1, pa[a].major, 0};
-            while (g.count < gmax && a + g.count < G.na && pa[a + g.count].major == g.major)
+            while (g.count < gmax && a + g.count < a_end && pa[a + g.count].major == g.major)
                 ++g.count;
             groups.push_back(g);
             a += g.count;
@@ -183,6 +189,7 @@ int build_proj_tables(scg_plan *p, const std::vector<ProjAngle> &pa, int start, 
         t.n_chunks = n_chunks;
         t.n_bands = n_bands;
         t.group_max = start;
+        t.mirror = mirror ? 1 : 0;
         return SCG_OK;
     }
     return SCG_EINVAL;
@@ -395,7 +402,8 @@ bool tuning_valid(const scg_tuning &t)
            (t.backproject_split == 1 || t.backproject_split == 2 ||
             t.backproject_split == 4 || (t.backproject_split == 8 && t.backproject_mirror == 1)) &&
            (t.project_angles == 8 || t.project_angles == 4) && (t.swizzle == 0 || t.swizzle == 1) &&
-           (t.backproject_mirror == 0 || t.backproject_mirror == 1);
+           (t.backproject_mirror == 0 || t.backproject_mirror == 1) &&
+           (t.project_mirror == 0 || t.project_mirror == 1);
 }
 
 // Mean time of `reps` launches of `fn` on stream s, after one untimed launch.
@@ -439,20 +447,21 @@ int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
     constexpr int kReps = 10;
     constexpr int kRounds = 2;
     scg_tuning best = plan->tune[pi];
-    struct PjCand { int ga, nq, swz; float ms; };
+    struct PjCand { int ga, nq, mir, swz; float ms; };
     struct BpCand { int sp, mir, swz; float ms; };
     std::vector<PjCand> pj;
     std::vector<BpCand> bp;
     for (int ga : {8, 4})
         for (int nq : {2, 4})
-            for (int swz : {0, 1}) pj.push_back({ga, nq, swz, -1.0f});
+            for (int mir : {0, 1})
+                for (int swz : {0, 1}) pj.push_back({ga, nq, mir, swz, -1.0f});
     for (int sp : {1, 2, 4, 8})
         for (int mir : {0, 1})
             for (int swz : {0, 1})
                 if (sp < 8 || mir) bp.push_back({sp, mir, swz, -1.0f});
     auto run_pj = [&](const PjCand &c) {
-        scg::launch_project<T>(x, xs, G, plan->ptab[c.ga == 8 ? 0 : 1], y, G.rs, scg::kSinoPadL,
-                               c.nq, c.swz, s);
+        scg::launch_project<T>(x, xs, G, plan->ptab[(c.ga == 8 ? 0 : 1) + (c.mir ? 2 : 0)], y,
+                               G.rs, scg::kSinoPadL, c.nq, c.swz, s);
     };
     auto run_bp = [&](const BpCand &c) {
         scg::launch_backproject<T>(y, G, plan->bang, plan->border, x, c.sp, c.mir, c.swz, s);
@@ -481,6 +490,7 @@ int autotune_impl(scg_plan *plan, hipStream_t s, scg_tuning *chosen)
             best_sum = sum;
             best.project_angles = bpj->ga;
             best.project_groups = bpj->nq;
+            best.project_mirror = bpj->mir;
             best.backproject_split = bbp->sp;
             best.backproject_mirror = bbp->mir;
             best.swizzle = swz;
@@ -605,8 +615,10 @@ int scg_plan_create(const scg_geom *g, int device, scg_plan **out)
         scg_plan_destroy(p);
         return SCG_EDEVICE;
     }
-    int rc = build_proj_tables(p, pa, 8, 0);
-    if (rc == SCG_OK) rc = build_proj_tables(p, pa, 4, 1);
+    int rc = build_proj_tables(p, pa, 8, 0, false);
+    if (rc == SCG_OK) rc = build_proj_tables(p, pa, 4, 1, false);
+    if (rc == SCG_OK) rc = build_proj_tables(p, pa, 8, 2, true);
+    if (rc == SCG_OK) rc = build_proj_tables(p, pa, 4, 3, true);
     // filter tables (spectrum for the default mu and twiddles) for each
     // precision whose transform fits the LDS bound; a solve later changes
     // only the spectrum, without allocating
@@ -640,7 +652,7 @@ void scg_plan_destroy(scg_plan *p)
     (void)hipFree(p->pang);
     (void)hipFree(p->bang);
     (void)hipFree(p->border);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4; ++i) {
         (void)hipFree(p->pgroups[i]);
         (void)hipFree(p->pwin[i]);
         (void)hipFree(p->porder[i]);

@@ -144,7 +144,7 @@ template <typename T> struct Enq {
     {
         Prof t(g.prof, SCG_KC_PROJECT, s);
         launch_b_project<T>(g.S, m(kKPj), n(kKPj), phase, g.tune.project_groups,
-                            g.tune.project_angles, g.tune.swizzle, s);
+                            g.tune.project_angles, g.tune.project_mirror, g.tune.swizzle, s);
     }
     void backproject(int phase, int dot) const
     {
@@ -972,8 +972,9 @@ int rebuild(scg_batch *b)
         const int pi = s.params.prec == SCG_F64 ? 1 : 0;
         const scg_tuning t = s.tune;
         keys[std::make_tuple(pi, (int)s.params.variant * 100 + s.params.restart_k,
-                             t.project_groups * 1000 + t.backproject_split * 100 +
-                                 t.backproject_mirror * 10 + t.swizzle,
+                             t.project_mirror * 10000 + t.project_groups * 1000 +
+                                 t.backproject_split * 100 + t.backproject_mirror * 10 +
+                                 t.swizzle,
                              t.project_angles)]
             .push_back(i);
     }

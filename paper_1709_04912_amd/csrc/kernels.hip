@@ -538,7 +538,28 @@ void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase
 // LDS reads and three FMAs/adds. With y given, out = A x - y. With partials
 // given, the block stores its sum of out^2, or of out * dotv with dotv given
 // (same layout as out).
+//
+// Mirrored form (MIR, tables over the angles a <= n_a / 2): mirroring the
+// image about its vertical axis maps ray (a, b) onto ray (n_a - a, b), so a
+// ray's crossings, split weights and LDS addresses also serve that second
+// ray, read from a second window of the band that holds the mirrored image
+// (columns reversed for angles stepping over rows; for angles stepping over
+// columns, the rows of x^T reversed). Each LDS column then holds the band's
+// kPjBand rows followed by the same rows of the mirrored window, so both
+// paired reads of a step come from one address with immediate offsets.
+// Angle 0 and angle n_a / 2 are their own mirrors: their slots form one ray.
+// A pair of rays is half the threads of the plain form, so the block has two
+// halves that trace the same rays over the first and the second half of each
+// band's rows, and the second half's sums join the first's at the end.
 // ---------------------------------------------------------------------------
+
+// Waves per SIMD a projector instance is compiled for: the FP32 mirrored
+// form's 1024-thread blocks need two per CU (8 waves per SIMD, at most 64
+// VGPRs) to match the plain form's occupancy; the others keep the default.
+template <typename T, int NQ, bool MIR> constexpr int pj_min_waves()
+{
+    return (MIR && NQ == 4 && sizeof(T) == 4) ? 8 : 1;
+}
 
 // Block id of the projector's local block index: heaviest first in launch
 // order (the XCD-contiguous order keeps neighbouring blocks together instead).
@@ -547,19 +568,32 @@ __device__ __forceinline__ int pj_block(const ProjTables &P, int local, int swz)
     return (swz || P.order == nullptr) ? local : gl(P.order)[local];
 }
 
-template <typename T, int NQ, int GA>
+template <typename T, int NQ, int GA, bool MIR>
 __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, const Geo &G,
                              const ProjTables &P, const T *__restrict__ y, int y_stride,
                              T *__restrict__ out, int out_stride, int out_off,
                              const T *__restrict__ dotv, double *partials, VBlk vb)
 {
-    constexpr int NT = kPjBins * NQ;
-    constexpr int LS = kPjBand + 1;               // LDS column stride (elements)
+    constexpr int NH = MIR ? 2 : 1;               // halves of a band's rows
+    constexpr int NTQ = kPjBins * NQ;             // threads of one half
+    constexpr int NT = NTQ * NH;
+    constexpr int KH = kPjBand / NH;              // rows of a band per half
+    // steps whose LDS reads are in flight together (two in the mirrored
+    // form, which holds four reads per step within its 64 VGPRs)
+    constexpr int GS = MIR ? 2 : kPjGroupSteps;
+    // LDS column stride (elements): the band's rows, then (MIR) the mirrored
+    // window's from one element past them; odd, so a half-wavefront's reads
+    // at one step stay in distinct banks, and a step's four reads pair into
+    // two-address reads (k, MO + k) and (LS + k, LS + MO + k) whose two
+    // addresses lie in different banks
+    constexpr int LS = (MIR ? 2 : 1) * kPjBand + 1;
+    constexpr int MO = kPjBand + 1;               // offset of the mirrored rows
+    constexpr int LSZ = kPjWin * LS;
     constexpr int SLOTS = GA / NQ;
     constexpr int RPT = kPjWin * kPjBand / NT;    // staged rows per thread
     static_assert(GA % NQ == 0 && GA <= kPjGroup && NT % kPjWin == 0 && kPjBand % RPT == 0,
                   "projector tiling");
-    __shared__ T lds[kPjWin * LS];
+    __shared__ T lds[LSZ];
     const int t = threadIdx.x;
     const int chunk = vb.x, gi = vb.y;
     const PjGroup grp = gl(P.groups)[gi];
@@ -569,8 +603,10 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     // most about 24 columns of a row (16 bins at up to sqrt(2) columns
     // apart), so their paired LDS reads fall in distinct banks; 64 bins of
     // one angle would span up to 90 columns and collide.
-    const int quarter = 2 * (t / (2 * kPjBins)) + (t & 1);
-    const int b_raw = chunk * kPjBins + ((t & (2 * kPjBins - 1)) >> 1);
+    const int th = MIR ? t % NTQ : t;             // thread within its half
+    const int half = MIR ? t / NTQ : 0;
+    const int quarter = 2 * (th / (2 * kPjBins)) + (th & 1);
+    const int b_raw = chunk * kPjBins + ((th & (2 * kPjBins - 1)) >> 1);
     const bool bin_ok = b_raw < G.nb;
     const int b = bin_ok ? b_raw : G.nb - 1;   // idle lanes trace the chunk's last ray
     const int n = G.n;
@@ -580,12 +616,14 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     const int scol = t % kPjWin, srow = (t / kPjWin) * RPT;
 
     double u0[SLOTS];
-    T acc[SLOTS], accr[SLOTS];
+    T acc[SLOTS], accr[SLOTS], macc[SLOTS], maccr[SLOTS];
 #pragma unroll
     for (int m = 0; m < SLOTS; ++m) {
         const int slot = quarter + NQ * m;
         acc[m] = T(0);
         accr[m] = T(0);
+        macc[m] = T(0);
+        maccr[m] = T(0);
         u0[m] = 0.0;
         if (slot < grp.count) {
             const auto &A = pang[grp.a0 + slot];
@@ -605,14 +643,15 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     }
 
     // staging loads: one per row, columns outside the image read as zero
-    T pre[RPT];
+    T pre[RPT], mpre[MIR ? RPT : 1];
     auto prefetch = [&](int band) {
         const int jw = win[band];
         const int i0 = band * kPjBand + srow;
         const int col = jw + scol;
         const bool cok = col >= 0 && col < n;
         const uint32_t vo = cok ? (uint32_t)(i0 * n + col) * (uint32_t)sizeof(T) : kBufOob;
-        if ((band + 1) * kPjBand <= n) {
+        const bool full = (band + 1) * kPjBand <= n;
+        if (full) {
             // every row of the band exists: the row step is a scalar offset
 #pragma unroll
             for (int r = 0; r < RPT; ++r) pre[r] = buf_load<T>(img, vo, (uint32_t)r * rowb);
@@ -620,6 +659,43 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
             // last band of a ragged image: rows past the end read as zero
 #pragma unroll
             for (int r = 0; r < RPT; ++r) pre[r] = buf_load<T>(img, vo + (uint32_t)r * rowb, 0u);
+        }
+        if constexpr (MIR) {
+            if (!grp.major) {
+                // rows of x: the mirrored window is column n - 1 - col of
+                // the same rows (inside the image exactly when col is)
+                const uint32_t mvo =
+                    cok ? (uint32_t)(i0 * n + (n - 1 - col)) * (uint32_t)sizeof(T) : kBufOob;
+                if (full) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        mpre[r] = buf_load<T>(img, mvo, (uint32_t)r * rowb);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        mpre[r] = buf_load<T>(img, mvo + (uint32_t)r * rowb, 0u);
+                }
+            } else {
+                // rows of x^T: band row i0 + r mirrors to row n - 1 - i0 - r;
+                // load them upwards from the lowest, mpre[r] holding band row
+                // srow + RPT - 1 - r. Rows above the image (a ragged last
+                // band) have a negative index: as an unsigned offset it lies
+                // past the view and reads zero.
+                const int lo = n - i0 - RPT;
+                if (full) {
+                    const uint32_t mvo =
+                        cok ? (uint32_t)(lo * n + col) * (uint32_t)sizeof(T) : kBufOob;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        mpre[r] = buf_load<T>(img, mvo, (uint32_t)r * rowb);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        mpre[r] = buf_load<T>(
+                            img, cok ? (uint32_t)((lo + r) * n + col) * (uint32_t)sizeof(T) : kBufOob,
+                            0u);
+                }
+            }
         }
     };
 
@@ -630,6 +706,15 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < RPT; ++r) lds[scol * LS + srow + r] = pre[r];
+        if constexpr (MIR) {
+            if (!grp.major) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) lds[scol * LS + MO + srow + r] = mpre[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) lds[scol * LS + MO + srow + RPT - 1 - r] = mpre[r];
+            }
+        }
         __syncthreads();
         const int jw = win[band];
         const int i0 = band * kPjBand;
@@ -653,24 +738,27 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                 // band: every step's offset from it is at least 1, so the
                 // column is the truncation of the offset
                 const double fu = floor(fmin(us, ue)) - 1.0;
-                // byte offset in LDS of the anchor column; a step's column
-                // adds a 24-bit multiple of the column stride
-                const int cb = ((int)fu - jw) * (LS * (int)sizeof(T));
-                const T F0 = (T)(us - fu);
+                // byte offset in LDS of the anchor column at the half's
+                // first row; a step's column adds a 24-bit multiple of the
+                // column stride
+                const int kb = half * KH;
+                const int cb = ((int)fu - jw) * (LS * (int)sizeof(T)) + kb * (int)sizeof(T);
                 const T slope = (T)slope64;
+                const T F0 = MIR ? fma((T)kb, slope, (T)(us - fu)) : (T)(us - fu);
                 const T K = s_K[slot];
                 const T C = s_C[slot];
                 // the band's terms are summed apart and then added to the
                 // ray's sum: rounding grows with the band plus the band count,
                 // not with N
-                T a_ = T(0), ar = T(0);
+                T a_ = T(0), ar = T(0), ma = T(0), mar = T(0);
                 // steps in groups of kPjGroupSteps: the group's LDS reads are
                 // issued before its terms are summed (in step order)
 #pragma unroll
-                for (int k0 = 0; k0 < kPjBand; k0 += kPjGroupSteps) {
-                    T xl[kPjGroupSteps], xr[kPjGroupSteps], wl[kPjGroupSteps];
+                for (int k0 = 0; k0 < KH; k0 += GS) {
+                    T xl[GS], xr[GS], wl[GS];
+                    T ml[MIR ? GS : 1], mr[MIR ? GS : 1];
 #pragma unroll
-                    for (int j = 0; j < kPjGroupSteps; ++j) {
+                    for (int j = 0; j < GS; ++j) {
                         const int k = k0 + j;
                         const T v = fma((T)k, slope, F0);
                         const int jl = (int)v;
@@ -680,25 +768,62 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
                             __mul24(jl, LS * (int)sizeof(T)) + cb);
                         xl[j] = col[k];
                         xr[j] = col[LS + k];
+                        if constexpr (MIR) {
+                            ml[j] = col[MO + k];
+                            mr[j] = col[LS + MO + k];
+                        }
                     }
 #pragma unroll
-                    for (int j = 0; j < kPjGroupSteps; ++j) {
+                    for (int j = 0; j < GS; ++j) {
                         a_ = fma(wl[j], xl[j] - xr[j], a_);
                         ar += xr[j];
+                        if constexpr (MIR) {
+                            ma = fma(wl[j], ml[j] - mr[j], ma);
+                            mar += mr[j];
+                        }
                     }
                 }
                 acc[m] += a_;
                 accr[m] += ar;
+                if constexpr (MIR) {
+                    macc[m] += ma;
+                    maccr[m] += mar;
+                }
             }
         }
         band = nxt;
     }
 
+    if constexpr (MIR) {
+        // the second half's sums join the first half's (LDS reused once
+        // every band's reads are done)
+        static_assert(4 * SLOTS * NTQ <= LSZ, "projector half sums");
+        __syncthreads();
+        if (half == 1) {
+#pragma unroll
+            for (int m = 0; m < SLOTS; ++m) {
+                lds[(4 * m + 0) * NTQ + th] = acc[m];
+                lds[(4 * m + 1) * NTQ + th] = accr[m];
+                lds[(4 * m + 2) * NTQ + th] = macc[m];
+                lds[(4 * m + 3) * NTQ + th] = maccr[m];
+            }
+        }
+        __syncthreads();
+        if (half == 0) {
+#pragma unroll
+            for (int m = 0; m < SLOTS; ++m) {
+                acc[m] += lds[(4 * m + 0) * NTQ + th];
+                accr[m] += lds[(4 * m + 1) * NTQ + th];
+                macc[m] += lds[(4 * m + 2) * NTQ + th];
+                maccr[m] += lds[(4 * m + 3) * NTQ + th];
+            }
+        }
+    }
     double sq = 0.0;
 #pragma unroll
     for (int m = 0; m < SLOTS; ++m) {
         const int slot = quarter + NQ * m;
-        if (slot < grp.count && bin_ok) {
+        if (slot < grp.count && bin_ok && half == 0) {
             const int a = grp.a0 + slot;
             const T im = sizeof(T) == 4 ? (T)pang[a].inv_mf : (T)pang[a].inv_m;
             T val = (acc[m] + accr[m]) * im;
@@ -707,6 +832,18 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
             gl(out)[o] = val;
             const T w = dotv != nullptr ? gl(dotv)[o] : val;
             sq += (double)val * (double)w;
+            if constexpr (MIR) {
+                // the mirrored ray n_a - a (angles 0 and n_a / 2 have none)
+                const int am = G.na - a;
+                if (a > 0 && am != a) {
+                    T mv = (macc[m] + maccr[m]) * im;
+                    if (y != nullptr) mv -= gl(y)[(size_t)am * y_stride + b];
+                    const size_t mo = (size_t)am * out_stride + out_off + b;
+                    gl(out)[mo] = mv;
+                    const T mw = dotv != nullptr ? gl(dotv)[mo] : mv;
+                    sq += (double)mv * (double)mw;
+                }
+            }
         }
     }
     if (partials == nullptr) return;
@@ -714,14 +851,16 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
     block_store(v, partials + vb.id());
 }
 
-template <typename T, int NQ, int GA>
-__global__ __launch_bounds__(kPjBins * NQ) void k_project(const T *__restrict__ x,
+template <typename T, int NQ, int GA, bool MIR>
+__global__ __launch_bounds__(kPjBins * NQ * (MIR ? 2 : 1), (pj_min_waves<T, NQ, MIR>())) void k_project(const T *__restrict__ x,
                                                           const T *__restrict__ xt, Geo G,
                                                           ProjTables P, T *__restrict__ out,
                                                           int out_stride, int out_off, int swz)
 {
-    project_body<T, NQ, GA>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr, nullptr,
-                            vblk_of(pj_block(P, launch_index(swz), swz), P.n_chunks, P.n_groups));
+    project_body<T, NQ, GA, MIR>(x, xt, G, P, nullptr, 0, out, out_stride, out_off, nullptr,
+                                 nullptr,
+                                 vblk_of(pj_block(P, launch_index(swz), swz), P.n_chunks,
+                                         P.n_groups));
 }
 
 template <typename T>
@@ -729,25 +868,28 @@ void launch_project(const T *x, const T *xt, const Geo &G, const ProjTables &P, 
                     int out_stride, int out_off, int nq, int swz, hipStream_t s)
 {
     dim3 grid(P.n_chunks * P.n_groups);
-    if (P.group_max <= 4) {
+    auto go = [&](auto kern, int nthreads) {
+        hipLaunchKernelGGL(kern, grid, dim3(nthreads), 0, s, x, xt, G, P, out, out_stride,
+                           out_off, swz);
+    };
+    const bool g8 = P.group_max > 4;
+    if (P.mirror) {
         if (nq == 4)
-            hipLaunchKernelGGL((k_project<T, 4, 4>), grid, dim3(kPjBins * 4), 0, s, x, xt, G, P,
-                               out, out_stride, out_off, swz);
+            g8 ? go(k_project<T, 4, 8, true>, kPjBins * 8) : go(k_project<T, 4, 4, true>, kPjBins * 8);
         else
-            hipLaunchKernelGGL((k_project<T, 2, 4>), grid, dim3(kPjBins * 2), 0, s, x, xt, G, P,
-                               out, out_stride, out_off, swz);
+            g8 ? go(k_project<T, 2, 8, true>, kPjBins * 4) : go(k_project<T, 2, 4, true>, kPjBins * 4);
     } else {
         if (nq == 4)
-            hipLaunchKernelGGL((k_project<T, 4, 8>), grid, dim3(kPjBins * 4), 0, s, x, xt, G, P,
-                               out, out_stride, out_off, swz);
+            g8 ? go(k_project<T, 4, 8, false>, kPjBins * 4)
+               : go(k_project<T, 4, 4, false>, kPjBins * 4);
         else
-            hipLaunchKernelGGL((k_project<T, 2, 8>), grid, dim3(kPjBins * 2), 0, s, x, xt, G, P,
-                               out, out_stride, out_off, swz);
+            g8 ? go(k_project<T, 2, 8, false>, kPjBins * 2)
+               : go(k_project<T, 2, 4, false>, kPjBins * 2);
     }
 }
 
-template <typename T, int NQ, int GA>
-__global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, const BlkMap *map,
+template <typename T, int NQ, int GA, bool MIR>
+__global__ __launch_bounds__(kPjBins * NQ * (MIR ? 2 : 1), (pj_min_waves<T, NQ, MIR>())) void kb_project(const Solve<T> *S, const BlkMap *map,
                                                            int phase, int swz)
 {
     const BlkMap m = locate(map, swz);
@@ -766,27 +908,29 @@ __global__ __launch_bounds__(kPjBins * NQ) void kb_project(const Solve<T> *S, co
     T *out = q ? d.q : (u ? d.rt : d.r);
     const T *dv = u ? d.q : nullptr;
     double *part = phase == kPjResXhF ? d.partials2 : d.partials;
-    project_body<T, NQ, GA>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, dv, part, vb);
+    project_body<T, NQ, GA, MIR>(img, imgt, G, P, y, G.nb, out, G.rs, kSinoPadL, dv, part, vb);
 }
 
 template <typename T>
 void launch_b_project(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int nq,
-                      int ga, int swz, hipStream_t s)
+                      int ga, int mir, int swz, hipStream_t s)
 {
-    if (ga <= 4) {
+    auto go = [&](auto kern, int nthreads) {
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, s, S, map, phase, swz);
+    };
+    const bool g8 = ga > 4;
+    if (mir) {
         if (nq == 4)
-            hipLaunchKernelGGL((kb_project<T, 4, 4>), dim3(nblocks), dim3(kPjBins * 4), 0, s, S,
-                               map, phase, swz);
+            g8 ? go(kb_project<T, 4, 8, true>, kPjBins * 8) : go(kb_project<T, 4, 4, true>, kPjBins * 8);
         else
-            hipLaunchKernelGGL((kb_project<T, 2, 4>), dim3(nblocks), dim3(kPjBins * 2), 0, s, S,
-                               map, phase, swz);
+            g8 ? go(kb_project<T, 2, 8, true>, kPjBins * 4) : go(kb_project<T, 2, 4, true>, kPjBins * 4);
     } else {
         if (nq == 4)
-            hipLaunchKernelGGL((kb_project<T, 4, 8>), dim3(nblocks), dim3(kPjBins * 4), 0, s, S,
-                               map, phase, swz);
+            g8 ? go(kb_project<T, 4, 8, false>, kPjBins * 4)
+               : go(kb_project<T, 4, 4, false>, kPjBins * 4);
         else
-            hipLaunchKernelGGL((kb_project<T, 2, 8>), dim3(nblocks), dim3(kPjBins * 2), 0, s, S,
-                               map, phase, swz);
+            g8 ? go(kb_project<T, 2, 8, false>, kPjBins * 2)
+               : go(kb_project<T, 2, 4, false>, kPjBins * 2);
     }
 }
 
@@ -2698,7 +2842,7 @@ void launch_gather(const Solve<T> *S, int ns, DevState *out, double *tv, hipStre
                                hipStream_t);                                                    \
     template void launch_filter<T>(const T *, T *, const T *, const Geo &, int, hipStream_t);  \
     template void launch_b_stage<T>(const Solve<T> *, const BlkMap *, int, int, hipStream_t);  \
-    template void launch_b_project<T>(const Solve<T> *, const BlkMap *, int, int, int, int,    \
+    template void launch_b_project<T>(const Solve<T> *, const BlkMap *, int, int, int, int, int,    \
                                       int, hipStream_t);                                        \
     template void launch_b_backproject<T>(const Solve<T> *, const BlkMap *, int, int, int,     \
                                           int, int, int, hipStream_t);                          \

@@ -20,11 +20,12 @@ struct scg_plan {
     std::vector<double> cosv, sinv;
     ProjAngle *pang = nullptr;
     BpAngle *bang = nullptr;
-    PjGroup *pgroups[2] = {nullptr, nullptr};
-    int *pwin[2] = {nullptr, nullptr};
-    int *porder[2] = {nullptr, nullptr};
+    // projector tables: 8 and 4 angles per group, then the same two mirrored
+    PjGroup *pgroups[4] = {nullptr, nullptr, nullptr, nullptr};
+    int *pwin[4] = {nullptr, nullptr, nullptr, nullptr};
+    int *porder[4] = {nullptr, nullptr, nullptr, nullptr};
     int *border = nullptr;                // backprojector tile of each launch position
-    ProjTables ptab[2] = {};              // projector tables, 8 and 4 angles per group
+    ProjTables ptab[4] = {};
     void *xs[2] = {nullptr, nullptr};     // transposed-image scratch per precision
     void *rpad[2] = {nullptr, nullptr};   // padded sinogram scratch per precision
     double *partials = nullptr;           // standalone TV partials
@@ -36,7 +37,7 @@ struct scg_plan {
     // positions, then the twiddles of each butterfly span (null where the
     // transform exceeds the LDS bound)
     void *ftab[2] = {nullptr, nullptr};
-    scg_tuning tune[2] = {{4, 4, 8, 0, 0}, {4, 2, 8, 0, 0}};  // launch shapes (F32, F64)
+    scg_tuning tune[2] = {{4, 4, 8, 0, 0, 0}, {4, 2, 8, 0, 0, 0}};  // launch shapes (F32, F64)
     double filt_mu[2] = {-1.0, -1.0};      // mu of each precision's spectrum
     // kernel timing (scg_profile): HIP events around launches of chosen classes
     struct ProfRec {
@@ -97,7 +98,7 @@ int check_params(const scg_params *pr);
 // Projector tables of a launch shape.
 inline const ProjTables &proj_tables(const scg_plan *p, const scg_tuning &t)
 {
-    return p->ptab[t.project_angles == 4 ? 1 : 0];
+    return p->ptab[(t.project_angles == 4 ? 1 : 0) + (t.project_mirror ? 2 : 0)];
 }
 
 }  // namespace scg

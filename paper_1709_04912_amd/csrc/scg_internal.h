@@ -96,6 +96,8 @@ struct ProjTables {
     const int *order;    // dispatch order: block ids (group * n_chunks + chunk) by
                          // decreasing count of bands to walk (heaviest first)
     int n_groups, n_chunks, n_bands, group_max;
+    int mirror;          // 1: groups cover the angles a <= n_a / 2 and each ray
+                         // also forms ray (n_a - a, b) (the mirrored form)
 };
 
 // Pixel-driven frame of one angle: pixel centre projects to the bin coordinate
@@ -261,7 +263,7 @@ template <typename T>
 void launch_b_stage(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, hipStream_t s);
 template <typename T>
 void launch_b_project(const Solve<T> *S, const BlkMap *map, int nblocks, int phase, int nq,
-                      int ga, int swz, hipStream_t s);
+                      int ga, int mir, int swz, hipStream_t s);
 template <typename T>
 void launch_b_backproject(const Solve<T> *S, const BlkMap *map, int nblocks, int phase,
                           int dot, int split, int mirror, int swz, hipStream_t s);

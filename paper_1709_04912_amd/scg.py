@@ -56,7 +56,7 @@ class scg_kernel_time(C.Structure):
 class scg_tuning(C.Structure):
     _fields_ = [("project_groups", C.c_int32), ("backproject_split", C.c_int32),
                 ("project_angles", C.c_int32), ("swizzle", C.c_int32),
-                ("backproject_mirror", C.c_int32)]
+                ("backproject_mirror", C.c_int32), ("project_mirror", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -235,9 +235,9 @@ class Plan:
 
     def set_tuning(self, prec: int = SCG_F32, project_groups: int = 4,
                    backproject_split: int = 2, project_angles: int = 8, swizzle: int = 0,
-                   backproject_mirror: int = 0):
+                   backproject_mirror: int = 0, project_mirror: int = 0):
         t = scg_tuning(project_groups, backproject_split, project_angles, swizzle,
-                       backproject_mirror)
+                       backproject_mirror, project_mirror)
         _check(lib.scg_plan_set_tuning(self._h, prec, C.byref(t)), "scg_plan_set_tuning")
 
     def autotune(self, prec: int = SCG_F32, stream=None) -> dict:

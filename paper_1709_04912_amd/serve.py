@@ -42,7 +42,8 @@ class Request:
 class PlanCache:
     """One plan per geometry (trig tables, projector windows). Launch shapes:
     `shape` (project_groups, backproject_split, project_angles, swizzle and
-    optionally backproject_mirror) for every plan when given - solves that share a shape run as one group, one
+    optionally backproject_mirror and project_mirror) for every plan when given - solves that
+    share a shape run as one group, one
     launch per phase in a batch - else the autotuner's pick per geometry."""
 
     def __init__(self, device: int = 0, autotune: bool = True, shape=None):

@@ -22,6 +22,8 @@ GEOMS = [
     (40, 1, 57),      # a single angle
     (100, 13, 200),   # wide detector
     (128, 180, 183),
+    (35, 2, 51),      # 0 and 90 degrees only: both their own mirrors
+    (97, 3, 140),     # odd angle count, image two bands and a ragged one
 ]
 
 
@@ -74,6 +76,11 @@ def test_project_backproject(scg, torch_mod, oracle_lib, geom, kind):
             plan.set_tuning(prec, 4, 8, 8, 0, 1)
             aty = plan.backproject(yd).cpu().numpy()
             assert _rel(aty, aty_ref) <= tol, (dt, "mirrored", _rel(aty, aty_ref))
+            # the mirrored projector: 4 and 8 angles per block, 2 and 4 groups
+            for pg, ga in ((4, 4), (2, 8)):
+                plan.set_tuning(prec, pg, 8, ga, 1, 1, 1)
+                axm = plan.project(xd).cpu().numpy()
+                assert _rel(axm, ax_ref) <= tol, (dt, "mirrored A", pg, ga, _rel(axm, ax_ref))
 
 
 @pytest.mark.parametrize("geom", [(64, 90, 95), (129, 77, 190)])
@@ -163,9 +170,9 @@ def test_filter_bin_limits(scg, torch_mod, oracle_lib):
 def test_full_size_sampled(scg, torch_mod, oracle_lib):
     """512 x 512, 720 angles, 729 bins: the operator launches at the
     benchmark's size, checked on 400 sampled rays and 400 sampled pixels
-    against the oracle: the default shapes, and the mirrored backprojector
-    with eight angle groups per tile (the autotuner's pick there) in FP32 and
-    FP64."""
+    against the oracle: the default shapes, and the mirrored operators (the
+    backprojector with eight angle groups per tile and the projector with
+    four angles per block, the autotuner's picks there) in FP32 and FP64."""
     torch = torch_mod
     n, na, nb = 512, 720, 729
     g = oracle_lib.Geometry(n, na, nb)
@@ -185,9 +192,14 @@ def test_full_size_sampled(scg, torch_mod, oracle_lib):
     with scg.Plan(n, na, nb) as plan:
         for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
                               (scg.SCG_F64, torch.float64, 1e-12)):
-            plan.set_tuning(prec, 4, 8, 4, 1, 1)
+            plan.set_tuning(prec, 4, 8, 4, 1, 1, 1)
             atm = plan.backproject(torch.tensor(y, dtype=dt, device="cuda")).cpu().numpy()
             assert _rel(atm[pix], ref_t) <= tol, (dt, _rel(atm[pix], ref_t))
+            axm = plan.project(torch.tensor(x, dtype=dt, device="cuda")).cpu().numpy()
+            assert _rel(axm[rays], ref_a) <= tol, (dt, "mirrored A", _rel(axm[rays], ref_a))
+            if prec == scg.SCG_F32:
+                # the two forms differ only in rounding order
+                assert _rel(axm, ax) <= 1e-6
     # property at any size: the axis-angle projections conserve mass
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
 
@@ -218,23 +230,25 @@ def test_errors(scg, torch_mod):
         assert e.value.status == scg.SCG_EINVAL
 
 
-ALL_SHAPES = [(pg, bs, ga, sw, mr) for mr in (0, 1) for pg in (2, 4)
-              for bs in ((1, 2, 4, 8) if mr else (1, 2, 4)) for ga in (8, 4) for sw in (0, 1)]
+ALL_SHAPES = [(pg, bs, ga, sw, mr, pm) for mr in (0, 1) for pg in (2, 4)
+              for bs in ((1, 2, 4, 8) if mr else (1, 2, 4)) for ga in (8, 4) for sw in (0, 1)
+              for pm in (0, 1)]
 SHAPE_CASES = ([((128, 180, 183), sh) for sh in ALL_SHAPES]
-               + [(g, sh) for g in ((33, 45, 49), (100, 13, 200), (50, 7, 30))
-                  for sh in ((2, 1, 8, 0, 0), (4, 4, 4, 1, 0), (2, 2, 4, 1, 0), (4, 2, 8, 1, 0),
-                             (4, 8, 8, 0, 1), (2, 1, 4, 1, 1))])
+               + [(g, sh) for g in ((33, 45, 49), (100, 13, 200), (50, 7, 30), (64, 4, 95))
+                  for sh in ((2, 1, 8, 0, 0, 0), (4, 4, 4, 1, 0, 1), (2, 2, 4, 1, 0, 0),
+                             (4, 2, 8, 1, 0, 1), (4, 8, 8, 0, 1, 0), (2, 1, 4, 1, 1, 1))])
 
 
 @pytest.mark.parametrize("geom,shape", SHAPE_CASES)
 def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
-    """Every projector group count and angle-group size, backprojector angle
-    split, mirrored or not, and block order gives the oracle's A and A^T (FP32
+    """Every projector group count and angle-group size, mirrored or not,
+    backprojector angle split, mirrored or not, and block order gives the
+    oracle's A and A^T (FP32
     1e-5, FP64 1e-12; the dual A^T of S-PCG is covered by the solver tests)
     and is bitwise repeatable."""
     torch = torch_mod
     n, na, nb = geom
-    pg, bs, ga, sw, mr = shape
+    pg, bs, ga, sw, mr, pm = shape
     print(f"[op shapes] geom={geom} shape={shape}", flush=True)
     g = oracle_lib.Geometry(n, na, nb)
     x, y = _inputs(geom, 3 * n + nb, "uniform")
@@ -243,10 +257,10 @@ def test_launch_shapes(scg, torch_mod, oracle_lib, geom, shape):
         for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
                               (scg.SCG_F64, torch.float64, 1e-12)):
             plan.set_tuning(prec, project_groups=pg, backproject_split=bs, project_angles=ga,
-                            swizzle=sw, backproject_mirror=mr)
+                            swizzle=sw, backproject_mirror=mr, project_mirror=pm)
             assert plan.tuning(prec) == {"project_groups": pg, "backproject_split": bs,
                                          "project_angles": ga, "swizzle": sw,
-                                         "backproject_mirror": mr}
+                                         "backproject_mirror": mr, "project_mirror": pm}
             xd = torch.tensor(x, dtype=dt, device="cuda")
             yd = torch.tensor(y, dtype=dt, device="cuda")
             ax, aty = plan.project(xd), plan.backproject(yd)
@@ -264,9 +278,10 @@ def test_autotune_and_bad_shapes(scg, torch_mod):
             assert t["project_angles"] in (8, 4) and t["swizzle"] in (0, 1)
             assert t["backproject_mirror"] in (0, 1)
             assert t["backproject_split"] < 8 or t["backproject_mirror"] == 1
+            assert t["project_mirror"] in (0, 1)
             assert plan.tuning(prec) == t
         for bad in ((3, 2, 8, 0), (4, 3, 8, 0), (0, 1, 8, 0), (4, 2, 6, 0), (4, 2, 8, 2),
-                    (4, 8, 8, 0, 0), (4, 2, 8, 0, 2)):
+                    (4, 8, 8, 0, 0), (4, 2, 8, 0, 2), (4, 2, 8, 0, 0, 2)):
             with pytest.raises(scg.ScgError):
                 plan.set_tuning(scg.SCG_F32, *bad)
 
@@ -290,14 +305,17 @@ def test_size_limits(scg, torch_mod, oracle_lib):
         aty = plan.backproject(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         filt = plan.filter(torch.tensor(y, dtype=torch.float32, device="cuda")).cpu().numpy()
         filt64 = plan.filter(torch.tensor(y, dtype=torch.float64, device="cuda")).cpu().numpy()
-        # the mirrored backprojector at the largest image, both precisions
-        atm = []
+        # the mirrored operators at the largest image, both precisions
+        atm, axm = [], []
         for prec, dt in ((scg.SCG_F32, torch.float32), (scg.SCG_F64, torch.float64)):
-            plan.set_tuning(prec, 4, 8, 8, 0, 1)
+            plan.set_tuning(prec, 4, 8, 8, 0, 1, 1)
             atm.append(plan.backproject(torch.tensor(y, dtype=dt, device="cuda")).cpu().numpy())
+            axm.append(plan.project(torch.tensor(x, dtype=dt, device="cuda")).cpu().numpy())
     fref = g.filter(y)
     assert _rel(filt, fref) <= 1e-5 and _rel(filt64, fref) <= 1e-12
-    assert _rel(ax[rays], g.project_rays(x, rays)) <= 1e-5
+    ref_a = g.project_rays(x, rays)
+    assert _rel(ax[rays], ref_a) <= 1e-5
+    assert _rel(axm[0][rays], ref_a) <= 1e-5 and _rel(axm[1][rays], ref_a) <= 1e-12
     ref_t = g.backproject_pixels(y, pix)
     assert _rel(aty[pix], ref_t) <= 1e-5
     assert _rel(atm[0][pix], ref_t) <= 1e-5 and _rel(atm[1][pix], ref_t) <= 1e-12

@@ -72,9 +72,10 @@ ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg, "S_CG_3O
                                                                      max_iter=max_iter)}
 
 
-# the mirrored backprojector with eight angle groups per tile (the
-# autotuner's pick at 512 x 512); S-PCG's solves keep the full tile grid
-MIRRORED = (4, 8, 8, 0, 1)
+# the mirrored operators: the backprojector with eight angle groups per tile
+# and the projector (the autotuner's picks at 512 x 512); S-PCG's solves keep
+# the backprojector's full tile grid
+MIRRORED = (4, 8, 8, 0, 1, 1)
 
 
 @pytest.mark.parametrize("variant", ["S_CG", "S_CG_CD", "S_PCG", "S_CG_K", "S_CG_3OP"])
