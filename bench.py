@@ -280,6 +280,12 @@ def mixed_runs(n_serve, n_sustained, shape):
         "k_mean": float(sum(r.k for r in p.reports.values()) / len(p.reports)),
         "roofline": batched_roofline()}
     log(f"batched: {batched}")
+    # the largest requests run on an engine of their own (below), so their
+    # plan takes the autotuner's own pick without splitting the other
+    # engine's groups; the plain loop solves them with the same plan
+    from paper_1709_04912_amd import scg
+    large_shape = cache.get(1024, 1440, 1450).autotune(scg.SCG_F32)
+    log(f"served runs: 1024x1024 launch shapes {large_shape}")
     pool = SERVE_POOL
     log(f"served runs: generating {pool} distinct requests (eps = {LS_FACTOR} x f after "
         f"{LS_STEPS} CG iterations) for streams of {n_serve} and {n_sustained}")
@@ -296,6 +302,7 @@ def mixed_runs(n_serve, n_sustained, shape):
                      f"(an upper bound of the least-squares floor); {pool} distinct requests, "
                      f"the stream takes them in turn"),
         "launch_shape": list(shape),
+        "launch_shape_1024": large_shape,
         "size_aware": "1024x1024 requests on an engine of their own (2 slots), 4 iterations of "
                       "it alternating with 4 of the other engine (64 slots); a smaller request "
                       "that finds nothing resident or waiting is solved on its own "

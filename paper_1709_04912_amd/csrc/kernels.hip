@@ -699,10 +699,17 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         }
     };
 
+    // The plain form loads the next band into registers while it works on
+    // the current one. The mirrored form issues a band's loads just before
+    // the barrier that precedes its LDS stores: holding them through the
+    // band's steps would take 16 more VGPRs than its 64 allow, and with two
+    // blocks per CU one block's steps cover the other's loads.
+    constexpr bool PRE = !MIR;
     int band = 0;
     while (band < P.n_bands && win[band] == kWinSkip) ++band;
-    if (band < P.n_bands) prefetch(band);
+    if (PRE && band < P.n_bands) prefetch(band);
     while (band < P.n_bands) {
+        if (!PRE) prefetch(band);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < RPT; ++r) lds[scol * LS + srow + r] = pre[r];
@@ -720,7 +727,7 @@ __device__ void project_body(const T *__restrict__ x, const T *__restrict__ xt, 
         const int i0 = band * kPjBand;
         int nxt = band + 1;
         while (nxt < P.n_bands && win[nxt] == kWinSkip) ++nxt;
-        if (nxt < P.n_bands) prefetch(nxt);
+        if (PRE && nxt < P.n_bands) prefetch(nxt);
 #pragma unroll
         for (int m = 0; m < SLOTS; ++m) {
             const int slot = quarter + NQ * m;
