@@ -239,7 +239,8 @@ size_t scg_static_workspace_bytes(void);
  * the image mirrored about the vertical axis). */
 typedef struct {
     int32_t project_groups;     /* 2 or 4: angle groups of 128 rays per projector block
-                                   (256 or 512 threads)                               */
+                                   (256 or 512 threads; twice that in the mirrored
+                                   form, whose two halves trace the same rays)        */
     int32_t backproject_split;  /* 1, 2 or 4 (8 with backproject_mirror): angle split
                                    inside each 16 x 16 pixel tile (128 threads each) */
     int32_t project_angles;     /* 8 or 4: angles per projector block                 */
@@ -250,7 +251,8 @@ typedef struct {
                                    footprint (half the tiles), 0: every tile      */
     int32_t project_mirror;     /* 1: each projector thread also forms the ray of the
                                    mirror angle n_a - a from the same crossings and
-                                   weights (half the blocks), 0: every angle      */
+                                   weights (blocks over the angles a <= n_a / 2),
+                                   0: every angle                                  */
 } scg_tuning;
 
 /* Current shapes for precision prec. */
