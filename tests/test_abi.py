@@ -61,3 +61,35 @@ def test_host_only_entry_points(lib):
     lib.scg_solve_static.argtypes = [vp] * 7 + [C.c_int32, vp, C.c_int32, vp]
     assert lib.scg_solve_static(None, None, None, None, None, None, None, 0, None, 0,
                                 None) == -1
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the Python binding passes across the C-ABI has the size
+    and field offsets that a C compiler gives the declaration in
+    include/scg.h (the header compiled as C99 with gcc)."""
+    import shutil
+    import subprocess
+    from paper_1709_04912_amd import scg as b
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [b.scg_geom, b.scg_params, b.scg_report, b.scg_trace_entry, b.scg_kernel_time,
+               b.scg_tuning, b.scg_batch_stats]
+    lines = ['#include "scg.h"', "#include <stddef.h>", "#include <stdio.h>", "int main(void) {"]
+    for cls in structs:
+        name = cls.__name__
+        lines.append(f'    printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                    str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for cls in structs:
+        name = cls.__name__
+        assert int(got[name]) == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
