@@ -62,8 +62,8 @@ def test_tiny_problem(oracle_lib, case, variant):
     tol = max(1e-8, 10 * amp * 2.0 ** -52)
     n, na, nb = case
     with scg.Plan(n, na, nb) as plan:
-        if mirrored:
-            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
+        if mirrored:   # both mirrored operators
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1, 1)
         p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
                         max_iter=MAX_ITER)
         x, rep, trace = plan.solve(torch.tensor(y, dtype=torch.float64, device="cuda"), p)
@@ -83,7 +83,7 @@ def test_tiny_problem(oracle_lib, case, variant):
 
 @pytest.mark.parametrize("case", CASES)
 def test_tiny_operators(oracle_lib, case):
-    """A, A^T (also mirrored), the ramp filter, TV and its subgradient at the
+    """A, A^T (both also mirrored), the ramp filter, TV and its subgradient at the
     same geometries against the oracle (FP32 within 1e-5, TV's value 1e-6;
     FP64 within 1e-12), and on a flat image, whose TV and subgradient are
     exactly zero."""
@@ -105,9 +105,10 @@ def test_tiny_operators(oracle_lib, case):
             yd = torch.tensor(y, dtype=dt, device="cuda")
             tv, s = plan.tv(xd, subgrad=True)
             got = [plan.project(xd), plan.backproject(yd), plan.filter(yd), s]
-            plan.set_tuning(prec, 4, 8, 8, 0, 1)    # mirrored backprojector
+            plan.set_tuning(prec, 4, 8, 8, 0, 1, 1)    # both mirrored operators
             got.append(plan.backproject(yd))
-            for out, ref in zip(got, refs + (refs[1],)):
+            got.append(plan.project(xd))
+            for out, ref in zip(got, refs + (refs[1], refs[0])):
                 out = out.cpu().numpy()
                 assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(ref), dt
             assert abs(tv - tv_ref) <= tol_tv * tv_ref, dt

@@ -204,6 +204,40 @@ def test_full_size_sampled(scg, torch_mod, oracle_lib):
     assert abs(ax[:nb].sum() - x.sum()) <= 1e-5 * x.sum()
 
 
+def test_large_served_sampled(scg, torch_mod, oracle_lib):
+    """1024 x 1024, 1440 angles, 1450 bins (the served stream's largest
+    requests): the launch shapes the autotuner picks there (the mirrored
+    projector with 8 angles per block, the mirrored backprojector with 4
+    groups per tile) and the default ones, on 300 sampled rays and 300
+    sampled pixels against the oracle in FP32 and FP64, plus the axis
+    angle's mass conservation."""
+    torch = torch_mod
+    n, na, nb = 1024, 1440, 1450
+    print(f"[op parity] served large {n}x{na}x{nb}", flush=True)
+    g = oracle_lib.Geometry(n, na, nb)
+    rng = np.random.default_rng(1024)
+    x = rng.uniform(0, 1, n * n)
+    y = rng.uniform(-1, 1, na * nb)
+    rays = np.concatenate([rng.choice(na * nb, 300, replace=False),
+                           np.arange(0, nb, 53), (na // 2) * nb + np.arange(0, nb, 59),
+                           (na // 4) * nb + np.arange(0, nb, 61)])
+    pix = rng.choice(n * n, 300, replace=False)
+    ref_a = g.project_rays(x, rays)
+    ref_t = g.backproject_pixels(y, pix)
+    with scg.Plan(n, na, nb) as plan:
+        for prec, dt, tol in ((scg.SCG_F32, torch.float32, 1e-5),
+                              (scg.SCG_F64, torch.float64, 1e-12)):
+            xd = torch.tensor(x, dtype=dt, device="cuda")
+            yd = torch.tensor(y, dtype=dt, device="cuda")
+            for shape in ((4, 2, 8, 0, 0, 0), (4, 4, 8, 0, 1, 1)):
+                plan.set_tuning(prec, *shape)
+                ax = plan.project(xd).cpu().numpy()
+                aty = plan.backproject(yd).cpu().numpy()
+                assert _rel(ax[rays], ref_a) <= tol, (dt, shape, _rel(ax[rays], ref_a))
+                assert _rel(aty[pix], ref_t) <= tol, (dt, shape, _rel(aty[pix], ref_t))
+                assert abs(ax[:nb].sum() - x.sum()) <= 10 * tol * x.sum(), (dt, shape)
+
+
 def test_deterministic(scg, torch_mod):
     torch = torch_mod
     n, na, nb = 96, 120, 139

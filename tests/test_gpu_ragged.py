@@ -85,8 +85,8 @@ def test_ragged_fp64(oracle_lib, key, variant):
         tol = max(tol, 10 * ref.steps * amp * 2.0 ** -52)
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        if mirrored:   # the mirrored backprojector, odd N: a centre column
-            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
+        if mirrored:   # the mirrored operators, odd N: a centre column
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1, 1)
         p = plan.params(eps=eps, gamma0=gamma0, variant=variant, prec=scg.SCG_F64,
                         max_iter=MAX_ITER)
         x, rep, trace = plan.solve(y, p)

@@ -87,8 +87,8 @@ def test_resumed_searches_match_oracle(oracle_lib, variant, kappa, max_iter):
     assert sus, "the case must suspend at least once"
     y = torch.tensor(w.y.reshape(-1), dtype=torch.float64, device="cuda")
     with scg.Plan(w.n, w.n_angles, w.n_bins) as plan:
-        if mirrored:   # the mirrored backprojector (its solves resume the same way)
-            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1)
+        if mirrored:   # the mirrored operators (their solves resume the same way)
+            plan.set_tuning(scg.SCG_F64, 4, 8, 8, 0, 1, 1)
         p = plan.params(eps=eps, gamma0=pp.gamma0, variant=variant, prec=scg.SCG_F64,
                         a=0.999, max_trials=40, max_iter=max_iter, kappa=kappa)
         x, rep, trace = plan.solve(y, p)
