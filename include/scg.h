@@ -327,7 +327,8 @@ int scg_profile_read(scg_plan *plan, scg_kernel_time *out);
  * Buffers passed to scg_batch_submit (y, x0, x_out) and the plan must stay
  * valid until the ticket has been retired (scg_batch_poll no longer returns
  * SCG_EINPROGRESS). Work runs on the batch's own stream (scg_batch_stream);
- * callers that produce y on another stream must order it before submitting.
+ * callers that produce y on another stream order it before submitting with
+ * scg_batch_wait_stream.
  * A batch is not thread-safe. */
 typedef struct scg_batch scg_batch;
 
@@ -387,6 +388,16 @@ int scg_batch_get_stats(const scg_batch *batch, scg_batch_stats *out);
 
 /* The hipStream_t the batch runs on. */
 void *scg_batch_stream(const scg_batch *batch);
+
+/* Orders the batch's later work (the staging of the next submissions, the
+ * steps) after the work already enqueued on `stream`, a hipStream_t of the
+ * batch's device (NULL: the null stream), without blocking the host: an
+ * event recorded on `stream` that the batch's stream waits for. For callers
+ * that produce y or x0 on a stream of their own; call it before
+ * scg_batch_submit. A solve's output is complete once the scg_batch_step
+ * that retires it has returned (the step synchronises the batch's stream).
+ * SCG_EDEVICE if the event cannot be recorded or waited for. */
+int scg_batch_wait_stream(scg_batch *batch, void *stream);
 
 /* Fills *params with the library's defaults: S-CG, FP32, a = 0.975,
  * max_iter = 1000, max_trials = 100, kappa = 0, mu = 2 pi / P; eps and

@@ -785,6 +785,7 @@ struct scg_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipEvent_t order_ev = nullptr;   // a caller stream's point the batch waits for
     uint32_t flags = 0;
     int max_slots = 0;
     char *arena_mem = nullptr;
@@ -1286,6 +1287,7 @@ int scg_batch_create(int device, size_t arena_bytes, int max_slots, uint32_t fla
     arena_bytes = scg::align256(arena_bytes);
     bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
     b->own_stream = ok;
+    ok = ok && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipMalloc(&b->arena_mem, arena_bytes) == hipSuccess &&
          hipMalloc(&b->dstates, (size_t)max_slots * sizeof(DevState)) == hipSuccess &&
          hipMalloc(&b->dtv, (size_t)max_slots * sizeof(double)) == hipSuccess &&
@@ -1321,6 +1323,7 @@ void scg_batch_destroy(scg_batch *b)
     if (b->hstates) (void)hipHostFree(b->hstates);
     if (b->htv) (void)hipHostFree(b->htv);
     if (b->staging) (void)hipHostFree(b->staging);
+    if (b->order_ev) (void)hipEventDestroy(b->order_ev);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -1452,5 +1455,14 @@ int scg_batch_get_stats(const scg_batch *b, scg_batch_stats *out)
 }
 
 void *scg_batch_stream(const scg_batch *b) { return b ? static_cast<void *>(b->stream) : nullptr; }
+
+int scg_batch_wait_stream(scg_batch *b, void *stream)
+{
+    if (b == nullptr) return SCG_EINVAL;
+    scg::Device dg(b->device);
+    HIP_TRY(hipEventRecord(b->order_ev, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->order_ev, 0));
+    return SCG_OK;
+}
 
 }  // extern "C"

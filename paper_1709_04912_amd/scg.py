@@ -383,8 +383,9 @@ def _bind_batch(L):
     L.scg_batch_get_stats.argtypes = [vp, C.POINTER(scg_batch_stats)]
     L.scg_batch_stream.argtypes = [vp]
     L.scg_batch_stream.restype = vp
+    L.scg_batch_wait_stream.argtypes = [vp, vp]
     for name in ("scg_batch_create", "scg_batch_submit", "scg_batch_step", "scg_batch_poll",
-                 "scg_batch_cancel", "scg_batch_get_stats"):
+                 "scg_batch_cancel", "scg_batch_get_stats", "scg_batch_wait_stream"):
         getattr(L, name).restype = C.c_int
 
 
@@ -436,8 +437,11 @@ class Batch:
             raise ValueError("params.prec does not match the tensor dtype")
         if out is None:
             out = torch.empty(plan.J, dtype=y.dtype, device=y.device)
-        # y (and x0) come from torch's stream: order them before the batch's
-        self._stream.wait_stream(torch.cuda.current_stream(y.device))
+        # y (and x0) come from torch's current stream: the batch's work waits
+        # for what is enqueued there
+        _check(lib.scg_batch_wait_stream(
+            self._h, C.c_void_p(_stream_handle(torch.cuda.current_stream(y.device)))),
+            "scg_batch_wait_stream")
         t = C.c_uint64()
         rc = lib.scg_batch_submit(self._h, plan._h, C.byref(params), _dev(y, plan.L, "y"),
                                   _dev(x0, plan.J, "x0") if x0 is not None else None,

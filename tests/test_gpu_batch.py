@@ -141,6 +141,42 @@ def test_batch_equals_alone(scg, torch_mod, oracle_lib, graph):
         plan.close()
 
 
+def test_submit_waits_for_the_callers_stream(scg, torch_mod, oracle_lib):
+    """y written on a stream of the caller's, behind a long run of matrix
+    products there: the batch's work waits for that stream
+    (scg_batch_wait_stream, called by submit), so the solve reads the
+    finished y and equals the one run alone, bitwise."""
+    torch = torch_mod
+    print("[batch] submit from a side stream", flush=True)
+    items = _prepared(scg, torch, oracle_lib, CASES[:2])
+    alone = _alone(items)
+    side = torch.cuda.Stream()
+    m = torch.rand(2048, 2048, device="cuda")
+    torch.cuda.synchronize()
+    with scg.Batch(1 << 30, max_slots=8, graph=False) as b, torch.cuda.stream(side):
+        tickets = []
+        for _, plan, y, p in items:
+            yb = torch.zeros_like(y)
+            for _ in range(16):
+                m = m @ m
+                m = m / m.abs().max()
+            yb.copy_(y)
+            r = b.submit(plan, yb, p)
+            assert r is not None
+            tickets.append((r[0], r[1], yb))
+        reps = [None] * len(items)
+        for _ in range(1000):
+            if b.step(3) == 0:
+                break
+        for i, (t, out, _) in enumerate(tickets):
+            reps[i] = (out.clone(), b.poll(t))
+    for (x, rep), (xb, rb) in zip(alone, reps):
+        assert rb is not None and _same(rep, rb), (rep, rb)
+        assert torch.equal(x, xb)
+    for _, plan, _, _ in items:
+        plan.close()
+
+
 def test_continuous_admission(scg, torch_mod, oracle_lib):
     """Three slots for seven solves: solves are admitted while others are on
     the device and retire at different iterations; every result is the one
