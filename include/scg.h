@@ -233,8 +233,9 @@ size_t scg_static_workspace_bytes(void);
  * sums in a fixed order, so each choice is itself deterministic). The
  * mirrored backprojector takes angle theta's parameters for pi - theta (a
  * trig table made exactly symmetric about the vertical axis), which moves
- * A^T by about 1e-13 relative in FP64; the filtered variants' two-sinogram
- * backprojection never runs mirrored. The mirrored projector does the same
+ * A^T by about 1e-13 relative in FP64; in the filtered variants' solves only
+ * h = A^T q runs mirrored (their two-sinogram backprojection and z' = A^T r~
+ * with its dot run on every tile). The mirrored projector does the same
  * for A (each ray (a, b) with a <= n_a / 2 also forms ray (n_a - a, b) from
  * the image mirrored about the vertical axis). */
 typedef struct {

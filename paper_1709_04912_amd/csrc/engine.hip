@@ -83,7 +83,7 @@ Layout layout(const Geo &G, size_t esz, int max_iter)
 }
 
 // Block kinds of the phase launches.
-enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKVec, kKFilt, kKPQ, kKXR, kKinds };
+enum Kind { kKT32 = 0, kKXtv, kKTrA, kKTrB, kKPj, kKBp, kKBpH, kKVec, kKFilt, kKPQ, kKXR, kKinds };
 
 template <typename T> int count_of(const Solve<T> &d, int kind)
 {
@@ -94,12 +94,20 @@ template <typename T> int count_of(const Solve<T> &d, int kind)
     case kKTrB: return d.nb_trB;
     case kKPj: return d.nb_pj;
     case kKBp: return d.nb_bp;
+    case kKBpH: return d.nb_bph;
     case kKVec: return d.nb_vec;
     case kKFilt: return (d.G.na + 1) / 2;
     case kKPQ: return d.nb_t32 + d.nb_sv;
     case kKXR: return d.nb_vec + d.nb_sv;
     default: return 0;
     }
+}
+
+inline bool restarted(int variant) { return variant == SCG_S_CG_K || variant == SCG_S_PCG_K; }
+inline bool unsuperiorized(int variant) { return variant == SCG_CG || variant == SCG_PCG; }
+inline bool filtered(int variant)
+{
+    return variant == SCG_S_PCG || variant == SCG_PCG || variant == SCG_S_PCG_K;
 }
 
 // A set of solves advanced together: same precision, variant and launch shapes.
@@ -146,11 +154,18 @@ template <typename T> struct Enq {
         launch_b_project<T>(g.S, m(kKPj), n(kKPj), phase, g.tune.project_groups,
                             g.tune.project_angles, g.tune.project_mirror, g.tune.swizzle, s);
     }
+    // The filtered variants' two-sinogram phase and their z' = A^T r~ with
+    // its dot run on every tile (no mirrored form; their partials are laid
+    // out by tile); their h = A^T q, which stores no partials, and every
+    // phase of the other variants follow the shape.
     void backproject(int phase, int dot) const
     {
         Prof t(g.prof, SCG_KC_BACKPROJECT, s);
-        launch_b_backproject<T>(g.S, m(kKBp), n(kKBp), phase, dot, g.tune.backproject_split,
-                                g.tune.backproject_mirror, g.tune.swizzle, s);
+        const bool fil = filtered(g.variant);
+        const int kind = fil && phase == kBpH ? kKBpH : kKBp;
+        const int mir = (!fil || phase == kBpH) ? g.tune.backproject_mirror : 0;
+        launch_b_backproject<T>(g.S, m(kind), n(kind), phase, dot, g.tune.backproject_split, mir,
+                                g.tune.swizzle, s);
     }
     void finish(int fin, int a0 = 0, int a1 = 0) const
     {
@@ -225,20 +240,11 @@ template <typename T> struct Enq {
     }
 };
 
-inline bool restarted(int variant) { return variant == SCG_S_CG_K || variant == SCG_S_PCG_K; }
-inline bool unsuperiorized(int variant) { return variant == SCG_CG || variant == SCG_PCG; }
-inline bool filtered(int variant)
-{
-    return variant == SCG_S_PCG || variant == SCG_PCG || variant == SCG_S_PCG_K;
-}
-// The launch shapes a solve runs with: the filtered variants backproject two
-// sinograms at once in one phase, which has no mirrored form, so their
-// solves keep the full tile grid throughout.
-inline scg_tuning solve_tuning(scg_tuning t, int variant)
-{
-    if (filtered(variant)) t.backproject_mirror = 0;
-    return t;
-}
+// The launch shapes a solve runs with: the plan's. (The filtered variants'
+// two-sinogram phase and their single-sinogram phase with a dot have no
+// mirrored form and keep every tile; their h = A^T q phase follows the
+// shape; see Enq::backproject.)
+inline scg_tuning solve_tuning(scg_tuning t, int /*variant*/) { return t; }
 
 // Initial step. S- variants (steps 1-6 of the algorithms): x_{1/2} = x0, g0
 // (and z0), p0, h0 and alpha; x1 = x0 + alpha p0 and k = 1 are formed by the
@@ -506,7 +512,8 @@ int prepare_solve(scg_plan *plan, const scg_params *pr, const scg_tuning &tune, 
     h.nb_t32 = blocks_t32(G);
     h.nb_vec = blocks_vec(J);
     h.nb_pj = h.P.n_chunks * h.P.n_groups;
-    h.nb_bp = blocks_bp(G, tune.backproject_mirror != 0);
+    h.nb_bp = blocks_bp(G, tune.backproject_mirror != 0 && !filtered(pr->variant));
+    h.nb_bph = blocks_bp(G, tune.backproject_mirror != 0);
     h.nb_sv = blocks_sv(G);
     h.trB_chunks = (std::max(pr->max_trials - kTrialsPerPass, 0) + kTrialsPerPass - 1) /
                    kTrialsPerPass;

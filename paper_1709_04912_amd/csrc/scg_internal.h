@@ -158,6 +158,8 @@ template <typename T> struct Solve {
     scg_trace_entry *trace;
     const int32_t *forced;      // replayed decisions or null
     int nb_xtv, nb_trA, nb_trB, nb_t32, nb_pj, nb_bp, nb_vec, nb_sv;
+    int nb_bph;   // blocks of the h = A^T q phase (mirrored where the shape is, also in the
+                  // filtered variants, whose other backprojections keep every tile)
     int trB_chunks;             // trial chunks of the second trial launch
 };
 

@@ -33,8 +33,8 @@ def torch_mod():
 # launch shapes per case (project_groups, backproject_split, project_angles,
 # swizzle, backproject_mirror, project_mirror): solves with different shapes
 # run in different groups of a batch; the filtered variants' solves (S-PCG,
-# PCG, S-PCG-K) drop the mirrored backprojector (their two-sinogram phase has
-# none) and run every tile
+# PCG, S-PCG-K) mirror only their h = A^T q (their two-sinogram phase has no
+# mirrored form and runs on every tile)
 SHAPES = [(4, 4, 8, 0, 0, 1), (4, 8, 8, 0, 1, 0), (2, 1, 4, 1, 0, 1), (4, 4, 8, 0, 1, 1),
           (4, 4, 4, 1, 0, 0), (4, 8, 4, 1, 1, 1), (2, 2, 8, 0, 0, 0), (2, 2, 4, 0, 1, 1),
           (4, 4, 8, 1, 1, 0), (2, 4, 4, 0, 0, 1), (4, 1, 8, 1, 0, 0)]

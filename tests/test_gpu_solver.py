@@ -73,8 +73,8 @@ ORACLE_FN = {"S_CG": alg.scg, "S_CG_CD": alg.scg_cd, "S_PCG": alg.spcg, "S_CG_3O
 
 
 # the mirrored operators: the backprojector with eight angle groups per tile
-# and the projector (the autotuner's picks at 512 x 512); S-PCG's solves keep
-# the backprojector's full tile grid
+# and the projector (the autotuner's picks at 512 x 512); S-PCG's solves
+# mirror only their h = A^T q
 MIRRORED = (4, 8, 8, 0, 1, 1)
 
 
